@@ -1,0 +1,221 @@
+/*
+ * rkkt -- reduced-KKT (Schur complement) hot path of a block-structured
+ * interior-point method, for AMD MI355X (gfx950), FP64.
+ *
+ * Method: Pacaud, Schanen, Shin, Maldonado, Anitescu, "Parallel interior-point
+ * solver for block-structured nonlinear programs on SIMD/GPU architectures"
+ * (arXiv 2301.04869).  The problem is the two-stage program of its problem
+ * statement (eq. "originalproblem", slack form "slackedproblem"): N scenario
+ * blocks with states x_i, one shared control u, state equations
+ * g_i(x_i, u) = 0 and operational constraints h_i(x_i, u) + s_i = 0.  The
+ * instance is the block (stochastic) AC optimal power flow of its case study.
+ *
+ * Variable split (the paper's Table 1 dimensions follow from it):
+ *   x_i = [voltage angle of every non-reference bus (bus order);
+ *          voltage magnitude of every bus without a generator (bus order)]
+ *         n_x = 2 n_bus - n_gen - 1
+ *   u   = [voltage magnitude of every generator bus (generator order);
+ *          active output of every non-reference generator (generator order)]
+ *         n_u = 2 n_gen - 1
+ *   g_i = [P balance of every non-reference bus; Q balance of every bus
+ *          without a generator]  (row r pairs with x entry r)
+ *   h_i = [reference active output; reactive output of every generator;
+ *          |S_from|^2 of every line; |S_to|^2 of every line]
+ *         m = 2 n_line + n_gen + 1
+ *   f_i = obj_weight * sum_k (c2_k (100 Pg_k)^2 + c1_k (100 Pg_k) + c0_k)
+ * The reference bus is the bus of the reference generator (ref_bus); its
+ * generator's output is per scenario (it balances each scenario).
+ *
+ * Layout.  All arrays are FP64 unless stated.  Per-scenario arrays are
+ * scenario-major: a [N][n] array holds scenario i's n-vector contiguously at
+ * offset i*n (the paper stacks one column per scenario, X_M = (x_1 .. x_M)).
+ * Dense n_u x n_u matrices are row-major.  Pointers named *_dev or passed to
+ * evaluate/condense/factor/step are device pointers; rkkt_network arrays and
+ * the loads given to rkkt_create are host pointers.
+ *
+ * Ownership.  The caller owns every buffer it passes and keeps it alive until
+ * the stream has finished the call.  The handle owns its sparsity patterns,
+ * level schedules, cached Jacobian/Hessian/condensed/LU values and workspace,
+ * all allocated by rkkt_create and freed by rkkt_destroy.  evaluate, condense,
+ * factor and step allocate nothing and never synchronise the host with the
+ * device; they enqueue work on the given stream and return.
+ *
+ * Errors.  Every call returns RKKT_OK (0) or a negative RKKT_ERR_* code and
+ * then rkkt_last_error() describes it.  Argument errors are detected on the
+ * host before anything is enqueued.  Numerical conditions found on the device
+ * (a G_x pivot failing the health test, a non-finite value) are recorded in a
+ * device status word that rkkt_status() reads (it synchronises the stream).
+ * The library never aborts or exits.  A handle is not thread-safe; calls that
+ * share a handle must be ordered on one stream.
+ */
+#ifndef RKKT_H
+#define RKKT_H
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  RKKT_OK = 0,
+  RKKT_ERR_ARG = -1,          /* bad argument (null pointer, size, index)       */
+  RKKT_ERR_HIP = -2,          /* a HIP runtime call failed                      */
+  RKKT_ERR_SINGULAR_GX = -3,  /* a G_x pivot failed |u_ii| >= 1e-10 max|row i| */
+  RKKT_ERR_NOT_PD = -4,       /* reduced matrix not positive definite           */
+  RKKT_ERR_NONFINITE = -5,    /* non-finite value found on the device           */
+  RKKT_ERR_NOMEM = -6         /* device allocation failed                       */
+};
+
+typedef struct rkkt_problem rkkt_problem;
+
+/* Host-side description of one grid (per unit on 100 MVA). */
+typedef struct {
+  int n_bus, n_line, n_gen, n_load;
+  int ref_bus;                       /* bus of the reference generator          */
+  const int *line_from, *line_to;    /* [n_line] bus indices, pi-model lines    */
+  const double *r, *x, *b;           /* [n_line] series r, x; total charging b  */
+  const double *rate;                /* [n_line] apparent-power limit           */
+  const int *gen_bus;                /* [n_gen] distinct buses                  */
+  const double *pmin, *pmax, *qmin, *qmax;   /* [n_gen]                         */
+  const double *c2, *c1, *c0;        /* [n_gen] $/MW^2h, $/MWh, $/h             */
+  const double *vmin, *vmax;         /* [n_bus]                                 */
+  const int *load_bus;               /* [n_load] distinct buses                 */
+} rkkt_network;
+
+typedef struct {
+  int col_tile;   /* right-hand-side columns per workgroup in the reduction;
+                     0 picks one from the sizes                               */
+  int device;     /* HIP device ordinal                                        */
+} rkkt_options;
+
+typedef struct {
+  int n_x, n_u, m, n_scen, n_bus, n_line, n_gen;
+  long long nnz_gx, nnz_gu, nnz_h, nnz_k, nnz_lu;   /* per scenario            */
+  long long lu_update_flops;        /* multiply-adds of one G_x refactorisation */
+  int levels_up, levels_down;       /* level-schedule depths of the LU solves   */
+  int col_tile;                     /* chosen column tile                       */
+  long long workspace_bytes;        /* device bytes owned by the handle         */
+} rkkt_dims;
+
+/*
+ * Symbolic analysis and allocation (problem statement; condensation and
+ * reduction propositions fix which matrices exist).  Builds the fixed
+ * sparsity patterns of G_x, G_u, H, W and K = W + H^T Sigma_s H, a
+ * fill-reducing symmetric ordering of G_x (minimum degree), its filled LU
+ * pattern with static diagonal pivots, level schedules and gather maps, and
+ * copies them and the network to device `opt->device`.
+ *   pd, qd : host [N][n_load] active / reactive load of every scenario.
+ * Returns RKKT_ERR_ARG for inconsistent networks (bad bus index, duplicate
+ * generator bus, ref_bus without generator, disconnected G_x).
+ */
+int rkkt_create(const rkkt_network* net, int n_scen, const double* pd, const double* qd,
+                const rkkt_options* opt, rkkt_problem** out);
+
+/* Host-only analysis: the sizes rkkt_create would produce, no device use. */
+int rkkt_analyze(const rkkt_network* net, int n_scen, const rkkt_options* opt, rkkt_dims* out);
+
+/* Replace the scenario loads with device arrays [N][n_load]. */
+int rkkt_set_loads(rkkt_problem* p, const double* pd_dev, const double* qd_dev, hipStream_t stream);
+
+int rkkt_dims_get(const rkkt_problem* p, rkkt_dims* out);
+
+/*
+ * Batched evaluation of every scenario block (paper: block evaluation through
+ * a nonlinear basis, eq. "eval:block"; first- and second-order derivatives).
+ *   x [N][n_x], u [n_u], y [N][n_x] (multipliers of g), z [N][m] (of h + s)
+ * Outputs (device, caller-owned):
+ *   f [N], grad_x [N][n_x], grad_u [N][n_u] (gradient of f_i w.r.t. u),
+ *   g [N][n_x], h [N][m].
+ * Also computes and caches on the handle the values of G_x, G_u, H and of the
+ * Hessian of the Lagrangian W_i = Hess(f_i + y_i^T g_i + z_i^T h_i), used by
+ * the next condense and step calls.
+ */
+int rkkt_evaluate(rkkt_problem* p, const double* x, const double* u, const double* y,
+                  const double* z, double obj_weight, double* f, double* grad_x,
+                  double* grad_u, double* g, double* h, hipStream_t stream);
+
+/*
+ * Condensation and reduction (propositions "Condensed KKT system" and
+ * "Reduction"; the local reduction and global sum of the parallel KKT solver):
+ *   K_i    = W_i + H_i^T Sigma_s,i H_i, with diag(sigma_x,i) + delta_w on K_xixi
+ *   G_x,i  = L_i U_i (refactorised on the fixed pattern, every scenario)
+ *   khat   = sum_i Z_i^T K_i Z_i + diag(sigma_u) + delta_w I,
+ *            Z_i = [-(G_x,i)^-1 G_u,i ; I]
+ * using the Jacobians and Hessian of the last rkkt_evaluate.
+ *   sigma_x [N][n_x], sigma_u [n_u], sigma_s [N][m] : IPM diagonals (>= 0)
+ *   khat    [n_u][n_u] row-major output
+ * The K and LU values are kept on the handle for rkkt_step.  A pivot that
+ * fails the health test sets RKKT_ERR_SINGULAR_GX in the device status word.
+ */
+int rkkt_condense(rkkt_problem* p, const double* sigma_x, const double* sigma_u,
+                  const double* sigma_s, double delta_w, double* khat, hipStream_t stream);
+
+/*
+ * Dense Cholesky khat = L L^T in place (lower triangle, row-major; the strict
+ * upper triangle is not referenced).  The reduced matrix is factorised
+ * densely in the paper ("Lapack on the GPU").  info_dev (device int) gets 0
+ * on success or the 1-based column of the first non-positive pivot, which
+ * signals wrong inertia of the condensed KKT system.
+ */
+int rkkt_factor(rkkt_problem* p, double* khat, int* info_dev, hipStream_t stream);
+
+/*
+ * Newton step from the factorised reduced matrix: reduced right-hand side
+ * (eq. "kkt:reduced"), p_u, then per-scenario recovery of p_x, p_y
+ * (proposition "Reduction") and p_s, p_z (proposition "Condensed KKT system";
+ * p_s is taken from the fourth block row of the augmented system,
+ * p_s = -(r4 + H p_d)).  The step solves the augmented system of the paper
+ * (eq. "kkt:augmented") with right-hand side -r:
+ *   r1x [N][n_x], r1u [n_u], r2 [N][m], r3 [N][n_x], r4 [N][m]   (inputs)
+ *   sigma_s [N][m]   the diagonal given to the last rkkt_condense
+ *   chol [n_u][n_u]  the factor written by rkkt_factor
+ *   px [N][n_x], pu [n_u], ps [N][m], py [N][n_x], pz [N][m]     (outputs)
+ * Uses the K and LU values of the last rkkt_condense.
+ */
+int rkkt_step(rkkt_problem* p, const double* r1x, const double* r1u, const double* r2,
+              const double* r3, const double* r4, const double* sigma_s, const double* chol,
+              double* px, double* pu, double* ps, double* py, double* pz, hipStream_t stream);
+
+/*
+ * Stage timing with HIP events recorded on the caller's stream around every
+ * internal launch group (for benchmarks).  rkkt_profile_begin creates up to
+ * max_records event pairs (this call allocates) and starts recording;
+ * rkkt_profile_end synchronises `stream`, writes the summed milliseconds and
+ * the number of records of every stage into ms[RKKT_NSTAGES] and
+ * count[RKKT_NSTAGES], stops recording and releases the events.  Records past
+ * max_records are dropped (count stops growing).
+ */
+enum {
+  RKKT_STAGE_EVALUATE = 0,        /* line kernel, gathers, line Hessians, W     */
+  RKKT_STAGE_CONDENSE_VALUES,     /* K = W + H^T Sigma_s H + diagonals          */
+  RKKT_STAGE_REFACTOR,            /* batched LU of G_x                          */
+  RKKT_STAGE_REDUCE,              /* local reduction, all scenarios and tiles   */
+  RKKT_STAGE_SCENARIO_SUM,        /* sum over scenarios + Sigma_u + delta_w     */
+  RKKT_STAGE_FACTOR,              /* dense Cholesky                             */
+  RKKT_STAGE_STEP_RHS,            /* reduced right-hand side contributions      */
+  RKKT_STAGE_REDUCED_SOLVE,       /* p_u                                        */
+  RKKT_STAGE_STEP_RECOVER,        /* p_x, p_y, p_s, p_z                         */
+  RKKT_NSTAGES
+};
+int rkkt_profile_begin(rkkt_problem* p, int max_records);
+int rkkt_profile_end(rkkt_problem* p, hipStream_t stream, double* ms, int* count);
+
+/*
+ * Synchronise `stream`, read and clear the device status word:
+ * *code = RKKT_OK, RKKT_ERR_SINGULAR_GX or RKKT_ERR_NONFINITE;
+ * *scenario = first scenario that raised it (or -1).
+ */
+int rkkt_status(rkkt_problem* p, hipStream_t stream, int* code, int* scenario);
+
+int rkkt_destroy(rkkt_problem* p);
+
+/* Message of the last error on this handle (or of the last failed
+ * rkkt_create / rkkt_analyze when p is NULL).  Never NULL. */
+const char* rkkt_last_error(const rkkt_problem* p);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RKKT_H */

@@ -363,3 +363,24 @@ def bound_dual_steps(prob: Problem, it: Iterate, step: dict, mu: float):
         out["zl" + name] = np.where(hl, mu / dl - zl - zl / dl * p, 0.0)
         out["zu" + name] = np.where(hu, mu / du - zu + zu / du * p, 0.0)
     return out
+
+
+def reduced_hessian_columns(prob: Problem, ev: Eval, dg: Diag, delta_w: float, cols):
+    """Selected columns K_hat V of the reduced matrix, V = unit vectors e_j,
+    by the paper's three-step product (parallel KKT solver section):
+    T_x = -G_x^-1 (G_u V);  [L_x; L_u] = [K_xx K_xu; K_ux K_uu] [T_x; V];
+    K_hat V = L_u - G_u^T G_x^-T L_x; summed over scenarios, plus
+    (Sigma_u + delta_w) on the selected diagonal entries."""
+    cols = np.asarray(cols, dtype=np.int64)
+    nu = prob.n_u
+    V = np.zeros((nu, len(cols)))
+    V[cols, np.arange(len(cols))] = 1.0
+    out = V * (dg.su + delta_w)[:, None]
+    for k in range(prob.N):
+        Kxx, Kxu, Kuu = condensed_blocks(ev, dg, k, delta_w)
+        fac = _GxFactor(ev.Gx[k])
+        Tx = -fac.solve(ev.Gu[k] @ V)
+        Lx = Kxx @ Tx + Kxu @ V
+        Lu = Kxu.T @ Tx + Kuu @ V
+        out += Lu - ev.Gu[k].T @ fac.solve(Lx, trans=True)
+    return out

@@ -1,0 +1,258 @@
+"""ctypes binding of librkkt.so (include/rkkt.h).  Argument marshalling only:
+every computation runs in the library's HIP kernels.
+
+Device arrays are torch tensors (float64, contiguous, on the GPU); their
+``data_ptr()`` is passed.  Host arrays (the network, the initial loads) are
+numpy arrays.  Functions keep the C names; errors raise ``RkktError``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librkkt.so")
+
+c_int_p = ctypes.POINTER(ctypes.c_int)
+c_dbl_p = ctypes.POINTER(ctypes.c_double)
+
+RKKT_OK = 0
+ERRORS = {-1: "RKKT_ERR_ARG", -2: "RKKT_ERR_HIP", -3: "RKKT_ERR_SINGULAR_GX",
+          -4: "RKKT_ERR_NOT_PD", -5: "RKKT_ERR_NONFINITE", -6: "RKKT_ERR_NOMEM"}
+EXPORTS = ("rkkt_create", "rkkt_analyze", "rkkt_set_loads", "rkkt_dims_get", "rkkt_evaluate",
+           "rkkt_condense", "rkkt_factor", "rkkt_step", "rkkt_status", "rkkt_destroy",
+           "rkkt_last_error", "rkkt_profile_begin", "rkkt_profile_end")
+STAGES = ("evaluate", "condense_values", "refactor", "reduce", "scenario_sum", "factor",
+          "step_rhs", "reduced_solve", "step_recover")
+
+
+class RkktError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Network(ctypes.Structure):
+    _fields_ = [("n_bus", ctypes.c_int), ("n_line", ctypes.c_int), ("n_gen", ctypes.c_int),
+                ("n_load", ctypes.c_int), ("ref_bus", ctypes.c_int),
+                ("line_from", c_int_p), ("line_to", c_int_p),
+                ("r", c_dbl_p), ("x", c_dbl_p), ("b", c_dbl_p), ("rate", c_dbl_p),
+                ("gen_bus", c_int_p),
+                ("pmin", c_dbl_p), ("pmax", c_dbl_p), ("qmin", c_dbl_p), ("qmax", c_dbl_p),
+                ("c2", c_dbl_p), ("c1", c_dbl_p), ("c0", c_dbl_p),
+                ("vmin", c_dbl_p), ("vmax", c_dbl_p), ("load_bus", c_int_p)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("col_tile", ctypes.c_int), ("device", ctypes.c_int)]
+
+
+class Dims(ctypes.Structure):
+    _fields_ = [("n_x", ctypes.c_int), ("n_u", ctypes.c_int), ("m", ctypes.c_int),
+                ("n_scen", ctypes.c_int), ("n_bus", ctypes.c_int), ("n_line", ctypes.c_int),
+                ("n_gen", ctypes.c_int),
+                ("nnz_gx", ctypes.c_longlong), ("nnz_gu", ctypes.c_longlong),
+                ("nnz_h", ctypes.c_longlong), ("nnz_k", ctypes.c_longlong),
+                ("nnz_lu", ctypes.c_longlong), ("lu_update_flops", ctypes.c_longlong),
+                ("levels_up", ctypes.c_int), ("levels_down", ctypes.c_int),
+                ("col_tile", ctypes.c_int), ("workspace_bytes", ctypes.c_longlong)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load librkkt.so (built in place by paper_2301_04869_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2301_04869_amd.build` (hipcc, gfx950)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    L.rkkt_create.argtypes = [ctypes.POINTER(Network), ctypes.c_int, c_dbl_p, c_dbl_p,
+                              ctypes.POINTER(Options), ctypes.POINTER(vp)]
+    L.rkkt_analyze.argtypes = [ctypes.POINTER(Network), ctypes.c_int, ctypes.POINTER(Options),
+                               ctypes.POINTER(Dims)]
+    L.rkkt_set_loads.argtypes = [vp, vp, vp, vp]
+    L.rkkt_dims_get.argtypes = [vp, ctypes.POINTER(Dims)]
+    L.rkkt_evaluate.argtypes = [vp, vp, vp, vp, vp, ctypes.c_double, vp, vp, vp, vp, vp, vp]
+    L.rkkt_condense.argtypes = [vp, vp, vp, vp, ctypes.c_double, vp, vp]
+    L.rkkt_factor.argtypes = [vp, vp, vp, vp]
+    L.rkkt_step.argtypes = [vp] + [vp] * 12 + [vp]
+    L.rkkt_status.argtypes = [vp, vp, c_int_p, c_int_p]
+    L.rkkt_destroy.argtypes = [vp]
+    L.rkkt_profile_begin.argtypes = [vp, ctypes.c_int]
+    L.rkkt_profile_end.argtypes = [vp, vp, c_dbl_p, c_int_p]
+    L.rkkt_last_error.argtypes = [vp]
+    L.rkkt_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name != "rkkt_last_error":
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc, handle=None):
+    if rc != RKKT_OK:
+        msg = lib().rkkt_last_error(handle).decode()
+        raise RkktError(rc, msg)
+
+
+def _host_network(net):
+    """Build the C struct from an object with the synthgrid.Network fields.
+    Returns (struct, keepalive list)."""
+    keep = []
+
+    def ia(a):
+        a = np.ascontiguousarray(a, dtype=np.int32)
+        keep.append(a)
+        return a.ctypes.data_as(c_int_p)
+
+    def da(a):
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        keep.append(a)
+        return a.ctypes.data_as(c_dbl_p)
+    s = Network(int(net.n_bus), int(net.n_line), int(net.n_gen), int(len(net.load_bus)),
+                int(net.ref_bus), ia(net.line_from), ia(net.line_to), da(net.r), da(net.x),
+                da(net.b), da(net.rate), ia(net.gen_bus), da(net.pmin), da(net.pmax),
+                da(net.qmin), da(net.qmax), da(net.c2), da(net.c1), da(net.c0),
+                da(net.vmin), da(net.vmax), ia(net.load_bus))
+    return s, keep
+
+
+def _ptr(t, name, numel=None):
+    if t is None:
+        raise ValueError(f"{name} is None")
+    if not (t.is_cuda and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous device tensor")
+    if str(t.dtype) != "torch.float64":
+        raise ValueError(f"{name} must be float64")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(getattr(stream, "cuda_stream", stream))
+
+
+class Handle:
+    """An rkkt_problem* with its dimensions; destroyed with the object."""
+
+    def __init__(self, ptr, dims):
+        self.ptr = ptr
+        self.dims = dims
+
+    def __del__(self):
+        if getattr(self, "ptr", None) and _lib is not None:
+            _lib.rkkt_destroy(self.ptr)
+            self.ptr = None
+
+
+def rkkt_analyze(net, n_scen, col_tile=0):
+    s, keep = _host_network(net)
+    d = Dims()
+    _check(lib().rkkt_analyze(ctypes.byref(s), int(n_scen), ctypes.byref(Options(col_tile, 0)),
+                              ctypes.byref(d)))
+    return d.as_dict()
+
+
+def rkkt_create(net, pd, qd, col_tile=0, device=0):
+    """pd, qd: host [N][n_load] arrays (scenario-major)."""
+    s, keep = _host_network(net)
+    pd = np.ascontiguousarray(pd, dtype=np.float64)
+    qd = np.ascontiguousarray(qd, dtype=np.float64)
+    if pd.ndim != 2 or pd.shape != qd.shape or pd.shape[1] != len(net.load_bus):
+        raise ValueError("pd, qd must be [N][n_load]")
+    h = ctypes.c_void_p()
+    _check(lib().rkkt_create(ctypes.byref(s), pd.shape[0], pd.ctypes.data_as(c_dbl_p),
+                             qd.ctypes.data_as(c_dbl_p), ctypes.byref(Options(col_tile, device)),
+                             ctypes.byref(h)))
+    d = Dims()
+    _check(lib().rkkt_dims_get(h, ctypes.byref(d)), h)
+    return Handle(h, d.as_dict())
+
+
+def rkkt_dims_get(p):
+    d = Dims()
+    _check(lib().rkkt_dims_get(p.ptr, ctypes.byref(d)), p.ptr)
+    return d.as_dict()
+
+
+def rkkt_set_loads(p, pd, qd, stream=None):
+    """pd, qd: device [N][n_load] tensors."""
+    _check(lib().rkkt_set_loads(p.ptr, _ptr(pd, "pd"), _ptr(qd, "qd"), _stream(stream)), p.ptr)
+
+
+def rkkt_evaluate(p, x, u, y, z, obj_weight, f, grad_x, grad_u, g, h, stream=None):
+    d = p.dims
+    N, nx, nu, m = d["n_scen"], d["n_x"], d["n_u"], d["m"]
+    _check(lib().rkkt_evaluate(p.ptr, _ptr(x, "x", N * nx), _ptr(u, "u", nu), _ptr(y, "y", N * nx),
+                               _ptr(z, "z", N * m), float(obj_weight), _ptr(f, "f", N),
+                               _ptr(grad_x, "grad_x", N * nx), _ptr(grad_u, "grad_u", N * nu),
+                               _ptr(g, "g", N * nx), _ptr(h, "h", N * m), _stream(stream)), p.ptr)
+
+
+def rkkt_condense(p, sigma_x, sigma_u, sigma_s, delta_w, khat, stream=None):
+    d = p.dims
+    N, nx, nu, m = d["n_scen"], d["n_x"], d["n_u"], d["m"]
+    _check(lib().rkkt_condense(p.ptr, _ptr(sigma_x, "sigma_x", N * nx), _ptr(sigma_u, "sigma_u", nu),
+                               _ptr(sigma_s, "sigma_s", N * m), float(delta_w),
+                               _ptr(khat, "khat", nu * nu), _stream(stream)), p.ptr)
+
+
+def rkkt_factor(p, khat, info, stream=None):
+    nu = p.dims["n_u"]
+    if not (info.is_cuda and str(info.dtype) == "torch.int32" and info.numel() >= 1):
+        raise ValueError("info must be a device int32 tensor")
+    _check(lib().rkkt_factor(p.ptr, _ptr(khat, "khat", nu * nu), ctypes.c_void_p(info.data_ptr()),
+                             _stream(stream)), p.ptr)
+
+
+def rkkt_step(p, r1x, r1u, r2, r3, r4, sigma_s, chol, px, pu, ps, py, pz, stream=None):
+    d = p.dims
+    N, nx, nu, m = d["n_scen"], d["n_x"], d["n_u"], d["m"]
+    _check(lib().rkkt_step(p.ptr, _ptr(r1x, "r1x", N * nx), _ptr(r1u, "r1u", nu),
+                           _ptr(r2, "r2", N * m), _ptr(r3, "r3", N * nx), _ptr(r4, "r4", N * m),
+                           _ptr(sigma_s, "sigma_s", N * m), _ptr(chol, "chol", nu * nu),
+                           _ptr(px, "px", N * nx), _ptr(pu, "pu", nu), _ptr(ps, "ps", N * m),
+                           _ptr(py, "py", N * nx), _ptr(pz, "pz", N * m), _stream(stream)), p.ptr)
+
+
+def rkkt_status(p, stream=None):
+    code = ctypes.c_int()
+    scen = ctypes.c_int()
+    _check(lib().rkkt_status(p.ptr, _stream(stream), ctypes.byref(code), ctypes.byref(scen)), p.ptr)
+    return code.value, scen.value
+
+
+def rkkt_profile_begin(p, max_records):
+    _check(lib().rkkt_profile_begin(p.ptr, int(max_records)), p.ptr)
+
+
+def rkkt_profile_end(p, stream=None):
+    """Returns {stage: (total ms, records)}."""
+    ms = (ctypes.c_double * len(STAGES))()
+    cnt = (ctypes.c_int * len(STAGES))()
+    _check(lib().rkkt_profile_end(p.ptr, _stream(stream), ms, cnt), p.ptr)
+    return {s: (ms[i], cnt[i]) for i, s in enumerate(STAGES)}
+
+
+def rkkt_destroy(p):
+    if p.ptr:
+        lib().rkkt_destroy(p.ptr)
+        p.ptr = None
+
+
+def rkkt_last_error(p=None):
+    return lib().rkkt_last_error(p.ptr if p is not None else None).decode()

@@ -1,0 +1,374 @@
+// C ABI of the reduced-KKT hot path (declared in include/rkkt.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "device.h"
+#include "rkkt.h"
+#include "symbolic.h"
+
+struct rkkt_problem {
+  rkkt::Sym sym;
+  rkkt::DP d{};
+  int device = 0;
+  std::vector<void*> allocs;
+  long long bytes = 0;
+  std::string err;
+  // stage timing (rkkt_profile_begin / rkkt_profile_end)
+  bool prof = false;
+  std::vector<hipEvent_t> events;          // 2 per record
+  std::vector<int> rec_stage;
+  size_t rec_used = 0;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(rkkt_problem* p, int code, const std::string& msg) {
+  if (p) p->err = msg;
+  else g_err = msg;
+  return code;
+}
+
+int hip_fail(rkkt_problem* p, hipError_t e, const char* where) {
+  return fail(p, RKKT_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+template <typename T>
+hipError_t dalloc(rkkt_problem* p, T** out, size_t n) {
+  void* ptr = nullptr;
+  size_t bytes = (n ? n : 1) * sizeof(T);
+  hipError_t e = hipMalloc(&ptr, bytes);
+  if (e != hipSuccess) return e;
+  p->allocs.push_back(ptr);
+  p->bytes += (long long)bytes;
+  *out = static_cast<T*>(ptr);
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t upload(rkkt_problem* p, const T** out, const std::vector<T>& v) {
+  T* ptr = nullptr;
+  hipError_t e = dalloc(p, &ptr, v.size());
+  if (e != hipSuccess) return e;
+  if (!v.empty()) e = hipMemcpy(ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+  *out = ptr;
+  return e;
+}
+
+void fill_dims(const rkkt::Sym& s, rkkt_dims* o, long long bytes) {
+  std::memset(o, 0, sizeof(*o));
+  o->n_x = s.nx; o->n_u = s.nu; o->m = s.m; o->n_scen = s.N;
+  o->n_bus = s.nb; o->n_line = s.nl; o->n_gen = s.ng;
+  o->nnz_gx = (long long)s.gx_col.size();
+  o->nnz_gu = (long long)s.gu_col.size();
+  o->nnz_h = (long long)s.h_col.size();
+  o->nnz_k = (long long)s.k_col.size();
+  o->nnz_lu = (long long)s.f_col.size();
+  o->lu_update_flops = s.lu_flops;
+  o->levels_up = (int)s.lvu_ptr.size() - 1;
+  o->levels_down = (int)s.lvd_ptr.size() - 1;
+  o->col_tile = s.col_tile;
+  o->workspace_bytes = bytes;
+}
+
+// Runs `launch` between two events on `stream` when profiling is on.
+template <typename F>
+void stage(rkkt_problem* p, int id, hipStream_t stream, F&& launch) {
+  if (!p->prof || 2 * (p->rec_used + 1) > p->events.size()) {
+    launch();
+    return;
+  }
+  size_t r = p->rec_used++;
+  (void)hipEventRecord(p->events[2 * r], stream);
+  launch();
+  (void)hipEventRecord(p->events[2 * r + 1], stream);
+  p->rec_stage[r] = id;
+}
+
+int check_launch(rkkt_problem* p, const char* where) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(p, e, where);
+  return RKKT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rkkt_analyze(const rkkt_network* net, int n_scen, const rkkt_options* opt, rkkt_dims* out) {
+  if (!net || !out) return fail(nullptr, RKKT_ERR_ARG, "rkkt_analyze: null argument");
+  rkkt::Sym s;
+  std::string m = rkkt::build_symbolic(*net, n_scen, opt ? opt->col_tile : 0, s);
+  if (!m.empty()) return fail(nullptr, RKKT_ERR_ARG, "rkkt_analyze: " + m);
+  fill_dims(s, out, 0);
+  return RKKT_OK;
+}
+
+int rkkt_create(const rkkt_network* net, int n_scen, const double* pd, const double* qd,
+                const rkkt_options* opt, rkkt_problem** out) {
+  if (!net || !out) return fail(nullptr, RKKT_ERR_ARG, "rkkt_create: null argument");
+  *out = nullptr;
+  if (net->n_load > 0 && (!pd || !qd)) return fail(nullptr, RKKT_ERR_ARG, "rkkt_create: null loads");
+  rkkt_problem* p = new rkkt_problem();
+  p->device = opt ? opt->device : 0;
+  std::string m = rkkt::build_symbolic(*net, n_scen, opt ? opt->col_tile : 0, p->sym);
+  if (!m.empty()) {
+    delete p;
+    return fail(nullptr, RKKT_ERR_ARG, "rkkt_create: " + m);
+  }
+  hipError_t e = hipSetDevice(p->device);
+  if (e != hipSuccess) {
+    int rc = hip_fail(nullptr, e, "rkkt_create: hipSetDevice");
+    delete p;
+    return rc;
+  }
+  const rkkt::Sym& s = p->sym;
+  rkkt::DP& d = p->d;
+  d.nb = s.nb; d.nl = s.nl; d.ng = s.ng; d.nload = s.nload; d.ref = s.ref; d.gref = s.gref;
+  d.nx = s.nx; d.nu = s.nu; d.m = s.m; d.nz = s.nz; d.N = s.N;
+  d.n_ev = s.n_ev; d.off_P = s.off_P; d.off_Q = s.off_Q; d.off_gx = s.off_gx;
+  d.off_gu = s.off_gu; d.off_h = s.off_h;
+  d.nnz_gx = (int)s.gx_col.size(); d.nnz_gu = (int)s.gu_col.size();
+  d.nnz_h = (int)s.h_col.size(); d.nnz_k = (int)s.k_col.size(); d.nnz_f = (int)s.f_col.size();
+  d.nlev_up = (int)s.lvu_ptr.size() - 1;
+  d.nlev_dn = (int)s.lvd_ptr.size() - 1;
+  d.col_tile = s.col_tile;
+  d.lds = s.lds_resident ? 1 : 0;
+  // per-unit line and cost data
+  std::vector<double> gs(s.nl), bs(s.nl), bc(s.nl), ca(s.ng), cb(s.ng), cc(s.ng);
+  for (int l = 0; l < s.nl; ++l) {
+    double den = net->r[l] * net->r[l] + net->x[l] * net->x[l];
+    gs[l] = net->r[l] / den;
+    bs[l] = -net->x[l] / den;
+    bc[l] = 0.5 * net->b[l];
+  }
+  for (int g = 0; g < s.ng; ++g) {
+    ca[g] = 1e4 * net->c2[g];
+    cb[g] = 1e2 * net->c1[g];
+    cc[g] = net->c0[g];
+  }
+  d.aref = ca[s.gref];
+  d.bref = cb[s.gref];
+  std::vector<int> load_of_bus(s.nb, -1), grow_bus(s.nx), gen_u(s.ng, -1), k_row(s.k_col.size());
+  for (int j = 0; j < s.nload; ++j) load_of_bus[net->load_bus[j]] = j;
+  for (int b = 0; b < s.nb; ++b) {
+    if (s.prow[b] >= 0) grow_bus[s.prow[b]] = b;
+    if (s.qrow[b] >= 0) grow_bus[s.qrow[b]] = b;
+  }
+  for (size_t j = 0; j < s.gnr.size(); ++j) gen_u[s.gnr[j]] = s.ng + (int)j;
+  for (int r = 0; r < s.nz; ++r)
+    for (int q = s.k_ptr[r]; q < s.k_ptr[r + 1]; ++q) k_row[q] = r;
+
+#define UP(field, vec) \
+  if ((e = upload(p, &d.field, vec)) != hipSuccess) goto hip_error;
+  UP(line_f, s.line_f) UP(line_t, s.line_t) UP(line_loc, s.line_loc)
+  UP(gs, gs) UP(bs, bs) UP(bc, bc)
+  UP(th_src, s.th_src) UP(v_src, s.v_src) UP(prow, s.prow) UP(qrow, s.qrow) UP(pg_u, s.pg_u)
+  UP(gnr, s.gnr) UP(gen_bus, s.gen_bus) UP(ca, ca) UP(cb, cb) UP(cc, cc)
+  UP(load_of_bus, load_of_bus) UP(grow_bus, grow_bus) UP(gen_u, gen_u)
+  UP(perm, s.perm) UP(pinv, s.pinv)
+  UP(ev_ptr, s.ev_ptr) UP(ev_src, s.ev_src) UP(ev_const, s.ev_const)
+  UP(gx_ptr, s.gx_ptr) UP(gx_col, s.gx_col) UP(gu_ptr, s.gu_ptr) UP(gu_col, s.gu_col)
+  UP(guc_ptr, s.guc_ptr) UP(guc_row, s.guc_row) UP(guc_pos, s.guc_pos)
+  UP(h_ptr, s.h_ptr) UP(h_col, s.h_col) UP(ht_ptr, s.ht_ptr) UP(ht_row, s.ht_row)
+  UP(ht_pos, s.ht_pos) UP(h0pos, s.h0pos)
+  UP(k_ptr, s.k_ptr) UP(k_col, s.k_col) UP(k_diag, s.k_diag) UP(k_usplit, s.k_usplit)
+  UP(k_row, k_row)
+  UP(w_ptr, s.w_ptr) UP(w_src, s.w_src) UP(wp_ptr, s.wp_ptr) UP(wp_a, s.wp_a) UP(wp_b, s.wp_b)
+  UP(wp_coef, s.wp_coef) UP(w_const, s.w_const)
+  UP(t_ptr, s.t_ptr) UP(t_row, s.t_row) UP(t_a, s.t_a) UP(t_b, s.t_b)
+  UP(f_ptr, s.f_ptr) UP(f_col, s.f_col) UP(f_diag, s.f_diag) UP(f_tpos, s.f_tpos) UP(gx2f, s.gx2f)
+  UP(lvu_ptr, s.lvu_ptr) UP(lvu_rows, s.lvu_rows) UP(lvd_ptr, s.lvd_ptr) UP(lvd_rows, s.lvd_rows)
+#undef UP
+  {
+    const size_t N = s.N;
+    const int ntile = (s.nu + s.col_tile - 1) / s.col_tile;
+    size_t panel = 2 * N * (size_t)s.nx;
+    if (!d.lds) panel = std::max(panel, N * ntile * 2 * (size_t)s.nx * s.col_tile);
+    if ((e = dalloc(p, &d.pdb, N * s.nb)) != hipSuccess) goto hip_error;
+    if ((e = dalloc(p, &d.qdb, N * s.nb)) != hipSuccess) goto hip_error;
+    if ((e = dalloc(p, &d.LV, N * s.nl * rkkt::kLVsize)) != hipSuccess) goto hip_error;
+    if ((e = dalloc(p, &d.LH, N * s.nl * rkkt::kLHsize)) != hipSuccess) goto hip_error;
+    if ((e = dalloc(p, &d.EV, N * s.n_ev)) != hipSuccess) goto hip_error;
+    if ((e = dalloc(p, &d.W, N * s.k_col.size())) != hipSuccess) goto hip_error;
+    if ((e = dalloc(p, &d.K, N * s.k_col.size())) != hipSuccess) goto hip_error;
+    if ((e = dalloc(p, &d.LU, N * s.f_col.size())) != hipSuccess) goto hip_error;
+    if ((e = dalloc(p, &d.invd, N * s.nx)) != hipSuccess) goto hip_error;
+    if ((e = dalloc(p, &d.part, N * s.nu * (size_t)s.nu)) != hipSuccess) goto hip_error;
+    if ((e = dalloc(p, &d.panel, panel)) != hipSuccess) goto hip_error;
+    if ((e = dalloc(p, &d.imap, d.lds ? 1 : N * 4 * (size_t)s.nx)) != hipSuccess) goto hip_error;
+    if ((e = dalloc(p, &d.rhat1, N * s.nx)) != hipSuccess) goto hip_error;
+    if ((e = dalloc(p, &d.rpart, N * s.nu)) != hipSuccess) goto hip_error;
+    if ((e = dalloc(p, &d.status, 2)) != hipSuccess) goto hip_error;
+    if ((e = hipMemset(d.status, 0, 2 * sizeof(int))) != hipSuccess) goto hip_error;
+    // loads
+    if (s.nload > 0) {
+      double *tpd = nullptr, *tqd = nullptr;
+      size_t nbytes = N * s.nload * sizeof(double);
+      if ((e = hipMalloc((void**)&tpd, nbytes)) != hipSuccess) goto hip_error;
+      if ((e = hipMalloc((void**)&tqd, nbytes)) != hipSuccess) { (void)hipFree(tpd); goto hip_error; }
+      e = hipMemcpy(tpd, pd, nbytes, hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = hipMemcpy(tqd, qd, nbytes, hipMemcpyHostToDevice);
+      if (e == hipSuccess) {
+        rkkt::launch_bus_loads(d, tpd, tqd, nullptr);
+        e = hipGetLastError();
+      }
+      if (e == hipSuccess) e = hipDeviceSynchronize();
+      (void)hipFree(tpd);
+      (void)hipFree(tqd);
+      if (e != hipSuccess) goto hip_error;
+    } else {
+      if ((e = hipMemset(d.pdb, 0, N * s.nb * sizeof(double))) != hipSuccess) goto hip_error;
+      if ((e = hipMemset(d.qdb, 0, N * s.nb * sizeof(double))) != hipSuccess) goto hip_error;
+    }
+  }
+  *out = p;
+  return RKKT_OK;
+hip_error : {
+  int rc = hip_fail(nullptr, e, "rkkt_create");
+  for (void* q : p->allocs) (void)hipFree(q);
+  delete p;
+  return rc;
+}
+}
+
+int rkkt_set_loads(rkkt_problem* p, const double* pd_dev, const double* qd_dev, hipStream_t stream) {
+  if (!p) return fail(nullptr, RKKT_ERR_ARG, "rkkt_set_loads: null handle");
+  if (p->d.nload > 0 && (!pd_dev || !qd_dev)) return fail(p, RKKT_ERR_ARG, "rkkt_set_loads: null loads");
+  if (p->d.nload == 0) return RKKT_OK;
+  rkkt::launch_bus_loads(p->d, pd_dev, qd_dev, stream);
+  return check_launch(p, "rkkt_set_loads");
+}
+
+int rkkt_dims_get(const rkkt_problem* p, rkkt_dims* out) {
+  if (!p || !out) return fail(nullptr, RKKT_ERR_ARG, "rkkt_dims_get: null argument");
+  fill_dims(p->sym, out, p->bytes);
+  return RKKT_OK;
+}
+
+int rkkt_evaluate(rkkt_problem* p, const double* x, const double* u, const double* y,
+                  const double* z, double obj_weight, double* f, double* grad_x, double* grad_u,
+                  double* g, double* h, hipStream_t stream) {
+  if (!p) return fail(nullptr, RKKT_ERR_ARG, "rkkt_evaluate: null handle");
+  if (!x || !u || !y || !z || !f || !grad_x || !grad_u || !g || !h)
+    return fail(p, RKKT_ERR_ARG, "rkkt_evaluate: null array");
+  if (!std::isfinite(obj_weight)) return fail(p, RKKT_ERR_ARG, "rkkt_evaluate: non-finite obj_weight");
+  stage(p, RKKT_STAGE_EVALUATE, stream, [&] {
+    rkkt::launch_evaluate(p->d, x, u, y, z, obj_weight, f, grad_x, grad_u, g, h, stream);
+  });
+  return check_launch(p, "rkkt_evaluate");
+}
+
+int rkkt_condense(rkkt_problem* p, const double* sigma_x, const double* sigma_u,
+                  const double* sigma_s, double delta_w, double* khat, hipStream_t stream) {
+  if (!p) return fail(nullptr, RKKT_ERR_ARG, "rkkt_condense: null handle");
+  if (!sigma_x || !sigma_u || !sigma_s || !khat) return fail(p, RKKT_ERR_ARG, "rkkt_condense: null array");
+  if (!std::isfinite(delta_w)) return fail(p, RKKT_ERR_ARG, "rkkt_condense: non-finite delta_w");
+  stage(p, RKKT_STAGE_CONDENSE_VALUES, stream,
+        [&] { rkkt::launch_condense_values(p->d, sigma_x, sigma_s, delta_w, stream); });
+  stage(p, RKKT_STAGE_REFACTOR, stream, [&] { rkkt::launch_refactor(p->d, stream); });
+  stage(p, RKKT_STAGE_REDUCE, stream, [&] { rkkt::launch_reduce(p->d, stream); });
+  stage(p, RKKT_STAGE_SCENARIO_SUM, stream,
+        [&] { rkkt::launch_scenario_sum(p->d, sigma_u, delta_w, khat, stream); });
+  return check_launch(p, "rkkt_condense");
+}
+
+int rkkt_factor(rkkt_problem* p, double* khat, int* info_dev, hipStream_t stream) {
+  if (!p) return fail(nullptr, RKKT_ERR_ARG, "rkkt_factor: null handle");
+  if (!khat || !info_dev) return fail(p, RKKT_ERR_ARG, "rkkt_factor: null array");
+  stage(p, RKKT_STAGE_FACTOR, stream, [&] { rkkt::launch_cholesky(p->d, khat, info_dev, stream); });
+  return check_launch(p, "rkkt_factor");
+}
+
+int rkkt_step(rkkt_problem* p, const double* r1x, const double* r1u, const double* r2,
+              const double* r3, const double* r4, const double* sigma_s, const double* chol,
+              double* px, double* pu, double* ps, double* py, double* pz, hipStream_t stream) {
+  if (!p) return fail(nullptr, RKKT_ERR_ARG, "rkkt_step: null handle");
+  if (!r1x || !r1u || !r2 || !r3 || !r4 || !sigma_s || !chol || !px || !pu || !ps || !py || !pz)
+    return fail(p, RKKT_ERR_ARG, "rkkt_step: null array");
+  stage(p, RKKT_STAGE_STEP_RHS, stream,
+        [&] { rkkt::launch_step_rhs(p->d, r1x, r2, r3, r4, sigma_s, stream); });
+  stage(p, RKKT_STAGE_REDUCED_SOLVE, stream,
+        [&] { rkkt::launch_reduced_solve(p->d, r1u, chol, pu, stream); });
+  stage(p, RKKT_STAGE_STEP_RECOVER, stream, [&] {
+    rkkt::launch_step_recover(p->d, r2, r3, r4, sigma_s, pu, px, ps, py, pz, stream);
+  });
+  return check_launch(p, "rkkt_step");
+}
+
+int rkkt_status(rkkt_problem* p, hipStream_t stream, int* code, int* scenario) {
+  if (!p || !code) return fail(p, RKKT_ERR_ARG, "rkkt_status: null argument");
+  hipError_t e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(p, e, "rkkt_status");
+  int st[2] = {0, -1};
+  e = hipMemcpy(st, p->d.status, sizeof st, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(p, e, "rkkt_status");
+  int zero[2] = {0, 0};
+  e = hipMemcpy(p->d.status, zero, sizeof zero, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(p, e, "rkkt_status");
+  *code = st[0];
+  if (scenario) *scenario = st[0] ? st[1] : -1;
+  return RKKT_OK;
+}
+
+static void release_events(rkkt_problem* p) {
+  for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
+  p->events.clear();
+  p->rec_stage.clear();
+  p->rec_used = 0;
+  p->prof = false;
+}
+
+int rkkt_profile_begin(rkkt_problem* p, int max_records) {
+  if (!p || max_records < 1) return fail(p, RKKT_ERR_ARG, "rkkt_profile_begin: bad argument");
+  release_events(p);
+  p->events.resize(2 * (size_t)max_records);
+  for (auto& e : p->events) {
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) {
+      e = nullptr;
+      release_events(p);
+      return hip_fail(p, r, "rkkt_profile_begin");
+    }
+  }
+  p->rec_stage.assign(max_records, -1);
+  p->prof = true;
+  return RKKT_OK;
+}
+
+int rkkt_profile_end(rkkt_problem* p, hipStream_t stream, double* ms, int* count) {
+  if (!p || !ms || !count) return fail(p, RKKT_ERR_ARG, "rkkt_profile_end: null argument");
+  for (int i = 0; i < RKKT_NSTAGES; ++i) { ms[i] = 0.0; count[i] = 0; }
+  hipError_t e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) { release_events(p); return hip_fail(p, e, "rkkt_profile_end"); }
+  for (size_t r = 0; r < p->rec_used; ++r) {
+    float t = 0.0f;
+    e = hipEventElapsedTime(&t, p->events[2 * r], p->events[2 * r + 1]);
+    if (e != hipSuccess) { release_events(p); return hip_fail(p, e, "rkkt_profile_end"); }
+    ms[p->rec_stage[r]] += t;
+    count[p->rec_stage[r]] += 1;
+  }
+  release_events(p);
+  return RKKT_OK;
+}
+
+int rkkt_destroy(rkkt_problem* p) {
+  if (!p) return RKKT_OK;
+  release_events(p);
+  for (void* q : p->allocs) (void)hipFree(q);
+  delete p;
+  return RKKT_OK;
+}
+
+const char* rkkt_last_error(const rkkt_problem* p) {
+  if (p) return p->err.c_str();
+  return g_err.c_str();
+}
+
+}  // extern "C"

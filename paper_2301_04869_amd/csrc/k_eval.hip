@@ -1,0 +1,282 @@
+// Batched evaluation of the scenario blocks and condensation of the KKT matrix.
+//
+// Paper: block evaluation through a nonlinear basis (eq. "AST", "eval:block"):
+// every scenario's f, g, h are linear maps of per-line basis terms
+// (V_f^2, V_t^2, V_f V_t cos, V_f V_t sin).  Here the basis is evaluated per
+// (scenario, line) and every output -- bus injections, Jacobian values of the
+// fixed patterns, Hessian values -- is a fixed gather over per-line
+// quantities, so no value is ever accumulated with atomics.  Derivatives are
+// the analytic derivatives of the basis (the paper uses forward-mode and
+// forward-over-reverse AD on the same structure).
+#include "device.h"
+
+namespace rkkt {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+inline unsigned grid_for(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+__device__ inline double bus_theta(const DP& d, const double* xk, int b) {
+  int s = d.th_src[b];
+  return s >= 0 ? xk[s] : 0.0;
+}
+
+__device__ inline double bus_vm(const DP& d, const double* xk, const double* u, int b) {
+  int s = d.v_src[b];
+  return s >= 0 ? xk[s] : u[-s - 1];
+}
+
+// The four line-end functions F = A vf^2 + B vt^2 + vf vt (C cos + D sin)
+// of the pi-model (order: P_from, Q_from, P_to, Q_to).
+__device__ inline void line_coeffs(double gs, double bs, double bc, double A[4], double B[4],
+                                   double C[4], double D[4]) {
+  A[0] = gs;          B[0] = 0.0;          C[0] = -gs; D[0] = -bs;
+  A[1] = -(bs + bc);  B[1] = 0.0;          C[1] = bs;  D[1] = -gs;
+  A[2] = 0.0;         B[2] = gs;           C[2] = -gs; D[2] = bs;
+  A[3] = 0.0;         B[3] = -(bs + bc);   C[3] = bs;  D[3] = gs;
+}
+
+__global__ void k_bus_loads(DP d, const double* pd, const double* qd) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)d.N * d.nb) return;
+  int k = (int)(t / d.nb), b = (int)(t % d.nb);
+  int j = d.load_of_bus[b];
+  d.pdb[t] = j >= 0 ? pd[(long long)k * d.nload + j] : 0.0;
+  d.qdb[t] = j >= 0 ? qd[(long long)k * d.nload + j] : 0.0;
+}
+
+// a1: basis terms and first derivatives of the four line-end functions
+__global__ void k_line_eval(DP d, const double* x, const double* u) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)d.N * d.nl) return;
+  int k = (int)(t / d.nl), l = (int)(t % d.nl);
+  const double* xk = x + (long long)k * d.nx;
+  int bf = d.line_f[l], bt = d.line_t[l];
+  double dth = bus_theta(d, xk, bf) - bus_theta(d, xk, bt);
+  double vf = bus_vm(d, xk, u, bf), vt = bus_vm(d, xk, u, bt);
+  double sn, cs;
+  sincos(dth, &sn, &cs);
+  double A[4], B[4], C[4], D[4];
+  line_coeffs(d.gs[l], d.bs[l], d.bc[l], A, B, C, D);
+  double val[4], grad[4][4];
+  for (int q = 0; q < 4; ++q) {
+    double T = C[q] * cs + D[q] * sn;
+    double Tp = -C[q] * sn + D[q] * cs;
+    val[q] = A[q] * vf * vf + B[q] * vt * vt + vf * vt * T;
+    grad[q][0] = vf * vt * Tp;
+    grad[q][1] = -vf * vt * Tp;
+    grad[q][2] = 2.0 * A[q] * vf + vt * T;
+    grad[q][3] = 2.0 * B[q] * vt + vf * T;
+  }
+  double* o = d.LV + t * kLVsize;
+  for (int e = 0; e < 2; ++e) {
+    double P = val[2 * e], Q = val[2 * e + 1];
+    double* oe = o + 14 * e;
+    oe[0] = P;
+    oe[1] = Q;
+    for (int q = 0; q < 4; ++q) {
+      oe[2 + q] = grad[2 * e][q];
+      oe[6 + q] = grad[2 * e + 1][q];
+      oe[10 + q] = 2.0 * (P * grad[2 * e][q] + Q * grad[2 * e + 1][q]);
+    }
+  }
+}
+
+// bus injections and Jacobian values on the fixed patterns
+__global__ void k_gather_ev(DP d) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)d.N * d.n_ev) return;
+  int k = (int)(t / d.n_ev), e = (int)(t % d.n_ev);
+  const double* lv = d.LV + (long long)k * d.nl * kLVsize;
+  double acc = d.ev_const[e];
+  for (int j = d.ev_ptr[e]; j < d.ev_ptr[e + 1]; ++j) acc += lv[d.ev_src[j]];
+  d.EV[t] = acc;
+}
+
+__device__ inline double pg_ref(const DP& d, int k) {
+  return d.EV[(long long)k * d.n_ev + d.off_P + d.ref] + d.pdb[(long long)k * d.nb + d.ref];
+}
+
+// g, h, gradient of f and f itself
+__global__ void k_assemble(DP d, const double* u, double w, double* f, double* gx, double* gu,
+                           double* g, double* h) {
+  const int per = 2 * d.nx + d.m + d.nu + 1;
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)d.N * per) return;
+  int k = (int)(t / per), i = (int)(t % per);
+  const double* ev = d.EV + (long long)k * d.n_ev;
+  const double* pdb = d.pdb + (long long)k * d.nb;
+  const double* qdb = d.qdb + (long long)k * d.nb;
+  double pref = ev[d.off_P + d.ref] + pdb[d.ref];
+  double cref = w * (2.0 * d.aref * pref + d.bref);
+  if (i < d.nx) {
+    int b = d.grow_bus[i];
+    double v;
+    if (i < d.nb - 1) {
+      int pu = d.pg_u[b];
+      v = ev[d.off_P + b] - (pu >= 0 ? u[pu] : 0.0) + pdb[b];
+    } else {
+      v = ev[d.off_Q + b] + qdb[b];
+    }
+    g[(long long)k * d.nx + i] = v;
+    return;
+  }
+  i -= d.nx;
+  if (i < d.m) {
+    double v;
+    if (i == 0) {
+      v = pref;
+    } else if (i <= d.ng) {
+      int b = d.gen_bus[i - 1];
+      v = ev[d.off_Q + b] + qdb[b];
+    } else {
+      int r = i - 1 - d.ng;
+      int e = r >= d.nl ? 1 : 0;
+      int l = r - e * d.nl;
+      const double* lv = d.LV + ((long long)k * d.nl + l) * kLVsize + 14 * e;
+      v = lv[0] * lv[0] + lv[1] * lv[1];
+    }
+    h[(long long)k * d.m + i] = v;
+    return;
+  }
+  i -= d.m;
+  if (i < d.nx) {
+    int p = d.h0pos[d.pinv[i]];
+    gx[(long long)k * d.nx + i] = p >= 0 ? cref * ev[d.off_h + p] : 0.0;
+    return;
+  }
+  i -= d.nx;
+  if (i < d.nu) {
+    double v;
+    if (i < d.ng) {
+      int p = d.h0pos[d.nx + i];
+      v = p >= 0 ? cref * ev[d.off_h + p] : 0.0;
+    } else {
+      int gg = d.gnr[i - d.ng];
+      v = w * (2.0 * d.ca[gg] * u[i] + d.cb[gg]);
+    }
+    gu[(long long)k * d.nu + i] = v;
+    return;
+  }
+  double acc = 0.0;
+  for (int gg = 0; gg < d.ng; ++gg) {
+    int ui = d.gen_u[gg];
+    double pg = ui >= 0 ? u[ui] : pref;
+    acc += d.ca[gg] * pg * pg + d.cb[gg] * pg + d.cc[gg];
+  }
+  f[k] = w * acc;
+}
+
+// a3: local 4x4 Hessian of every line's share of f + y^T g + z^T h
+__global__ void k_line_hess(DP d, const double* x, const double* u, const double* y,
+                            const double* z, double w) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)d.N * d.nl) return;
+  int k = (int)(t / d.nl), l = (int)(t % d.nl);
+  const double* xk = x + (long long)k * d.nx;
+  const double* yk = y + (long long)k * d.nx;
+  const double* zk = z + (long long)k * d.m;
+  int bus[2] = {d.line_f[l], d.line_t[l]};
+  double dth = bus_theta(d, xk, bus[0]) - bus_theta(d, xk, bus[1]);
+  double vf = bus_vm(d, xk, u, bus[0]), vt = bus_vm(d, xk, u, bus[1]);
+  double sn, cs;
+  sincos(dth, &sn, &cs);
+  double A[4], B[4], C[4], D[4];
+  line_coeffs(d.gs[l], d.bs[l], d.bc[l], A, B, C, D);
+  const double* lv = d.LV + t * kLVsize;
+  double H[kLHsize];
+  for (int q = 0; q < kLHsize; ++q) H[q] = 0.0;
+  for (int e = 0; e < 2; ++e) {
+    int b = bus[e];
+    double wP, wQ;
+    if (d.prow[b] >= 0) wP = yk[d.prow[b]];
+    else wP = zk[0] + w * (2.0 * d.aref * pg_ref(d, k) + d.bref);
+    wQ = d.qrow[b] >= 0 ? yk[d.qrow[b]] : zk[1 + (-d.qrow[b] - 1)];
+    double zs = zk[1 + d.ng + e * d.nl + l];
+    const double* le = lv + 14 * e;
+    double mu[2] = {wP + 2.0 * zs * le[0], wQ + 2.0 * zs * le[1]};
+    for (int f2 = 0; f2 < 2; ++f2) {
+      int q = 2 * e + f2;
+      double T = C[q] * cs + D[q] * sn;
+      double Tp = -C[q] * sn + D[q] * cs;
+      double m = mu[f2];
+      double vv = vf * vt * T;
+      H[0] += m * (-vv);
+      H[1] += m * vv;
+      H[2] += m * vt * Tp;
+      H[3] += m * vf * Tp;
+      H[4] += m * (-vv);
+      H[5] += m * (-vt * Tp);
+      H[6] += m * (-vf * Tp);
+      H[7] += m * 2.0 * A[q];
+      H[8] += m * T;
+      H[9] += m * 2.0 * B[q];
+      const double* gr = le + (f2 == 0 ? 2 : 6);
+      double c2 = 2.0 * zs;
+      for (int a = 0; a < 4; ++a)
+        for (int bq = a; bq < 4; ++bq) H[lh_index(a, bq)] += c2 * gr[a] * gr[bq];
+    }
+  }
+  double* o = d.LH + t * kLHsize;
+  for (int q = 0; q < kLHsize; ++q) o[q] = H[q];
+}
+
+// Hessian of the Lagrangian on the pattern of K
+__global__ void k_w_gather(DP d, double w) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)d.N * d.nnz_k) return;
+  int k = (int)(t / d.nnz_k), e = (int)(t % d.nnz_k);
+  const double* lh = d.LH + (long long)k * d.nl * kLHsize;
+  const double* hv = d.EV + (long long)k * d.n_ev + d.off_h;
+  double acc = 0.0;
+  for (int j = d.w_ptr[e]; j < d.w_ptr[e + 1]; ++j) acc += lh[d.w_src[j]];
+  double prod = d.w_const[e];
+  for (int j = d.wp_ptr[e]; j < d.wp_ptr[e + 1]; ++j) prod += d.wp_coef[j] * hv[d.wp_a[j]] * hv[d.wp_b[j]];
+  d.W[t] = acc + w * prod;
+}
+
+// a4: K = W + H^T Sigma_s H + diag(Sigma_x) + delta_w on the x block
+__global__ void k_condense_values(DP d, const double* sx, const double* ss, double dw) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)d.N * d.nnz_k) return;
+  int k = (int)(t / d.nnz_k), e = (int)(t % d.nnz_k);
+  const double* hv = d.EV + (long long)k * d.n_ev + d.off_h;
+  const double* sk = ss + (long long)k * d.m;
+  double acc = d.W[t];
+  for (int j = d.t_ptr[e]; j < d.t_ptr[e + 1]; ++j) acc += sk[d.t_row[j]] * hv[d.t_a[j]] * hv[d.t_b[j]];
+  int r = d.k_row[e];
+  if (r < d.nx && d.k_col[e] == r) acc += sx[(long long)k * d.nx + d.perm[r]] + dw;
+  if (!isfinite(acc)) atomicCAS(d.status, 0, RKKT_ERR_NONFINITE);
+  d.K[t] = acc;
+}
+
+}  // namespace
+
+void launch_bus_loads(const DP& d, const double* pd, const double* qd, hipStream_t s) {
+  long long n = (long long)d.N * d.nb;
+  k_bus_loads<<<grid_for(n), kBlock, 0, s>>>(d, pd, qd);
+}
+
+void launch_evaluate(const DP& d, const double* x, const double* u, const double* y,
+                     const double* z, double w, double* f, double* gx, double* gu, double* g,
+                     double* h, hipStream_t s) {
+  long long nl = (long long)d.N * d.nl;
+  k_line_eval<<<grid_for(nl), kBlock, 0, s>>>(d, x, u);
+  long long ne = (long long)d.N * d.n_ev;
+  k_gather_ev<<<grid_for(ne), kBlock, 0, s>>>(d);
+  long long na = (long long)d.N * (2 * d.nx + d.m + d.nu + 1);
+  k_assemble<<<grid_for(na), kBlock, 0, s>>>(d, u, w, f, gx, gu, g, h);
+  k_line_hess<<<grid_for(nl), kBlock, 0, s>>>(d, x, u, y, z, w);
+  long long nk = (long long)d.N * d.nnz_k;
+  k_w_gather<<<grid_for(nk), kBlock, 0, s>>>(d, w);
+}
+
+void launch_condense_values(const DP& d, const double* sx, const double* ss, double dw,
+                            hipStream_t s) {
+  long long nk = (long long)d.N * d.nnz_k;
+  k_condense_values<<<grid_for(nk), kBlock, 0, s>>>(d, sx, ss, dw);
+}
+
+}  // namespace rkkt

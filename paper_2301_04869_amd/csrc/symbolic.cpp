@@ -1,0 +1,456 @@
+// Host-side symbolic analysis: variable maps, fixed sparsity patterns, gather
+// lists, fill-reducing ordering and the filled LU pattern of G_x.
+#include "symbolic.h"
+
+#include <algorithm>
+#include <array>
+#include <cstdio>
+#include <map>
+#include <numeric>
+#include <set>
+#include <utility>
+
+namespace rkkt {
+namespace {
+
+struct Contrib {
+  std::vector<int> src;
+  double c = 0.0;
+};
+using SparseRow = std::map<int, Contrib>;  // internal z var -> contributions
+
+struct KEntry {
+  std::vector<int> wsrc;                          // LH sources
+  std::vector<std::array<int, 2>> wprod;          // product of two H values
+  std::vector<double> wcoef;
+  double wconst = 0.0;
+  std::vector<std::array<int, 3>> trip;           // (h row, H value a, H value b)
+};
+
+// Minimum-degree elimination on an undirected graph.  Returns the elimination
+// order; fill[v] receives the neighbours of v that are still uneliminated when v
+// is eliminated (the off-diagonal pattern of column v of the Cholesky-like
+// factor of the symmetrised matrix).  Ties go to the smaller index.
+std::vector<int> minimum_degree(int n, std::vector<std::vector<int>> adj,
+                                std::vector<std::vector<int>>& fill) {
+  std::set<std::pair<int, int>> pq;
+  for (int v = 0; v < n; ++v) pq.insert({(int)adj[v].size(), v});
+  std::vector<int> order;
+  order.reserve(n);
+  fill.assign(n, {});
+  std::vector<int> merged;
+  while (!pq.empty()) {
+    int v = pq.begin()->second;
+    pq.erase(pq.begin());
+    order.push_back(v);
+    const std::vector<int>& nv = adj[v];
+    fill[v] = nv;
+    for (int w : nv) {
+      pq.erase({(int)adj[w].size(), w});
+      merged.clear();
+      std::set_union(adj[w].begin(), adj[w].end(), nv.begin(), nv.end(),
+                     std::back_inserter(merged));
+      std::vector<int> out;
+      out.reserve(merged.size());
+      for (int q : merged)
+        if (q != v && q != w) out.push_back(q);
+      adj[w].swap(out);
+      pq.insert({(int)adj[w].size(), w});
+    }
+    adj[v].clear();
+    adj[v].shrink_to_fit();
+  }
+  return order;
+}
+
+int find_pos(const std::vector<int>& ptr, const std::vector<int>& col, int row, int c) {
+  auto b = col.begin() + ptr[row], e = col.begin() + ptr[row + 1];
+  auto it = std::lower_bound(b, e, c);
+  if (it == e || *it != c) return -1;
+  return (int)(it - col.begin());
+}
+
+}  // namespace
+
+long long reduce_lds_bytes(const Sym& s, int w) {
+  return 8LL * ((long long)s.f_col.size() + 2LL * s.nx * w + s.nx);
+}
+
+long long refactor_lds_bytes(const Sym& s) {
+  return 8LL * ((long long)s.f_col.size() + 2LL * s.nx) + 4LL * 4 * s.nx;
+}
+
+std::string build_symbolic(const rkkt_network& net, int N, int col_tile_req, Sym& s) {
+  char msg[256];
+  const int nb = net.n_bus, nl = net.n_line, ng = net.n_gen, nload = net.n_load;
+  if (nb < 2 || nl < 1 || ng < 1 || nload < 0 || N < 1) return "bad sizes";
+  if (!net.line_from || !net.line_to || !net.r || !net.x || !net.b || !net.rate ||
+      !net.gen_bus || !net.pmin || !net.pmax || !net.qmin || !net.qmax || !net.c2 ||
+      !net.c1 || !net.c0 || !net.vmin || !net.vmax || (nload > 0 && !net.load_bus))
+    return "null network array";
+  for (int l = 0; l < nl; ++l) {
+    int f = net.line_from[l], t = net.line_to[l];
+    if (f < 0 || f >= nb || t < 0 || t >= nb || f == t) {
+      snprintf(msg, sizeof msg, "line %d has bad end buses (%d, %d)", l, f, t);
+      return msg;
+    }
+  }
+  std::vector<int> gen_of_bus(nb, -1);
+  for (int g = 0; g < ng; ++g) {
+    int b = net.gen_bus[g];
+    if (b < 0 || b >= nb) return "generator bus out of range";
+    if (gen_of_bus[b] >= 0) return "two generators on one bus";
+    gen_of_bus[b] = g;
+  }
+  if (net.ref_bus < 0 || net.ref_bus >= nb || gen_of_bus[net.ref_bus] < 0)
+    return "ref_bus must be a generator bus";
+  {
+    std::vector<char> seen(nb, 0);
+    for (int i = 0; i < nload; ++i) {
+      int b = net.load_bus[i];
+      if (b < 0 || b >= nb) return "load bus out of range";
+      if (seen[b]) return "two loads on one bus";
+      seen[b] = 1;
+    }
+  }
+  s = Sym();
+  s.nb = nb; s.nl = nl; s.ng = ng; s.nload = nload; s.N = N;
+  s.ref = net.ref_bus;
+  s.gref = gen_of_bus[s.ref];
+  s.nx = 2 * nb - ng - 1;
+  s.nu = 2 * ng - 1;
+  s.m = 2 * nl + ng + 1;
+  s.nz = s.nx + s.nu;
+  const int nx = s.nx, nu = s.nu;
+  s.gen_bus.assign(net.gen_bus, net.gen_bus + ng);
+  for (int g = 0; g < ng; ++g)
+    if (g != s.gref) s.gnr.push_back(g);
+
+  // external variable maps (the order of the public interface)
+  s.th_src.assign(nb, -1);
+  s.v_src.assign(nb, 0);
+  s.prow.assign(nb, -1);
+  s.qrow.assign(nb, 0);
+  s.pg_u.assign(nb, -1);
+  {
+    int k = 0;
+    for (int b = 0; b < nb; ++b)
+      if (b != s.ref) { s.th_src[b] = k; s.prow[b] = k; ++k; }
+    for (int b = 0; b < nb; ++b)
+      if (gen_of_bus[b] < 0) { s.v_src[b] = k; s.qrow[b] = k; ++k; }
+      else { s.v_src[b] = -(1 + gen_of_bus[b]); s.qrow[b] = -(1 + gen_of_bus[b]); }
+    if (k != nx) return "internal: x size";
+    for (size_t j = 0; j < s.gnr.size(); ++j) s.pg_u[s.gen_bus[s.gnr[j]]] = ng + (int)j;
+  }
+  s.line_f.assign(net.line_from, net.line_from + nl);
+  s.line_t.assign(net.line_to, net.line_to + nl);
+  std::vector<std::vector<std::pair<int, int>>> ends(nb);  // (line, end)
+  for (int l = 0; l < nl; ++l) {
+    ends[s.line_f[l]].push_back({l, 0});
+    ends[s.line_t[l]].push_back({l, 1});
+  }
+
+  // ---- fill-reducing ordering of G_x (pattern of G_x + G_x^T, external order)
+  auto ext_var = [&](int b, int which) -> int {  // which 0: theta, 1: v ; -1 if not an x var
+    if (which == 0) return s.th_src[b];
+    return s.v_src[b] >= 0 ? s.v_src[b] : -1;
+  };
+  {
+    std::vector<std::vector<int>> adj(nx);
+    auto add_row = [&](int r, int b) {
+      for (auto& le : ends[b]) {
+        int l = le.first;
+        int bb[2] = {s.line_f[l], s.line_t[l]};
+        for (int q = 0; q < 2; ++q)
+          for (int w = 0; w < 2; ++w) {
+            int c = ext_var(bb[q], w);
+            if (c >= 0 && c != r) { adj[r].push_back(c); adj[c].push_back(r); }
+          }
+      }
+    };
+    for (int b = 0; b < nb; ++b) {
+      if (s.prow[b] >= 0) add_row(s.prow[b], b);
+      if (s.qrow[b] >= 0) add_row(s.qrow[b], b);
+    }
+    for (auto& a : adj) {
+      std::sort(a.begin(), a.end());
+      a.erase(std::unique(a.begin(), a.end()), a.end());
+    }
+    std::vector<std::vector<int>> fill;
+    std::vector<int> order = minimum_degree(nx, adj, fill);
+    s.perm = order;
+    s.pinv.assign(nx, 0);
+    for (int i = 0; i < nx; ++i) s.pinv[order[i]] = i;
+    // filled pattern in internal order: row i has U part = pinv(fill[perm[i]])
+    std::vector<std::vector<int>> up(nx), lo(nx);
+    for (int i = 0; i < nx; ++i) {
+      for (int w : fill[order[i]]) up[i].push_back(s.pinv[w]);
+      std::sort(up[i].begin(), up[i].end());
+      for (int j : up[i]) {
+        if (j <= i) return "internal: fill order";
+        lo[j].push_back(i);
+      }
+    }
+    s.f_ptr.assign(nx + 1, 0);
+    for (int i = 0; i < nx; ++i) s.f_ptr[i + 1] = s.f_ptr[i] + (int)(lo[i].size() + 1 + up[i].size());
+    s.f_col.resize(s.f_ptr[nx]);
+    s.f_diag.resize(nx);
+    for (int i = 0; i < nx; ++i) {
+      int p = s.f_ptr[i];
+      for (int k : lo[i]) s.f_col[p++] = k;  // lo[i] is ascending by construction
+      s.f_diag[i] = p;
+      s.f_col[p++] = i;
+      for (int j : up[i]) s.f_col[p++] = j;
+    }
+    s.f_tpos.resize(s.f_col.size());
+    for (int i = 0; i < nx; ++i)
+      for (int e = s.f_ptr[i]; e < s.f_ptr[i + 1]; ++e) {
+        int t = find_pos(s.f_ptr, s.f_col, s.f_col[e], i);
+        if (t < 0) return "internal: filled pattern not symmetric";
+        s.f_tpos[e] = t;
+      }
+    s.lu_flops = 0;
+    for (int i = 0; i < nx; ++i)
+      for (int e = s.f_ptr[i]; e < s.f_diag[i]; ++e) {
+        int k = s.f_col[e];
+        s.lu_flops += 1 + (s.f_ptr[k + 1] - s.f_diag[k] - 1);
+      }
+    // level schedules
+    std::vector<int> lvl(nx, 0);
+    int nlu = 0;
+    for (int i = 0; i < nx; ++i) {
+      int L = 0;
+      for (int e = s.f_ptr[i]; e < s.f_diag[i]; ++e) L = std::max(L, lvl[s.f_col[e]] + 1);
+      lvl[i] = L;
+      nlu = std::max(nlu, L + 1);
+    }
+    s.lvu_ptr.assign(nlu + 1, 0);
+    for (int i = 0; i < nx; ++i) s.lvu_ptr[lvl[i] + 1]++;
+    for (int q = 0; q < nlu; ++q) s.lvu_ptr[q + 1] += s.lvu_ptr[q];
+    s.lvu_rows.resize(nx);
+    {
+      std::vector<int> cur(s.lvu_ptr.begin(), s.lvu_ptr.end() - 1);
+      for (int i = 0; i < nx; ++i) s.lvu_rows[cur[lvl[i]]++] = i;
+    }
+    int nld = 0;
+    for (int i = nx - 1; i >= 0; --i) {
+      int L = 0;
+      for (int e = s.f_diag[i] + 1; e < s.f_ptr[i + 1]; ++e) L = std::max(L, lvl[s.f_col[e]] + 1);
+      lvl[i] = L;
+      nld = std::max(nld, L + 1);
+    }
+    s.lvd_ptr.assign(nld + 1, 0);
+    for (int i = 0; i < nx; ++i) s.lvd_ptr[lvl[i] + 1]++;
+    for (int q = 0; q < nld; ++q) s.lvd_ptr[q + 1] += s.lvd_ptr[q];
+    s.lvd_rows.resize(nx);
+    {
+      std::vector<int> cur(s.lvd_ptr.begin(), s.lvd_ptr.end() - 1);
+      for (int i = 0; i < nx; ++i) s.lvd_rows[cur[lvl[i]]++] = i;
+    }
+  }
+
+  // ---- internal z index of the locals of every line
+  auto zvar = [&](int b, int which) -> int {
+    if (which == 0) return s.th_src[b] >= 0 ? s.pinv[s.th_src[b]] : -1;
+    return s.v_src[b] >= 0 ? s.pinv[s.v_src[b]] : nx + (-s.v_src[b] - 1);
+  };
+  s.line_loc.resize(4 * nl);
+  for (int l = 0; l < nl; ++l) {
+    s.line_loc[4 * l + 0] = zvar(s.line_f[l], 0);
+    s.line_loc[4 * l + 1] = zvar(s.line_t[l], 0);
+    s.line_loc[4 * l + 2] = zvar(s.line_f[l], 1);
+    s.line_loc[4 * l + 3] = zvar(s.line_t[l], 1);
+  }
+
+  // ---- Jacobian rows: gradient of a bus injection (P: type 0, Q: type 1)
+  auto bus_row = [&](int b, int type, SparseRow& row) {
+    for (auto& le : ends[b]) {
+      int l = le.first, e = le.second;
+      for (int q = 0; q < 4; ++q) {
+        int v = s.line_loc[4 * l + q];
+        if (v < 0) continue;
+        row[v].src.push_back(l * kLVsize + 14 * e + (type == 0 ? kLVdP : kLVdQ) + q);
+      }
+    }
+  };
+  std::vector<SparseRow> grow(nx);  // by internal row
+  for (int b = 0; b < nb; ++b) {
+    if (s.prow[b] >= 0) {
+      SparseRow& row = grow[s.pinv[s.prow[b]]];
+      bus_row(b, 0, row);
+      if (s.pg_u[b] >= 0) row[nx + s.pg_u[b]].c = -1.0;
+    }
+    if (s.qrow[b] >= 0) bus_row(b, 1, grow[s.pinv[s.qrow[b]]]);
+  }
+  std::vector<SparseRow> hrow(s.m);
+  bus_row(s.ref, 0, hrow[0]);
+  for (int g = 0; g < ng; ++g) bus_row(s.gen_bus[g], 1, hrow[1 + g]);
+  for (int l = 0; l < nl; ++l)
+    for (int e = 0; e < 2; ++e) {
+      SparseRow& row = hrow[1 + ng + e * nl + l];
+      for (int q = 0; q < 4; ++q) {
+        int v = s.line_loc[4 * l + q];
+        if (v >= 0) row[v].src.push_back(l * kLVsize + 14 * e + kLVdS + q);
+      }
+    }
+
+  // ---- EV gather lists
+  s.off_P = 0;
+  s.off_Q = nb;
+  s.ev_ptr.assign(1, 0);
+  auto push_ev = [&](const std::vector<int>& src, double c) {
+    s.ev_src.insert(s.ev_src.end(), src.begin(), src.end());
+    s.ev_ptr.push_back((int)s.ev_src.size());
+    s.ev_const.push_back(c);
+  };
+  for (int type = 0; type < 2; ++type)
+    for (int b = 0; b < nb; ++b) {
+      std::vector<int> src;
+      for (auto& le : ends[b]) src.push_back(le.first * kLVsize + 14 * le.second + (type == 0 ? kLVP : kLVQ));
+      push_ev(src, 0.0);
+    }
+  s.off_gx = (int)s.ev_const.size();
+  s.gx_ptr.assign(nx + 1, 0);
+  for (int i = 0; i < nx; ++i) {
+    for (auto& kv : grow[i])
+      if (kv.first < nx) { s.gx_col.push_back(kv.first); push_ev(kv.second.src, kv.second.c); }
+    s.gx_ptr[i + 1] = (int)s.gx_col.size();
+  }
+  s.off_gu = (int)s.ev_const.size();
+  s.gu_ptr.assign(nx + 1, 0);
+  for (int i = 0; i < nx; ++i) {
+    for (auto& kv : grow[i])
+      if (kv.first >= nx) { s.gu_col.push_back(kv.first - nx); push_ev(kv.second.src, kv.second.c); }
+    s.gu_ptr[i + 1] = (int)s.gu_col.size();
+  }
+  s.off_h = (int)s.ev_const.size();
+  s.h_ptr.assign(s.m + 1, 0);
+  for (int r = 0; r < s.m; ++r) {
+    for (auto& kv : hrow[r]) { s.h_col.push_back(kv.first); push_ev(kv.second.src, kv.second.c); }
+    s.h_ptr[r + 1] = (int)s.h_col.size();
+  }
+  s.n_ev = (int)s.ev_const.size();
+  for (int i = 0; i < nx; ++i)
+    if (s.gx_ptr[i + 1] == s.gx_ptr[i] || find_pos(s.gx_ptr, s.gx_col, i, i) < 0)
+      return "G_x has a structurally zero diagonal (isolated bus?)";
+
+  // G_u by column
+  s.guc_ptr.assign(nu + 1, 0);
+  for (int c : s.gu_col) s.guc_ptr[c + 1]++;
+  for (int c = 0; c < nu; ++c) s.guc_ptr[c + 1] += s.guc_ptr[c];
+  s.guc_row.resize(s.gu_col.size());
+  s.guc_pos.resize(s.gu_col.size());
+  {
+    std::vector<int> cur(s.guc_ptr.begin(), s.guc_ptr.end() - 1);
+    for (int i = 0; i < nx; ++i)
+      for (int e = s.gu_ptr[i]; e < s.gu_ptr[i + 1]; ++e) {
+        int c = s.gu_col[e];
+        s.guc_row[cur[c]] = i;
+        s.guc_pos[cur[c]] = e;
+        cur[c]++;
+      }
+  }
+  // H transposed
+  s.ht_ptr.assign(s.nz + 1, 0);
+  for (int v : s.h_col) s.ht_ptr[v + 1]++;
+  for (int v = 0; v < s.nz; ++v) s.ht_ptr[v + 1] += s.ht_ptr[v];
+  s.ht_row.resize(s.h_col.size());
+  s.ht_pos.resize(s.h_col.size());
+  {
+    std::vector<int> cur(s.ht_ptr.begin(), s.ht_ptr.end() - 1);
+    for (int r = 0; r < s.m; ++r)
+      for (int e = s.h_ptr[r]; e < s.h_ptr[r + 1]; ++e) {
+        int v = s.h_col[e];
+        s.ht_row[cur[v]] = r;
+        s.ht_pos[cur[v]] = e;
+        cur[v]++;
+      }
+  }
+  s.h0pos.assign(s.nz, -1);
+  for (int e = s.h_ptr[0]; e < s.h_ptr[1]; ++e) s.h0pos[s.h_col[e]] = e;
+
+  // ---- K = W + H^T Sigma_s H (+ diagonals): pattern and gather lists
+  std::map<std::pair<int, int>, KEntry> K;
+  for (int l = 0; l < nl; ++l)
+    for (int a = 0; a < 4; ++a)
+      for (int b = a; b < 4; ++b) {
+        int va = s.line_loc[4 * l + a], vb = s.line_loc[4 * l + b];
+        if (va < 0 || vb < 0) continue;
+        int src = l * kLHsize + lh_index(a, b);
+        K[{va, vb}].wsrc.push_back(src);
+        if (va != vb) K[{vb, va}].wsrc.push_back(src);
+      }
+  const double aref = 1e4 * net.c2[s.gref];
+  for (int e1 = s.h_ptr[0]; e1 < s.h_ptr[1]; ++e1)
+    for (int e2 = s.h_ptr[0]; e2 < s.h_ptr[1]; ++e2) {
+      KEntry& ke = K[{s.h_col[e1], s.h_col[e2]}];
+      ke.wprod.push_back({e1, e2});
+      ke.wcoef.push_back(2.0 * aref);
+    }
+  for (size_t j = 0; j < s.gnr.size(); ++j) {
+    int v = nx + ng + (int)j;
+    K[{v, v}].wconst += 2.0 * 1e4 * net.c2[s.gnr[j]];
+  }
+  for (int r = 0; r < s.m; ++r)
+    for (int e1 = s.h_ptr[r]; e1 < s.h_ptr[r + 1]; ++e1)
+      for (int e2 = s.h_ptr[r]; e2 < s.h_ptr[r + 1]; ++e2)
+        K[{s.h_col[e1], s.h_col[e2]}].trip.push_back({r, e1, e2});
+  for (int v = 0; v < s.nz; ++v) K[{v, v}];
+  s.k_ptr.assign(s.nz + 1, 0);
+  s.w_ptr.assign(1, 0);
+  s.wp_ptr.assign(1, 0);
+  s.t_ptr.assign(1, 0);
+  for (auto& kv : K) {
+    int r = kv.first.first, c = kv.first.second;
+    s.k_ptr[r + 1]++;
+    s.k_col.push_back(c);
+    const KEntry& ke = kv.second;
+    s.w_src.insert(s.w_src.end(), ke.wsrc.begin(), ke.wsrc.end());
+    s.w_ptr.push_back((int)s.w_src.size());
+    for (size_t q = 0; q < ke.wprod.size(); ++q) {
+      s.wp_a.push_back(ke.wprod[q][0]);
+      s.wp_b.push_back(ke.wprod[q][1]);
+      s.wp_coef.push_back(ke.wcoef[q]);
+    }
+    s.wp_ptr.push_back((int)s.wp_a.size());
+    s.w_const.push_back(ke.wconst);
+    for (auto& t : ke.trip) {
+      s.t_row.push_back(t[0]);
+      s.t_a.push_back(t[1]);
+      s.t_b.push_back(t[2]);
+    }
+    s.t_ptr.push_back((int)s.t_row.size());
+  }
+  for (int r = 0; r < s.nz; ++r) s.k_ptr[r + 1] += s.k_ptr[r];
+  s.k_diag.resize(s.nz);
+  s.k_usplit.resize(s.nz);
+  for (int r = 0; r < s.nz; ++r) {
+    s.k_diag[r] = find_pos(s.k_ptr, s.k_col, r, r);
+    auto b = s.k_col.begin() + s.k_ptr[r], e = s.k_col.begin() + s.k_ptr[r + 1];
+    s.k_usplit[r] = (int)(std::lower_bound(b, e, nx) - s.k_col.begin());
+  }
+
+  // G_x entries inside the filled pattern
+  s.gx2f.resize(s.gx_col.size());
+  for (int i = 0; i < nx; ++i)
+    for (int e = s.gx_ptr[i]; e < s.gx_ptr[i + 1]; ++e) {
+      int p = find_pos(s.f_ptr, s.f_col, i, s.gx_col[e]);
+      if (p < 0) return "internal: G_x entry outside the filled pattern";
+      s.gx2f[e] = p;
+    }
+
+  // column tile of the reduction
+  const long long lds_max = 160 * 1024;
+  if (col_tile_req > 0) {
+    s.col_tile = col_tile_req;
+  } else {
+    s.col_tile = 0;
+    for (int w : {32, 16, 8, 4})
+      if (reduce_lds_bytes(s, w) <= 80 * 1024) { s.col_tile = w; break; }
+    if (s.col_tile == 0) s.col_tile = 64;
+  }
+  s.lds_resident = reduce_lds_bytes(s, s.col_tile) <= lds_max && refactor_lds_bytes(s) <= lds_max;
+  return "";
+}
+
+}  // namespace rkkt

@@ -1,0 +1,81 @@
+// Host-side symbolic analysis of the block AC-OPF reduced-KKT path.
+//
+// Everything here depends only on the network (never on values), is computed
+// once per problem and shared by all scenario blocks: the paper's blocks share
+// one sparsity pattern (parallel AD section: Jacobians of the blocks share
+// their pattern; parallel KKT section: batched LU on a shared pattern).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "layout.h"
+#include "rkkt.h"
+
+namespace rkkt {
+
+struct Sym {
+  int nb = 0, nl = 0, ng = 0, nload = 0, ref = 0, gref = 0;
+  int nx = 0, nu = 0, m = 0, nz = 0, N = 0;
+  int col_tile = 0;
+  bool lds_resident = true;
+
+  // internal x order: xhat = perm applied to the external order
+  std::vector<int> perm;  // perm[ihat] = i_ext
+  std::vector<int> pinv;  // pinv[i_ext] = ihat
+
+  // buses
+  std::vector<int> th_src;   // external x index of theta_b, -1 for the reference bus
+  std::vector<int> v_src;    // external x index of V_b (PQ), or -(1+u index) (generator bus)
+  std::vector<int> prow;     // external g row of the P balance of b, -1 for ref
+  std::vector<int> qrow;     // external g row of the Q balance of b (PQ) or -(1+gen) (gen bus)
+  std::vector<int> pg_u;     // u index of Pg at bus b (non-ref generator bus) or -1
+  std::vector<int> gnr;      // non-reference generators, generator order
+  std::vector<int> gen_bus;
+
+  // lines: internal z index of the locals (th_f, th_t, v_f, v_t), -1 = constant
+  std::vector<int> line_f, line_t, line_loc;
+
+  // evaluation outputs EV = [P_b (nb) | Q_b (nb) | Gx values | Gu values | H values]
+  int n_ev = 0, off_P = 0, off_Q = 0, off_gx = 0, off_gu = 0, off_h = 0;
+  std::vector<int> ev_ptr, ev_src;
+  std::vector<double> ev_const;
+
+  // G_x (internal rows and columns), CSR; value k is EV[off_gx + k]
+  std::vector<int> gx_ptr, gx_col;
+  // G_u (internal rows), CSR; value k is EV[off_gu + k]
+  std::vector<int> gu_ptr, gu_col;
+  // G_u by column: internal row and value index
+  std::vector<int> guc_ptr, guc_row, guc_pos;
+  // H (external rows), CSR with internal z columns; value k is EV[off_h + k]
+  std::vector<int> h_ptr, h_col;
+  // H transposed: for internal z var, (row, value index)
+  std::vector<int> ht_ptr, ht_row, ht_pos;
+  // position of every z var in H row 0 (gradient of the reference output), -1 if none
+  std::vector<int> h0pos;
+
+  // K over internal z = (xhat, u): CSR, full symmetric storage, sorted columns
+  std::vector<int> k_ptr, k_col, k_diag, k_usplit;  // k_usplit[r]: first entry with col >= nx
+  // W gather: LH sources, product terms (coef * Hval[a] * Hval[b]), constant (times obj weight)
+  std::vector<int> w_ptr, w_src;
+  std::vector<int> wp_ptr, wp_a, wp_b;
+  std::vector<double> wp_coef, w_const;
+  // condensation triplets: K[e] += sigma_s[row] * Hval[a] * Hval[b]
+  std::vector<int> t_ptr, t_row, t_a, t_b;
+
+  // filled LU pattern of P G_x P^T (internal order), CSR with sorted columns
+  std::vector<int> f_ptr, f_col, f_diag, f_tpos;
+  std::vector<int> upd_ptr, upd_src, upd_dst;  // per F position (L part): updates of row i by row k
+  std::vector<int> gx2f;                       // F position of every G_x entry
+  std::vector<int> lvu_ptr, lvu_rows, lvd_ptr, lvd_rows;
+  long long lu_flops = 0;
+};
+
+// Returns an empty string on success, else the error message.
+std::string build_symbolic(const rkkt_network& net, int n_scen, int col_tile_req, Sym& s);
+
+// LDS bytes of the reduction workgroup for a tile width.
+long long reduce_lds_bytes(const Sym& s, int w);
+long long refactor_lds_bytes(const Sym& s);
+
+}  // namespace rkkt

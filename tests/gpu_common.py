@@ -1,0 +1,101 @@
+"""Helpers shared by the GPU tests: move arrays to the device, run the C ABI,
+run the oracle on the same seeded inputs."""
+import numpy as np
+import scipy.linalg as sla
+
+import synthgrid as sg
+from synthgrid.iterates import random_iterate
+from oracle import kkt
+
+
+def dev(a, torch):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def oracle_state(inst, it, delta_w=None):
+    """Oracle evaluation, diagonals and reduced matrix on a seeded iterate.
+    If delta_w is None the smallest delta_w in {0, 1e-2 * 4^k} making the
+    reduced matrix positive definite is chosen."""
+    prob = kkt.Problem(inst)
+    N = prob.N
+    zeros = np.zeros
+    I = kkt.Iterate(it["x"], it["u"], zeros((N, prob.m)), it["y"], it["z"],
+                    zeros((N, prob.n_x)), zeros((N, prob.n_x)), zeros(prob.n_u), zeros(prob.n_u),
+                    zeros((N, prob.m)), zeros((N, prob.m)))
+    ev = kkt.evaluate(prob, I, it["obj_weight"])
+    dg = kkt.Diag(it["sigma_x"], it["sigma_u"], it["sigma_s"])
+    if delta_w is None:
+        dw = 0.0
+        while True:
+            red = kkt.reduced_hessian(prob, ev, dg, dw)
+            if kkt.cholesky_info(red.khat)[0] == 0:
+                break
+            dw = 1e-2 if dw == 0.0 else 4 * dw
+    else:
+        dw = delta_w
+        red = kkt.reduced_hessian(prob, ev, dg, dw)
+    return prob, ev, dg, red, dw
+
+
+class GpuRun:
+    """Runs evaluate / condense / factor / step through the C ABI."""
+
+    def __init__(self, inst, it, delta_w, torch, col_tile=0):
+        import paper_2301_04869_amd as R
+        self.R = R
+        net = inst.net
+        self.p = R.rkkt_create(net, inst.scen.pd.T, inst.scen.qd.T, col_tile=col_tile)
+        d = self.p.dims
+        N, nx, nu, m = d["n_scen"], d["n_x"], d["n_u"], d["m"]
+        t = lambda a: dev(a, torch)  # noqa: E731
+        self.inp = {k: t(v) for k, v in it.items() if k != "obj_weight"}
+        z = lambda *s: torch.zeros(*s, dtype=torch.float64, device="cuda")  # noqa: E731
+        self.f, self.gx, self.gu, self.g, self.h = z(N), z(N, nx), z(N, nu), z(N, nx), z(N, m)
+        self.khat = z(nu, nu)
+        self.info = torch.zeros(1, dtype=torch.int32, device="cuda")
+        self.out = dict(px=z(N, nx), pu=z(nu), ps=z(N, m), py=z(N, nx), pz=z(N, m))
+        self.delta_w = delta_w
+        self.w = it["obj_weight"]
+
+    def evaluate(self):
+        i = self.inp
+        self.R.rkkt_evaluate(self.p, i["x"], i["u"], i["y"], i["z"], self.w, self.f, self.gx,
+                             self.gu, self.g, self.h)
+
+    def condense(self):
+        i = self.inp
+        self.R.rkkt_condense(self.p, i["sigma_x"], i["sigma_u"], i["sigma_s"], self.delta_w, self.khat)
+
+    def factor(self):
+        self.chol = self.khat.clone()
+        self.R.rkkt_factor(self.p, self.chol, self.info)
+
+    def step(self):
+        i, o = self.inp, self.out
+        self.R.rkkt_step(self.p, i["r1x"], i["r1u"], i["r2"], i["r3"], i["r4"], i["sigma_s"],
+                         self.chol, o["px"], o["pu"], o["ps"], o["py"], o["pz"])
+
+
+def rel_fro(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def cond2(a):
+    return float(np.linalg.cond(a))
+
+
+def oracle_step(prob, ev, dg, red, dw, it):
+    rs = kkt.Resid(it["r1x"], it["r1u"], it["r2"], it["r3"], it["r4"])
+    return kkt.newton_reduced(prob, ev, dg, rs, dw, red)
+
+
+def chol_lower(a):
+    return sla.cholesky(a, lower=True)
+
+
+def instance(name, n_scen=None):
+    return sg.preset(name, n_scen=n_scen)
+
+
+def iterate(inst, seed):
+    return random_iterate(inst.net, inst.scen.n_scen, seed)

@@ -349,3 +349,17 @@ def test_planted_reduction_error_is_caught(monkeypatch):
     monkeypatch.setattr(kkt, "reduced_hessian", broken)
     with pytest.raises(AssertionError):
         test_full_condensed_reduced_steps_agree("tiny9", 3.0)
+
+
+def test_three_step_columns_equal_reduced_matrix():
+    """The paper's three-step K_hat V product equals the reduced matrix built
+    from S = -G_x^-1 G_u (two independent oracle paths)."""
+    prob = kkt.Problem(sg.preset("tiny9"))
+    rng = np.random.default_rng(29)
+    it = rand_iterate(prob, rng)
+    ev = kkt.evaluate(prob, it, 0.01)
+    dg = kkt.diagonals(prob, it)
+    full = kkt.reduced_hessian(prob, ev, dg, 0.7).khat
+    cols = [0, 2, prob.n_u - 1]
+    part = kkt.reduced_hessian_columns(prob, ev, dg, 0.7, cols)
+    assert np.abs(part - full[:, cols]).max() <= 1e-11 * np.abs(full).max()

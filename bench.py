@@ -1,0 +1,270 @@
+"""Benchmark of the reduced-KKT hot path on one MI355X.
+
+One step = one pass of the whole per-iteration hot path over all scenarios:
+evaluate (f, g, h, Jacobians, Hessian of the Lagrangian), condense (K, LU of
+G_x, local reduction, scenario sum), factor (dense Cholesky) and step
+(reduced right-hand side, p_u, recovery), through the C ABI, on a seeded
+synthetic iterate whose inputs are resident in device memory.
+
+Printed JSON line: the whole-path throughput in scenario-IPM-iterations/s,
+the condense+factor throughput next to the same kernels launched one
+scenario at a time (the plain per-scenario form), the roofline position of
+the dominant stage (HIP events on the launch stream inside the timed
+region) and the CPU oracle timed on a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--config c1|c4] [--no-cpu] [--no-plain]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP64_PEAK_TFS = 78.6           # MI355X FP64 vector (and FP64 matrix) TFLOP/s
+
+WORKLOADS = {
+    "c1": "118-bus / 186-line / 54-generator synthetic grid (the sizes of the paper's case118), "
+          "N = 128 load scenarios (sigma 0.1), n_x = 181, n_u = 107; full hot path per step",
+    "c4": "9241-bus / 16049-line / 1445-generator synthetic grid (the sizes of the paper's "
+          "case9241pegase), N = 16 load scenarios (sigma 0.1), n_x = 17036, n_u = 2889; full hot path per step",
+}
+
+
+def stage_work(d):
+    """Algorithmic flops and HBM bytes of one launch of every stage.
+
+    Bytes count every value array read or written once (inputs, cached
+    Jacobian / Hessian / K / LU values, outputs) and every shared index array
+    once; flops count the multiply-adds of the method (2 flops each)."""
+    N, nx, nu, m = d["n_scen"], d["n_x"], d["n_u"], d["m"]
+    nlu, nk, nkx, ngu, ngx, nh = d["nnz_lu"], d["nnz_k"], d["nnz_kx"], d["nnz_gu"], d["nnz_gx"], d["nnz_h"]
+    nev, ntrip = d["n_ev"], d["n_trip"]
+    nl = d["n_line"]
+    w = {}
+    w["evaluate"] = (N * (nl * 200 + 2 * ntrip),
+                     8 * N * (2 * nx + m + nu) + 8 * nu
+                     + 8 * N * (1 + 2 * nx + m + nu) + 8 * N * (nev + nk))
+    w["condense_values"] = (N * 3 * ntrip, 8 * N * (nk + nh + m + nx + nk) + 4 * 3 * ntrip)
+    w["refactor"] = (N * 2 * d["lu_update_flops"], 8 * N * (ngx + nlu + nx) + 4 * 3 * nlu)
+    w["reduce"] = (N * nu * (4 * nlu + 2 * nkx + 2 * ngu),
+                   8 * N * (nlu + nx + nk + ngu + nu * nu) + 4 * (3 * nlu + 2 * nk))
+    w["scenario_sum"] = (N * nu * nu, 8 * (N + 1) * nu * nu + 8 * nu)
+    w["factor"] = (nu ** 3 / 3.0, 8 * 2 * nu * nu)
+    w["step_rhs"] = (N * (8 * nlu + 4 * nkx + 4 * nh), 8 * N * (nlu + nk + nh + 2 * nx + 3 * m + nu))
+    w["reduced_solve"] = (2 * nu * nu + N * nu, 8 * (nu * nu + N * nu + 2 * nu))
+    w["step_recover"] = (N * (8 * nlu + 4 * nk + 4 * nh), 8 * N * (nlu + nk + nh + 4 * nx + 5 * m))
+    return w
+
+
+def roofline_entry(stage, ms, count, d):
+    flops, nbytes = stage_work(d)[stage]
+    t = ms / count * 1e-3
+    t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
+    t_alu = flops / (FP64_PEAK_TFS * 1e12)
+    if t_hbm >= t_alu:
+        ach = nbytes / t / 1e9
+        return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel_stage": stage,
+                "avg_ms": ms / count, "algorithmic_bytes": nbytes, "algorithmic_flops": flops}
+    ach = flops / t / 1e12
+    return {"bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
+            "frac": ach / FP64_PEAK_TFS, "traffic": None, "kernel_stage": stage,
+            "avg_ms": ms / count, "algorithmic_bytes": nbytes, "algorithmic_flops": flops}
+
+
+def find_delta_w(R, torch, p, t, khat, chol, info):
+    """Inertia correction of the interior-point rules: delta_w = 0, then 1e-4,
+    x100 until the reduced matrix factorises."""
+    dw = 0.0
+    while True:
+        R.rkkt_condense(p, t["sigma_x"], t["sigma_u"], t["sigma_s"], dw, khat)
+        chol.copy_(khat)
+        R.rkkt_factor(p, chol, info)
+        torch.cuda.synchronize()
+        if int(info.item()) == 0:
+            return dw
+        dw = 1e-4 if dw == 0.0 else 100.0 * dw
+        if dw > 1e20:
+            raise RuntimeError("inertia correction failed")
+
+
+def cpu_baseline(inst, it, dw, budget_s=12.0):
+    """The oracle (as it stands) on the same iterate: evaluation, diagonals,
+    reduced matrix, Cholesky and Newton step for a bounded number of
+    scenarios, repeated until the time budget is used."""
+    from threadpoolctl import threadpool_limits
+    import synthgrid as sg
+    from oracle import kkt
+    cores = len(os.sched_getaffinity(0))
+    net, N = inst.net, inst.scen.n_scen
+    ns = min(N, 16 if net.n_bus > 1000 else 32)
+    sub = sg.Instance(inst.name, net, sg.Scenarios(inst.scen.pd[:, :ns], inst.scen.qd[:, :ns],
+                                                   inst.scen.sigma, inst.scen.seed))
+    prob = kkt.Problem(sub)
+    z = np.zeros
+    I = kkt.Iterate(it["x"][:ns], it["u"], z((ns, prob.m)), it["y"][:ns], it["z"][:ns],
+                    z((ns, prob.n_x)), z((ns, prob.n_x)), z(prob.n_u), z(prob.n_u), z((ns, prob.m)),
+                    z((ns, prob.m)))
+    dg = kkt.Diag(it["sigma_x"][:ns], it["sigma_u"], it["sigma_s"][:ns])
+    rs = kkt.Resid(it["r1x"][:ns], it["r1u"], it["r2"][:ns], it["r3"][:ns], it["r4"][:ns])
+    passes = 0
+    t0 = time.perf_counter()
+    with threadpool_limits(limits=cores):
+        while True:
+            ev = kkt.evaluate(prob, I, it["obj_weight"])
+            red = kkt.reduced_hessian(prob, ev, dg, dw)
+            kkt.newton_reduced(prob, ev, dg, rs, dw, red)
+            passes += 1
+            el = time.perf_counter() - t0
+            if el >= budget_s or (net.n_bus > 1000 and passes >= 1):
+                break
+    return {"value": ns * passes / el, "unit": "scenario-IPM-iterations/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{passes} pass(es) of evaluate + reduced matrix + Cholesky + Newton step over "
+                      f"{ns} of the {N} scenarios, {el:.1f} s, BLAS threads = {cores}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="c1", choices=sorted(WORKLOADS))
+    ap.add_argument("--col-tile", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--seed", type=int, default=2024)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the scenario split across GPUs is not implemented)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synthgrid as sg
+    from synthgrid.iterates import random_iterate
+    import paper_2301_04869_amd as R
+
+    R.lib()
+    inst = sg.preset(args.config)
+    net, N = inst.net, inst.scen.n_scen
+    it = random_iterate(net, N, args.seed)
+    p = R.rkkt_create(net, inst.scen.pd.T, inst.scen.qd.T, col_tile=args.col_tile)
+    d = p.dims
+    nx, nu, m = d["n_x"], d["n_u"], d["m"]
+    t = {k: torch.tensor(np.ascontiguousarray(v), dtype=torch.float64, device="cuda")
+         for k, v in it.items() if k != "obj_weight"}
+    w = it["obj_weight"]
+    zf = lambda *s: torch.zeros(*s, dtype=torch.float64, device="cuda")  # noqa: E731
+    f, gx, gu, g, h = zf(N), zf(N, nx), zf(N, nu), zf(N, nx), zf(N, m)
+    khat, chol = zf(nu, nu), zf(nu, nu)
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    px, pu, ps, py, pz = zf(N, nx), zf(nu), zf(N, m), zf(N, nx), zf(N, m)
+    stream = torch.cuda.current_stream()
+
+    R.rkkt_evaluate(p, t["x"], t["u"], t["y"], t["z"], w, f, gx, gu, g, h)
+    dw = find_delta_w(R, torch, p, t, khat, chol, info)
+
+    def step():
+        R.rkkt_evaluate(p, t["x"], t["u"], t["y"], t["z"], w, f, gx, gu, g, h, stream)
+        R.rkkt_condense(p, t["sigma_x"], t["sigma_u"], t["sigma_s"], dw, khat, stream)
+        chol.copy_(khat)
+        R.rkkt_factor(p, chol, info, stream)
+        R.rkkt_step(p, t["r1x"], t["r1u"], t["r2"], t["r3"], t["r4"], t["sigma_s"], chol,
+                    px, pu, ps, py, pz, stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    code, scen = R.rkkt_status(p)
+    if code != 0:
+        raise RuntimeError(f"device status {code} in scenario {scen}")
+    R.rkkt_profile_begin(p, 16 * args.steps + 16)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    stages = R.rkkt_profile_end(p)
+    ms = e0.elapsed_time(e1) / args.steps
+    value = N / (ms * 1e-3)
+    cf_ms = sum(stages[s][0] for s in ("condense_values", "refactor", "reduce", "scenario_sum",
+                                       "factor")) / args.steps
+    dom = max((s for s in stages if stages[s][1] > 0), key=lambda s: stages[s][0])
+    roof = roofline_entry(dom, stages[dom][0], stages[dom][1], d)
+
+    out = {
+        "metric": "scenario-IPM-iterations/sec (condense+factor) vs plain form; IPM iters w/ warm start",
+        "value": value, "unit": "scenario-IPM-iterations/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.config], "n_scen": N, "n_x": nx, "n_u": nu, "m": m,
+                   "nnz_lu": d["nnz_lu"], "col_tile": d["col_tile"], "delta_w": dw,
+                   "seed": args.seed},
+        "condense_factor_value": N / (cf_ms * 1e-3),
+        "stage_ms": {s: stages[s][0] / max(stages[s][1], 1) for s in stages},
+        "roofline": roof,
+    }
+
+    if not args.no_plain:
+        # the same kernels, one scenario per handle and per launch, no batching
+        handles = [R.rkkt_create(net, inst.scen.pd[:, k:k + 1].T, inst.scen.qd[:, k:k + 1].T,
+                                 col_tile=args.col_tile) for k in range(N)]
+        tk = [{n: t[n][k:k + 1].contiguous() for n in ("x", "y", "z", "sigma_x", "sigma_s")}
+              for k in range(N)]
+        su0 = zf(nu)
+        kk = [zf(nu, nu) for _ in range(N)]
+        f1, gx1, gu1, g1, h1 = zf(1), zf(1, nx), zf(1, nu), zf(1, nx), zf(1, m)
+        kplain, cplain = zf(nu, nu), zf(nu, nu)
+        eye_dw = torch.eye(nu, dtype=torch.float64, device="cuda") * dw
+
+        for k in range(N):
+            R.rkkt_evaluate(handles[k], tk[k]["x"], t["u"], tk[k]["y"], tk[k]["z"], w,
+                            f1, gx1, gu1, g1, h1, stream)
+
+        def plain():
+            for k in range(N):
+                R.rkkt_condense(handles[k], tk[k]["sigma_x"], su0, tk[k]["sigma_s"], dw, kk[k], stream)
+            kplain.copy_(torch.diag(t["sigma_u"]) - (N - 1) * eye_dw)
+            for k in range(N):
+                kplain.add_(kk[k])
+            cplain.copy_(kplain)
+            R.rkkt_factor(handles[0], cplain, info, stream)
+
+        plain()
+        torch.cuda.synchronize()
+        err = float(torch.linalg.norm(kplain - khat) / torch.linalg.norm(khat))
+        n_pl = max(3, args.steps // 8)
+        e0.record(stream)
+        for _ in range(n_pl):
+            plain()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        pms = e0.elapsed_time(e1) / n_pl
+        out["plain_form"] = {"ms_per_iteration": pms, "value": N / (pms * 1e-3),
+                             "unit": "scenario-IPM-iterations/s",
+                             "what": "condense launched once per scenario (N = 1 handles), "
+                                     "sum of the scenario matrices, Cholesky",
+                             "khat_rel_diff_vs_batched": err}
+        out["speedup_condense_factor_vs_plain"] = out["condense_factor_value"] / out["plain_form"]["value"]
+        del handles
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(inst, it, dw)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -384,3 +384,36 @@ def reduced_hessian_columns(prob: Problem, ev: Eval, dg: Diag, delta_w: float, c
         Lu = Kxu.T @ Tx + Kuu @ V
         out += Lu - ev.Gu[k].T @ fac.solve(Lx, trans=True)
     return out
+
+
+def augmented_residual(prob: Problem, ev: Eval, dg: Diag, rs: Resid, delta_w: float, step: dict):
+    """Block rows of the augmented Newton system (eq. of the augmented system)
+    evaluated at a candidate step, scenario by scenario with sparse blocks:
+      row 1 (x_i): (W_xx + Sigma_x + dw) p_x + W_xu p_u + G_x^T p_y + H_x^T p_z + r1x
+      row 1 (u):   sum_i [W_ux p_x + W_uu p_u + G_u^T p_y + H_u^T p_z] + (Sigma_u + dw) p_u + r1u
+      row 2:       Sigma_s p_s + p_z + r2
+      row 3:       G_x p_x + G_u p_u + r3
+      row 4:       H_x p_x + H_u p_u + p_s + r4
+    Returns (residual 2-norm, scale) with scale the 2-norm of all terms."""
+    pu = step["pu"]
+    res = []
+    scale = []
+    ru = (dg.su + delta_w) * pu + rs.r1u
+    su_terms = [np.linalg.norm((dg.su + delta_w) * pu), np.linalg.norm(rs.r1u)]
+    for k in range(prob.N):
+        px, py, ps, pz = step["px"][k], step["py"][k], step["ps"][k], step["pz"][k]
+        t1 = [ev.Wxx[k] @ px + (dg.sx[k] + delta_w) * px, ev.Wxu[k] @ pu, ev.Gx[k].T @ py,
+              ev.Hx[k].T @ pz, rs.r1x[k]]
+        tu = [ev.Wxu[k].T @ px, ev.Wuu[k] @ pu, ev.Gu[k].T @ py, ev.Hu[k].T @ pz]
+        ru = ru + sum(tu)
+        su_terms += [np.linalg.norm(t) for t in tu]
+        t2 = [dg.ss[k] * ps, pz, rs.r2[k]]
+        t3 = [ev.Gx[k] @ px, ev.Gu[k] @ pu, rs.r3[k]]
+        t4 = [ev.Hx[k] @ px, ev.Hu[k] @ pu, ps, rs.r4[k]]
+        for terms in (t1, t2, t3, t4):
+            res.append(sum(terms))
+            scale += [np.linalg.norm(t) for t in terms]
+    res.append(ru)
+    scale += su_terms
+    r = float(np.sqrt(sum(float(np.dot(v, v)) for v in res)))
+    return r, float(np.linalg.norm(scale))

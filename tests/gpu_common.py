@@ -12,7 +12,7 @@ def dev(a, torch):
     return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
 
 
-def oracle_state(inst, it, delta_w=None):
+def oracle_state(inst, it, delta_w=None, reduced=True):
     """Oracle evaluation, diagonals and reduced matrix on a seeded iterate.
     If delta_w is None the smallest delta_w in {0, 1e-2 * 4^k} making the
     reduced matrix positive definite is chosen."""
@@ -24,6 +24,8 @@ def oracle_state(inst, it, delta_w=None):
                     zeros((N, prob.m)), zeros((N, prob.m)))
     ev = kkt.evaluate(prob, I, it["obj_weight"])
     dg = kkt.Diag(it["sigma_x"], it["sigma_u"], it["sigma_s"])
+    if not reduced:
+        return prob, ev, dg, None, delta_w
     if delta_w is None:
         dw = 0.0
         while True:

@@ -363,3 +363,20 @@ def test_three_step_columns_equal_reduced_matrix():
     cols = [0, 2, prob.n_u - 1]
     part = kkt.reduced_hessian_columns(prob, ev, dg, 0.7, cols)
     assert np.abs(part - full[:, cols]).max() <= 1e-11 * np.abs(full).max()
+
+
+def test_augmented_residual_vanishes_at_the_newton_step():
+    prob = kkt.Problem(sg.preset("tiny9"))
+    rng = np.random.default_rng(31)
+    it = rand_iterate(prob, rng)
+    ev = kkt.evaluate(prob, it, 0.01)
+    dg = kkt.diagonals(prob, it)
+    rs = kkt.residuals(prob, it, ev, 0.05)
+    dw = 3.0
+    st = kkt.newton_full(prob, ev, dg, rs, dw)
+    r, s = kkt.augmented_residual(prob, ev, dg, rs, dw, st)
+    assert r <= 1e-12 * s
+    bad = dict(st)
+    bad["pu"] = st["pu"] * (1 + 1e-6)
+    r2, _ = kkt.augmented_residual(prob, ev, dg, rs, dw, bad)
+    assert r2 > 1e3 * r

@@ -93,6 +93,9 @@ typedef struct {
   int n_x, n_u, m, n_scen, n_bus, n_line, n_gen;
   long long nnz_gx, nnz_gu, nnz_h, nnz_k, nnz_lu;   /* per scenario            */
   long long lu_update_flops;        /* multiply-adds of one G_x refactorisation */
+  long long nnz_kx;                 /* entries of K in x columns (K_xx and K_ux) */
+  long long n_ev;                   /* evaluation outputs per scenario          */
+  long long n_trip;                 /* H^T Sigma_s H product terms per scenario  */
   int levels_up, levels_down;       /* level-schedule depths of the LU solves   */
   int col_tile;                     /* chosen column tile                       */
   long long workspace_bytes;        /* device bytes owned by the handle         */
@@ -178,6 +181,41 @@ int rkkt_step(rkkt_problem* p, const double* r1x, const double* r1u, const doubl
               double* px, double* pu, double* ps, double* py, double* pz, hipStream_t stream);
 
 /*
+ * Interior-point solve on the device around evaluate / condense / factor /
+ * step.  The paper runs its KKT solver inside an IPOPT-style primal-dual
+ * method it does not spell out; this driver follows the published filter
+ * line-search rules (start point pushed into the boxes; monotone barrier
+ * update mu <- max(tol/10, min(0.2 mu, mu^1.5)) while E_mu <= 10 mu; fraction
+ * to boundary max(0.99, 1 - mu); inertia correction on the reduced matrix;
+ * switching / Armijo / filter acceptance with halving; no second-order
+ * correction, no restoration phase).  Objective scaled by
+ * min(1, 100 / max|grad f(x0)|) / N.  Per iteration the host reads a few
+ * scalars (this call synchronises; its workspace is allocated on first use).
+ * Outputs (device, caller-owned, may be NULL): the final x [N][n_x], u [n_u],
+ * y [N][n_x], z [N][m], s [N][m].  res->status: 0 converged (scaled KKT
+ * error <= tol), 1 iteration limit, 2 line search failed, 3 inertia
+ * correction failed, 4 device error.
+ */
+typedef struct {
+  double tol;      /* scaled KKT tolerance; <= 0 means 1e-8 */
+  int max_iter;    /* < 0 means 200 */
+  double mu0;      /* initial barrier parameter; <= 0 means 0.1 */
+  int verbose;     /* one line per iteration on stdout */
+} rkkt_ipm_options;
+
+typedef struct {
+  int status, iters;
+  double obj;          /* average scenario cost (unscaled) */
+  double kkt_error;    /* scaled KKT error at the last iterate */
+  double mu;           /* final barrier parameter */
+  double obj_weight;   /* objective weight used by evaluate */
+  int factorizations;  /* Cholesky factorisations, inertia corrections included */
+} rkkt_ipm_result;
+
+int rkkt_solve(rkkt_problem* p, const rkkt_ipm_options* opt, double* x, double* u, double* y,
+               double* z, double* s, rkkt_ipm_result* res, hipStream_t stream);
+
+/*
  * Stage timing with HIP events recorded on the caller's stream around every
  * internal launch group (for benchmarks).  rkkt_profile_begin creates up to
  * max_records event pairs (this call allocates) and starts recording;
@@ -200,6 +238,35 @@ enum {
 };
 int rkkt_profile_begin(rkkt_problem* p, int max_records);
 int rkkt_profile_end(rkkt_problem* p, hipStream_t stream, double* ms, int* count);
+
+/*
+ * One hot-path pass with fixed buffers: evaluate, condense, copy khat into
+ * chol, factor chol in place, step (the calls above in that order, each
+ * argument as documented there).
+ */
+typedef struct {
+  const double *x, *u, *y, *z;
+  double obj_weight;
+  double *f, *grad_x, *grad_u, *g, *h;
+  const double *sigma_x, *sigma_u, *sigma_s;
+  double delta_w;
+  double *khat, *chol;
+  int* info;
+  const double *r1x, *r1u, *r2, *r3, *r4;
+  double *px, *pu, *ps, *py, *pz;
+} rkkt_iteration;
+
+int rkkt_iterate(rkkt_problem* p, const rkkt_iteration* it, hipStream_t stream);
+
+/*
+ * The same pass captured once into a HIP graph owned by the handle
+ * (rkkt_graph_capture records it from a capture stream of the handle; no
+ * device work runs) and replayed on `stream` by rkkt_graph_launch: one launch
+ * per iteration instead of one per kernel.  The graph keeps the pointers and
+ * scalars of `it`; capture again after changing any of them (e.g. delta_w).
+ */
+int rkkt_graph_capture(rkkt_problem* p, const rkkt_iteration* it);
+int rkkt_graph_launch(rkkt_problem* p, hipStream_t stream);
 
 /*
  * Synchronise `stream`, read and clear the device status word:

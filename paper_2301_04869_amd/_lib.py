@@ -23,7 +23,10 @@ ERRORS = {-1: "RKKT_ERR_ARG", -2: "RKKT_ERR_HIP", -3: "RKKT_ERR_SINGULAR_GX",
           -4: "RKKT_ERR_NOT_PD", -5: "RKKT_ERR_NONFINITE", -6: "RKKT_ERR_NOMEM"}
 EXPORTS = ("rkkt_create", "rkkt_analyze", "rkkt_set_loads", "rkkt_dims_get", "rkkt_evaluate",
            "rkkt_condense", "rkkt_factor", "rkkt_step", "rkkt_status", "rkkt_destroy",
-           "rkkt_last_error", "rkkt_profile_begin", "rkkt_profile_end")
+           "rkkt_last_error", "rkkt_profile_begin", "rkkt_profile_end", "rkkt_solve",
+           "rkkt_iterate", "rkkt_graph_capture", "rkkt_graph_launch")
+IPM_STATUS = {0: "converged", 1: "max_iter", 2: "line_search_failed",
+              3: "inertia_correction_failed", 4: "device_error"}
 STAGES = ("evaluate", "condense_values", "refactor", "reduce", "scenario_sum", "factor",
           "step_rhs", "reduced_solve", "step_recover")
 
@@ -56,11 +59,34 @@ class Dims(ctypes.Structure):
                 ("nnz_gx", ctypes.c_longlong), ("nnz_gu", ctypes.c_longlong),
                 ("nnz_h", ctypes.c_longlong), ("nnz_k", ctypes.c_longlong),
                 ("nnz_lu", ctypes.c_longlong), ("lu_update_flops", ctypes.c_longlong),
+                ("nnz_kx", ctypes.c_longlong), ("n_ev", ctypes.c_longlong),
+                ("n_trip", ctypes.c_longlong),
                 ("levels_up", ctypes.c_int), ("levels_down", ctypes.c_int),
                 ("col_tile", ctypes.c_int), ("workspace_bytes", ctypes.c_longlong)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_ITER_FIELDS = ("x", "u", "y", "z", "obj_weight", "f", "grad_x", "grad_u", "g", "h", "sigma_x",
+                "sigma_u", "sigma_s", "delta_w", "khat", "chol", "info", "r1x", "r1u", "r2", "r3",
+                "r4", "px", "pu", "ps", "py", "pz")
+
+
+class Iteration(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double if n in ("obj_weight", "delta_w") else ctypes.c_void_p)
+                for n in _ITER_FIELDS]
+
+
+class IpmOptions(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("mu0", ctypes.c_double),
+                ("verbose", ctypes.c_int)]
+
+
+class IpmResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int), ("obj", ctypes.c_double),
+                ("kkt_error", ctypes.c_double), ("mu", ctypes.c_double),
+                ("obj_weight", ctypes.c_double), ("factorizations", ctypes.c_int)]
 
 
 _lib = None
@@ -90,6 +116,11 @@ def lib():
     L.rkkt_destroy.argtypes = [vp]
     L.rkkt_profile_begin.argtypes = [vp, ctypes.c_int]
     L.rkkt_profile_end.argtypes = [vp, vp, c_dbl_p, c_int_p]
+    L.rkkt_solve.argtypes = [vp, ctypes.POINTER(IpmOptions), vp, vp, vp, vp, vp,
+                             ctypes.POINTER(IpmResult), vp]
+    L.rkkt_iterate.argtypes = [vp, ctypes.POINTER(Iteration), vp]
+    L.rkkt_graph_capture.argtypes = [vp, ctypes.POINTER(Iteration)]
+    L.rkkt_graph_launch.argtypes = [vp, vp]
     L.rkkt_last_error.argtypes = [vp]
     L.rkkt_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -246,6 +277,61 @@ def rkkt_profile_end(p, stream=None):
     cnt = (ctypes.c_int * len(STAGES))()
     _check(lib().rkkt_profile_end(p.ptr, _stream(stream), ms, cnt), p.ptr)
     return {s: (ms[i], cnt[i]) for i, s in enumerate(STAGES)}
+
+
+def rkkt_solve(p, x=None, u=None, y=None, z=None, s=None, tol=0.0, max_iter=-1, mu0=0.0,
+               verbose=False, stream=None):
+    """Device interior-point solve; optional device outputs x, u, y, z, s.
+    Returns the result fields as a dict (status as text)."""
+    d = p.dims
+    N, nx, nu, m = d["n_scen"], d["n_x"], d["n_u"], d["m"]
+
+    def opt(t, name, n):
+        return ctypes.c_void_p(None) if t is None else _ptr(t, name, n)
+    r = IpmResult()
+    _check(lib().rkkt_solve(p.ptr, ctypes.byref(IpmOptions(tol, max_iter, mu0, int(verbose))),
+                            opt(x, "x", N * nx), opt(u, "u", nu), opt(y, "y", N * nx),
+                            opt(z, "z", N * m), opt(s, "s", N * m), ctypes.byref(r),
+                            _stream(stream)), p.ptr)
+    out = {k: getattr(r, k) for k, _ in r._fields_}
+    out["status"] = IPM_STATUS.get(out["status"], out["status"])
+    return out
+
+
+def _iteration(p, a):
+    """Marshal a dict of tensors / scalars into the rkkt_iteration struct."""
+    d = p.dims
+    N, nx, nu, m = d["n_scen"], d["n_x"], d["n_u"], d["m"]
+    sizes = dict(x=N * nx, u=nu, y=N * nx, z=N * m, f=N, grad_x=N * nx, grad_u=N * nu, g=N * nx,
+                 h=N * m, sigma_x=N * nx, sigma_u=nu, sigma_s=N * m, khat=nu * nu, chol=nu * nu,
+                 r1x=N * nx, r1u=nu, r2=N * m, r3=N * nx, r4=N * m, px=N * nx, pu=nu, ps=N * m,
+                 py=N * nx, pz=N * m)
+    vals = []
+    for n in _ITER_FIELDS:
+        if n in ("obj_weight", "delta_w"):
+            vals.append(float(a[n]))
+        elif n == "info":
+            t = a[n]
+            if not (t.is_cuda and str(t.dtype) == "torch.int32"):
+                raise ValueError("info must be a device int32 tensor")
+            vals.append(ctypes.c_void_p(t.data_ptr()))
+        else:
+            vals.append(_ptr(a[n], n, sizes[n]))
+    return Iteration(*vals)
+
+
+def rkkt_iterate(p, args, stream=None):
+    it = _iteration(p, args)
+    _check(lib().rkkt_iterate(p.ptr, ctypes.byref(it), _stream(stream)), p.ptr)
+
+
+def rkkt_graph_capture(p, args):
+    it = _iteration(p, args)
+    _check(lib().rkkt_graph_capture(p.ptr, ctypes.byref(it)), p.ptr)
+
+
+def rkkt_graph_launch(p, stream=None):
+    _check(lib().rkkt_graph_launch(p.ptr, _stream(stream)), p.ptr)
 
 
 def rkkt_destroy(p):

@@ -11,19 +11,7 @@
 #include "rkkt.h"
 #include "symbolic.h"
 
-struct rkkt_problem {
-  rkkt::Sym sym;
-  rkkt::DP d{};
-  int device = 0;
-  std::vector<void*> allocs;
-  long long bytes = 0;
-  std::string err;
-  // stage timing (rkkt_profile_begin / rkkt_profile_end)
-  bool prof = false;
-  std::vector<hipEvent_t> events;          // 2 per record
-  std::vector<int> rec_stage;
-  size_t rec_used = 0;
-};
+#include "handle.h"
 
 namespace {
 
@@ -71,6 +59,11 @@ void fill_dims(const rkkt::Sym& s, rkkt_dims* o, long long bytes) {
   o->nnz_k = (long long)s.k_col.size();
   o->nnz_lu = (long long)s.f_col.size();
   o->lu_update_flops = s.lu_flops;
+  long long nkx = 0;
+  for (int r = 0; r < s.nz; ++r) nkx += s.k_usplit[r] - s.k_ptr[r];
+  o->nnz_kx = nkx;
+  o->n_ev = s.n_ev;
+  o->n_trip = (long long)s.t_row.size();
   o->levels_up = (int)s.lvu_ptr.size() - 1;
   o->levels_down = (int)s.lvd_ptr.size() - 1;
   o->col_tile = s.col_tile;
@@ -128,6 +121,8 @@ int rkkt_create(const rkkt_network* net, int n_scen, const double* pd, const dou
     delete p;
     return rc;
   }
+  rkkt::configure_lu_kernels();
+  rkkt::configure_dense_kernels();
   const rkkt::Sym& s = p->sym;
   rkkt::DP& d = p->d;
   d.nb = s.nb; d.nl = s.nl; d.ng = s.ng; d.nload = s.nload; d.ref = s.ref; d.gref = s.gref;
@@ -175,6 +170,7 @@ int rkkt_create(const rkkt_network* net, int n_scen, const double* pd, const dou
   UP(perm, s.perm) UP(pinv, s.pinv)
   UP(ev_ptr, s.ev_ptr) UP(ev_src, s.ev_src) UP(ev_const, s.ev_const)
   UP(gx_ptr, s.gx_ptr) UP(gx_col, s.gx_col) UP(gu_ptr, s.gu_ptr) UP(gu_col, s.gu_col)
+  UP(gxc_ptr, s.gxc_ptr) UP(gxc_row, s.gxc_row) UP(gxc_pos, s.gxc_pos)
   UP(guc_ptr, s.guc_ptr) UP(guc_row, s.guc_row) UP(guc_pos, s.guc_pos)
   UP(h_ptr, s.h_ptr) UP(h_col, s.h_col) UP(ht_ptr, s.ht_ptr) UP(ht_row, s.ht_row)
   UP(ht_pos, s.ht_pos) UP(h0pos, s.h0pos)
@@ -317,6 +313,59 @@ int rkkt_status(rkkt_problem* p, hipStream_t stream, int* code, int* scenario) {
   return RKKT_OK;
 }
 
+int rkkt_iterate(rkkt_problem* p, const rkkt_iteration* it, hipStream_t stream) {
+  if (!p || !it) return fail(p, RKKT_ERR_ARG, "rkkt_iterate: null argument");
+  int rc = rkkt_evaluate(p, it->x, it->u, it->y, it->z, it->obj_weight, it->f, it->grad_x,
+                         it->grad_u, it->g, it->h, stream);
+  if (rc) return rc;
+  rc = rkkt_condense(p, it->sigma_x, it->sigma_u, it->sigma_s, it->delta_w, it->khat, stream);
+  if (rc) return rc;
+  if (!it->chol || !it->info) return fail(p, RKKT_ERR_ARG, "rkkt_iterate: null chol or info");
+  rkkt::launch_copy(it->khat, it->chol, (long long)p->d.nu * p->d.nu, stream);
+  rc = rkkt_factor(p, it->chol, it->info, stream);
+  if (rc) return rc;
+  return rkkt_step(p, it->r1x, it->r1u, it->r2, it->r3, it->r4, it->sigma_s, it->chol, it->px,
+                   it->pu, it->ps, it->py, it->pz, stream);
+}
+
+static void release_graph(rkkt_problem* p) {
+  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  p->gexec = nullptr;
+  p->graph = nullptr;
+}
+
+int rkkt_graph_capture(rkkt_problem* p, const rkkt_iteration* it) {
+  if (!p || !it) return fail(p, RKKT_ERR_ARG, "rkkt_graph_capture: null argument");
+  release_graph(p);
+  hipError_t e;
+  if (!p->cap_stream) {
+    e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(p, e, "rkkt_graph_capture: stream");
+  }
+  const bool prof = p->prof;
+  p->prof = false;
+  e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) { p->prof = prof; return hip_fail(p, e, "rkkt_graph_capture: begin"); }
+  int rc = rkkt_iterate(p, it, p->cap_stream);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(p->cap_stream, &g);
+  p->prof = prof;
+  if (rc != RKKT_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
+  if (e != hipSuccess) return hip_fail(p, e, "rkkt_graph_capture: end");
+  p->graph = g;
+  e = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) { release_graph(p); return hip_fail(p, e, "rkkt_graph_capture: instantiate"); }
+  return RKKT_OK;
+}
+
+int rkkt_graph_launch(rkkt_problem* p, hipStream_t stream) {
+  if (!p || !p->gexec) return fail(p, RKKT_ERR_ARG, "rkkt_graph_launch: nothing captured");
+  hipError_t e = hipGraphLaunch(p->gexec, stream);
+  if (e != hipSuccess) return hip_fail(p, e, "rkkt_graph_launch");
+  return RKKT_OK;
+}
+
 static void release_events(rkkt_problem* p) {
   for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
   p->events.clear();
@@ -361,6 +410,9 @@ int rkkt_profile_end(rkkt_problem* p, hipStream_t stream, double* ms, int* count
 int rkkt_destroy(rkkt_problem* p) {
   if (!p) return RKKT_OK;
   release_events(p);
+  release_graph(p);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  for (void* q : p->ipm_allocs) (void)hipFree(q);
   for (void* q : p->allocs) (void)hipFree(q);
   delete p;
   return RKKT_OK;

@@ -27,7 +27,8 @@ struct DP {
   // gathers
   const int *ev_ptr, *ev_src;
   const double *ev_const;
-  const int *gx_ptr, *gx_col, *gu_ptr, *gu_col, *guc_ptr, *guc_row, *guc_pos;
+  const int *gx_ptr, *gx_col, *gxc_ptr, *gxc_row, *gxc_pos;
+  const int *gu_ptr, *gu_col, *guc_ptr, *guc_row, *guc_pos;
   const int *h_ptr, *h_col, *ht_ptr, *ht_row, *ht_pos, *h0pos;
   const int *k_ptr, *k_col, *k_diag, *k_usplit, *k_row;
   const int *w_ptr, *w_src, *wp_ptr, *wp_a, *wp_b;
@@ -50,6 +51,11 @@ struct DP {
   double *rpart;   // [N][nu]
   int *status;     // [2]: code, scenario
 };
+
+// one-time kernel attributes (dynamic LDS limits); called by rkkt_create
+void configure_lu_kernels();
+void configure_dense_kernels();
+void launch_copy(const double* a, double* b, long long n, hipStream_t s);
 
 // launchers (k_eval.hip)
 void launch_bus_loads(const DP& d, const double* pd, const double* qd, hipStream_t s);

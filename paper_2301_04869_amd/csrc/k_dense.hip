@@ -167,6 +167,21 @@ __global__ __launch_bounds__(1024) void k_reduced_solve(DP d, const double* r1u,
 
 }  // namespace
 
+void configure_dense_kernels() {
+  const int lds = 160 * 1024;
+  (void)hipFuncSetAttribute((const void*)k_chol_small, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  (void)hipFuncSetAttribute((const void*)k_reduced_solve, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+}
+
+__global__ void k_copy(const double* a, double* b, long long n) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) b[t] = a[t];
+}
+
+void launch_copy(const double* a, double* b, long long n, hipStream_t s) {
+  k_copy<<<(unsigned)((n + kThreads - 1) / kThreads), kThreads, 0, s>>>(a, b, n);
+}
+
 void launch_scenario_sum(const DP& d, const double* su, double dw, double* khat, hipStream_t s) {
   const long long nn = (long long)d.nu * d.nu;
   k_scenario_sum<<<(unsigned)((nn + kThreads - 1) / kThreads), kThreads, 0, s>>>(d, su, dw, khat);
@@ -176,7 +191,6 @@ void launch_cholesky(const DP& d, double* a, int* info, hipStream_t s) {
   const int n = d.nu;
   if (n <= kSmallN) {
     size_t lds = 8 * (size_t)n * n;
-    (void)hipFuncSetAttribute((const void*)k_chol_small, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     k_chol_small<<<1, kThreads, lds, s>>>(a, n, info);
     return;
   }
@@ -195,7 +209,6 @@ void launch_cholesky(const DP& d, double* a, int* info, hipStream_t s) {
 void launch_reduced_solve(const DP& d, const double* r1u, const double* chol, double* pu,
                           hipStream_t s) {
   size_t lds = 8 * (size_t)d.nu;
-  (void)hipFuncSetAttribute((const void*)k_reduced_solve, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   k_reduced_solve<<<1, 1024, lds, s>>>(d, r1u, chol, pu);
 }
 

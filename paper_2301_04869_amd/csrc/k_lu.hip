@@ -395,10 +395,15 @@ __global__ __launch_bounds__(kThreads) void k_step_recover(DP d, const double* r
 
 }  // namespace
 
+void configure_lu_kernels() {
+  const int lds = 160 * 1024;
+  (void)hipFuncSetAttribute((const void*)k_refactor<true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  (void)hipFuncSetAttribute((const void*)k_reduce<true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+}
+
 void launch_refactor(const DP& d, hipStream_t s) {
   if (d.lds) {
     size_t lds = 8 * ((size_t)d.nnz_f + 2 * (size_t)d.nx) + 4 * (size_t)kWaves * d.nx;
-    (void)hipFuncSetAttribute((const void*)k_refactor<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     k_refactor<true><<<d.N, kThreads, lds, s>>>(d);
   } else {
     k_refactor<false><<<d.N, kThreads, 0, s>>>(d);
@@ -410,7 +415,6 @@ void launch_reduce(const DP& d, hipStream_t s) {
   dim3 grid(ntile, d.N);
   if (d.lds) {
     size_t lds = 8 * ((size_t)d.nnz_f + (size_t)d.nx + 2 * (size_t)d.nx * d.col_tile);
-    (void)hipFuncSetAttribute((const void*)k_reduce<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     k_reduce<true><<<grid, kThreads, lds, s>>>(d);
   } else {
     k_reduce<false><<<grid, kThreads, 0, s>>>(d);

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <array>
 #include <cstdio>
+#include <limits>
 #include <map>
 #include <numeric>
 #include <set>
@@ -334,6 +335,22 @@ std::string build_symbolic(const rkkt_network& net, int N, int col_tile_req, Sym
     if (s.gx_ptr[i + 1] == s.gx_ptr[i] || find_pos(s.gx_ptr, s.gx_col, i, i) < 0)
       return "G_x has a structurally zero diagonal (isolated bus?)";
 
+  // G_x by column
+  s.gxc_ptr.assign(nx + 1, 0);
+  for (int c : s.gx_col) s.gxc_ptr[c + 1]++;
+  for (int c = 0; c < nx; ++c) s.gxc_ptr[c + 1] += s.gxc_ptr[c];
+  s.gxc_row.resize(s.gx_col.size());
+  s.gxc_pos.resize(s.gx_col.size());
+  {
+    std::vector<int> cur(s.gxc_ptr.begin(), s.gxc_ptr.end() - 1);
+    for (int i = 0; i < nx; ++i)
+      for (int e = s.gx_ptr[i]; e < s.gx_ptr[i + 1]; ++e) {
+        int c = s.gx_col[e];
+        s.gxc_row[cur[c]] = i;
+        s.gxc_pos[cur[c]] = e;
+        cur[c]++;
+      }
+  }
   // G_u by column
   s.guc_ptr.assign(nu + 1, 0);
   for (int c : s.gu_col) s.guc_ptr[c + 1]++;
@@ -438,6 +455,31 @@ std::string build_symbolic(const rkkt_network& net, int N, int col_tile_req, Sym
       if (p < 0) return "internal: G_x entry outside the filled pattern";
       s.gx2f[e] = p;
     }
+
+  // boxes
+  {
+    const double inf = std::numeric_limits<double>::infinity();
+    s.xl.assign(nx, -inf);
+    s.xu.assign(nx, inf);
+    for (int b = 0; b < nb; ++b)
+      if (s.v_src[b] >= 0) { s.xl[s.v_src[b]] = net.vmin[b]; s.xu[s.v_src[b]] = net.vmax[b]; }
+    s.ul.assign(nu, 0.0);
+    s.uu.assign(nu, 0.0);
+    for (int g = 0; g < ng; ++g) { s.ul[g] = net.vmin[s.gen_bus[g]]; s.uu[g] = net.vmax[s.gen_bus[g]]; }
+    for (size_t j = 0; j < s.gnr.size(); ++j) {
+      s.ul[ng + j] = net.pmin[s.gnr[j]];
+      s.uu[ng + j] = net.pmax[s.gnr[j]];
+    }
+    s.sl.assign(s.m, -inf);
+    s.su.assign(s.m, inf);
+    s.sl[0] = -net.pmax[s.gref];
+    s.su[0] = -net.pmin[s.gref];
+    for (int g = 0; g < ng; ++g) { s.sl[1 + g] = -net.qmax[g]; s.su[1 + g] = -net.qmin[g]; }
+    for (int l = 0; l < nl; ++l) {
+      s.sl[1 + ng + l] = -net.rate[l] * net.rate[l];
+      s.sl[1 + ng + nl + l] = -net.rate[l] * net.rate[l];
+    }
+  }
 
   // column tile of the reduction
   const long long lds_max = 160 * 1024;

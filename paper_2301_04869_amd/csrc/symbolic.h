@@ -31,6 +31,8 @@ struct Sym {
   std::vector<int> qrow;     // external g row of the Q balance of b (PQ) or -(1+gen) (gen bus)
   std::vector<int> pg_u;     // u index of Pg at bus b (non-ref generator bus) or -1
   std::vector<int> gnr;      // non-reference generators, generator order
+  // boxes (+-inf when absent): x (external order), u, s = -h
+  std::vector<double> xl, xu, ul, uu, sl, su;
   std::vector<int> gen_bus;
 
   // lines: internal z index of the locals (th_f, th_t, v_f, v_t), -1 = constant
@@ -43,6 +45,8 @@ struct Sym {
 
   // G_x (internal rows and columns), CSR; value k is EV[off_gx + k]
   std::vector<int> gx_ptr, gx_col;
+  // G_x by column: internal row and value index
+  std::vector<int> gxc_ptr, gxc_row, gxc_pos;
   // G_u (internal rows), CSR; value k is EV[off_gu + k]
   std::vector<int> gu_ptr, gu_col;
   // G_u by column: internal row and value index

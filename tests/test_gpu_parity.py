@@ -125,3 +125,40 @@ def test_bad_arguments_raise_before_launch():
     with pytest.raises(R.RkktError):
         R.rkkt_condense(run.p, run.inp["sigma_x"], run.inp["sigma_u"], run.inp["sigma_s"],
                         float("nan"), run.khat)
+
+
+def _iter_args(run):
+    i, o = run.inp, run.out
+    return dict(x=i["x"], u=i["u"], y=i["y"], z=i["z"], obj_weight=run.w, f=run.f, grad_x=run.gx,
+                grad_u=run.gu, g=run.g, h=run.h, sigma_x=i["sigma_x"], sigma_u=i["sigma_u"],
+                sigma_s=i["sigma_s"], delta_w=run.delta_w, khat=run.khat, chol=run.chol,
+                info=run.info, r1x=i["r1x"], r1u=i["r1u"], r2=i["r2"], r3=i["r3"], r4=i["r4"],
+                px=o["px"], pu=o["pu"], ps=o["ps"], py=o["py"], pz=o["pz"])
+
+
+def test_graph_replays_match_eager():
+    """The captured pass, replayed several times with eager work and host
+    synchronisation between replays, reproduces the eager pass bit for bit."""
+    import paper_2301_04869_amd as R
+    inst = gc.instance("c1", 16)
+    it = gc.iterate(inst, seed=21)
+    _, _, _, _, dw = gc.oracle_state(inst, it)
+    run = gc.GpuRun(inst, it, dw, torch)
+    run.chol = torch.zeros_like(run.khat)
+    args = _iter_args(run)
+    R.rkkt_iterate(run.p, args)
+    torch.cuda.synchronize()
+    ref = {k: v.clone() for k, v in run.out.items()}
+    ref["khat"] = run.khat.clone()
+    R.rkkt_graph_capture(run.p, args)
+    for rep in range(4):
+        for v in list(run.out.values()) + [run.khat, run.chol]:
+            v.fill_(float("nan"))
+        run.evaluate()             # eager work between replays
+        torch.cuda.synchronize()
+        R.rkkt_graph_launch(run.p)
+        torch.cuda.synchronize()
+        for k, v in run.out.items():
+            assert torch.equal(v, ref[k]), (rep, k)
+        assert torch.equal(run.khat, ref["khat"]), rep
+        assert int(run.info.item()) == 0

@@ -386,7 +386,8 @@ def reduced_hessian_columns(prob: Problem, ev: Eval, dg: Diag, delta_w: float, c
     return out
 
 
-def augmented_residual(prob: Problem, ev: Eval, dg: Diag, rs: Resid, delta_w: float, step: dict):
+def augmented_residual(prob: Problem, ev: Eval, dg: Diag, rs: Resid, delta_w: float, step: dict,
+                       blocks=False):
     """Block rows of the augmented Newton system (eq. of the augmented system)
     evaluated at a candidate step, scenario by scenario with sparse blocks:
       row 1 (x_i): (W_xx + Sigma_x + dw) p_x + W_xu p_u + G_x^T p_y + H_x^T p_z + r1x
@@ -394,10 +395,12 @@ def augmented_residual(prob: Problem, ev: Eval, dg: Diag, rs: Resid, delta_w: fl
       row 2:       Sigma_s p_s + p_z + r2
       row 3:       G_x p_x + G_u p_u + r3
       row 4:       H_x p_x + H_u p_u + p_s + r4
-    Returns (residual 2-norm, scale) with scale the 2-norm of all terms."""
+    Returns (residual 2-norm, scale) with scale the 2-norm of all terms; with
+    blocks=True also a dict of (residual, scale) per block row."""
     pu = step["pu"]
     res = []
     scale = []
+    per = {"x": [0.0, 0.0], "s": [0.0, 0.0], "g": [0.0, 0.0], "h": [0.0, 0.0], "u": [0.0, 0.0]}
     ru = (dg.su + delta_w) * pu + rs.r1u
     su_terms = [np.linalg.norm((dg.su + delta_w) * pu), np.linalg.norm(rs.r1u)]
     for k in range(prob.N):
@@ -410,10 +413,17 @@ def augmented_residual(prob: Problem, ev: Eval, dg: Diag, rs: Resid, delta_w: fl
         t2 = [dg.ss[k] * ps, pz, rs.r2[k]]
         t3 = [ev.Gx[k] @ px, ev.Gu[k] @ pu, rs.r3[k]]
         t4 = [ev.Hx[k] @ px, ev.Hu[k] @ pu, ps, rs.r4[k]]
-        for terms in (t1, t2, t3, t4):
-            res.append(sum(terms))
-            scale += [np.linalg.norm(t) for t in terms]
+        for name, terms in (("x", t1), ("s", t2), ("g", t3), ("h", t4)):
+            rv = sum(terms)
+            res.append(rv)
+            sc = [np.linalg.norm(t) for t in terms]
+            scale += sc
+            per[name][0] += float(np.dot(rv, rv))
+            per[name][1] += float(np.sum(np.square(sc)))
     res.append(ru)
     scale += su_terms
+    per["u"] = [float(np.dot(ru, ru)), float(np.sum(np.square(su_terms)))]
     r = float(np.sqrt(sum(float(np.dot(v, v)) for v in res)))
+    if blocks:
+        return r, float(np.linalg.norm(scale)), {k: (np.sqrt(a), np.sqrt(b)) for k, (a, b) in per.items()}
     return r, float(np.linalg.norm(scale))

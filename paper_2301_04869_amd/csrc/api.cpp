@@ -105,6 +105,7 @@ int rkkt_analyze(const rkkt_network* net, int n_scen, const rkkt_options* opt, r
 
 int rkkt_create(const rkkt_network* net, int n_scen, const double* pd, const double* qd,
                 const rkkt_options* opt, rkkt_problem** out) {
+  (void)hipGetLastError();
   if (!net || !out) return fail(nullptr, RKKT_ERR_ARG, "rkkt_create: null argument");
   *out = nullptr;
   if (net->n_load > 0 && (!pd || !qd)) return fail(nullptr, RKKT_ERR_ARG, "rkkt_create: null loads");
@@ -121,8 +122,7 @@ int rkkt_create(const rkkt_network* net, int n_scen, const double* pd, const dou
     delete p;
     return rc;
   }
-  rkkt::configure_lu_kernels();
-  rkkt::configure_dense_kernels();
+
   const rkkt::Sym& s = p->sym;
   rkkt::DP& d = p->d;
   d.nb = s.nb; d.nl = s.nl; d.ng = s.ng; d.nload = s.nload; d.ref = s.ref; d.gref = s.gref;
@@ -202,6 +202,8 @@ int rkkt_create(const rkkt_network* net, int n_scen, const double* pd, const dou
     if ((e = dalloc(p, &d.rhat1, N * s.nx)) != hipSuccess) goto hip_error;
     if ((e = dalloc(p, &d.rpart, N * s.nu)) != hipSuccess) goto hip_error;
     if ((e = dalloc(p, &d.status, 2)) != hipSuccess) goto hip_error;
+    if ((e = rkkt::configure_lu_kernels(d)) != hipSuccess) goto hip_error;
+    if ((e = rkkt::configure_dense_kernels(d)) != hipSuccess) goto hip_error;
     if ((e = hipMemset(d.status, 0, 2 * sizeof(int))) != hipSuccess) goto hip_error;
     // loads
     if (s.nload > 0) {
@@ -235,6 +237,7 @@ hip_error : {
 }
 
 int rkkt_set_loads(rkkt_problem* p, const double* pd_dev, const double* qd_dev, hipStream_t stream) {
+  (void)hipGetLastError();  // do not report an earlier, unrelated error
   if (!p) return fail(nullptr, RKKT_ERR_ARG, "rkkt_set_loads: null handle");
   if (p->d.nload > 0 && (!pd_dev || !qd_dev)) return fail(p, RKKT_ERR_ARG, "rkkt_set_loads: null loads");
   if (p->d.nload == 0) return RKKT_OK;
@@ -251,6 +254,7 @@ int rkkt_dims_get(const rkkt_problem* p, rkkt_dims* out) {
 int rkkt_evaluate(rkkt_problem* p, const double* x, const double* u, const double* y,
                   const double* z, double obj_weight, double* f, double* grad_x, double* grad_u,
                   double* g, double* h, hipStream_t stream) {
+  (void)hipGetLastError();  // do not report an earlier, unrelated error
   if (!p) return fail(nullptr, RKKT_ERR_ARG, "rkkt_evaluate: null handle");
   if (!x || !u || !y || !z || !f || !grad_x || !grad_u || !g || !h)
     return fail(p, RKKT_ERR_ARG, "rkkt_evaluate: null array");
@@ -263,6 +267,7 @@ int rkkt_evaluate(rkkt_problem* p, const double* x, const double* u, const doubl
 
 int rkkt_condense(rkkt_problem* p, const double* sigma_x, const double* sigma_u,
                   const double* sigma_s, double delta_w, double* khat, hipStream_t stream) {
+  (void)hipGetLastError();  // do not report an earlier, unrelated error
   if (!p) return fail(nullptr, RKKT_ERR_ARG, "rkkt_condense: null handle");
   if (!sigma_x || !sigma_u || !sigma_s || !khat) return fail(p, RKKT_ERR_ARG, "rkkt_condense: null array");
   if (!std::isfinite(delta_w)) return fail(p, RKKT_ERR_ARG, "rkkt_condense: non-finite delta_w");
@@ -276,6 +281,7 @@ int rkkt_condense(rkkt_problem* p, const double* sigma_x, const double* sigma_u,
 }
 
 int rkkt_factor(rkkt_problem* p, double* khat, int* info_dev, hipStream_t stream) {
+  (void)hipGetLastError();  // do not report an earlier, unrelated error
   if (!p) return fail(nullptr, RKKT_ERR_ARG, "rkkt_factor: null handle");
   if (!khat || !info_dev) return fail(p, RKKT_ERR_ARG, "rkkt_factor: null array");
   stage(p, RKKT_STAGE_FACTOR, stream, [&] { rkkt::launch_cholesky(p->d, khat, info_dev, stream); });
@@ -285,6 +291,7 @@ int rkkt_factor(rkkt_problem* p, double* khat, int* info_dev, hipStream_t stream
 int rkkt_step(rkkt_problem* p, const double* r1x, const double* r1u, const double* r2,
               const double* r3, const double* r4, const double* sigma_s, const double* chol,
               double* px, double* pu, double* ps, double* py, double* pz, hipStream_t stream) {
+  (void)hipGetLastError();  // do not report an earlier, unrelated error
   if (!p) return fail(nullptr, RKKT_ERR_ARG, "rkkt_step: null handle");
   if (!r1x || !r1u || !r2 || !r3 || !r4 || !sigma_s || !chol || !px || !pu || !ps || !py || !pz)
     return fail(p, RKKT_ERR_ARG, "rkkt_step: null array");

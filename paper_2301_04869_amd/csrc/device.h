@@ -52,9 +52,9 @@ struct DP {
   int *status;     // [2]: code, scenario
 };
 
-// one-time kernel attributes (dynamic LDS limits); called by rkkt_create
-void configure_lu_kernels();
-void configure_dense_kernels();
+// dynamic LDS limits of the kernels for this problem's sizes; called by rkkt_create
+hipError_t configure_lu_kernels(const DP& d);
+hipError_t configure_dense_kernels(const DP& d);
 void launch_copy(const double* a, double* b, long long n, hipStream_t s);
 
 // launchers (k_eval.hip)

@@ -103,7 +103,13 @@ __global__ __launch_bounds__(kThreads) void k_chol_trsm(double* A, int n, int jb
   for (int p = 0; p < nb; ++p) row[p] = x[p];
 }
 
-// blocked: trailing update A[i, l] -= sum_p A[i, p] A[l, p], lower tiles only
+// blocked: trailing update A[i, l] -= sum_p A[i, p] A[l, p] over the lower
+// 64 x 64 tiles, on the FP64 matrix cores.  Each of the 4 waves owns a 32 x 32
+// quarter as 2 x 2 blocks of v_mfma_f64_16x16x4f64 (A operand: lane holds
+// row lane%16, k = lane/16; B operand: k = lane/16, column lane%16; result
+// register r of a lane: row lane/16 + 4 r, column lane%16).
+typedef double v4d __attribute__((ext_vector_type(4)));
+
 __global__ __launch_bounds__(kThreads) void k_chol_update(double* A, int n, int jb, const int* info) {
   if (*info != 0) return;
   const int nb = min(kNB, n - jb);
@@ -113,64 +119,89 @@ __global__ __launch_bounds__(kThreads) void k_chol_update(double* A, int n, int 
   const int i0 = s0 + ti * 64, l0 = s0 + tl * 64;
   __shared__ double sa[64][kNB + 1];
   __shared__ double sb[64][kNB + 1];
-  for (int t = threadIdx.x; t < 64 * nb; t += blockDim.x) {
-    const int r = t / nb, p = t % nb;
-    sa[r][p] = (i0 + r < n) ? A[(long long)(i0 + r) * n + jb + p] : 0.0;
-    sb[r][p] = (l0 + r < n) ? A[(long long)(l0 + r) * n + jb + p] : 0.0;
+  for (int t = threadIdx.x; t < 64 * kNB; t += blockDim.x) {
+    const int r = t / kNB, p = t % kNB;
+    const bool kin = p < nb;
+    sa[r][p] = (kin && i0 + r < n) ? A[(long long)(i0 + r) * n + jb + p] : 0.0;
+    sb[r][p] = (kin && l0 + r < n) ? A[(long long)(l0 + r) * n + jb + p] : 0.0;
   }
   __syncthreads();
-  // each thread: 4 x 4 outputs
-  const int tr = (threadIdx.x / 16) * 4, tc = (threadIdx.x % 16) * 4;
-  double acc[4][4] = {};
-  for (int p = 0; p < nb; ++p) {
-    double av[4], bv[4];
-    for (int q = 0; q < 4; ++q) { av[q] = sa[tr + q][p]; bv[q] = sb[tc + q][p]; }
-    for (int q = 0; q < 4; ++q)
-      for (int w = 0; w < 4; ++w) acc[q][w] += av[q] * bv[w];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int rb = (wv >> 1) * 32, cb = (wv & 1) * 32;   // wave's quarter
+  const int lm = lane & 15, lk = lane >> 4;
+  v4d acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < kNB; k0 += 4) {
+    const double a0 = sa[rb + lm][k0 + lk], a1 = sa[rb + 16 + lm][k0 + lk];
+    const double b0 = sb[cb + lm][k0 + lk], b1 = sb[cb + 16 + lm][k0 + lk];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
   }
-  for (int q = 0; q < 4; ++q)
-    for (int w = 0; w < 4; ++w) {
-      const int i = i0 + tr + q, l = l0 + tc + w;
-      if (i < n && l < n && l <= i) A[(long long)i * n + l] -= acc[q][w];
-    }
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + rb + 16 * a + lk + 4 * r, l = l0 + cb + 16 * b + lm;
+        if (i < n && l <= i) A[(long long)i * n + l] -= acc[a][b][r];
+      }
 }
 
-// p_u = K_hat^-1 rhs with rhs = -r1u + sum_i rpart_i (fixed scenario order)
-__global__ __launch_bounds__(1024) void k_reduced_solve(DP d, const double* r1u, const double* L,
-                                                        double* pu) {
+// p_u = K_hat^-1 rhs with rhs = -r1u + sum_i rpart_i (fixed scenario order).
+// One wavefront: lanes own rows, the forward and backward column sweeps need
+// only wavefront-scope ordering of LDS accesses (no workgroup barriers).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(64) void k_reduced_solve(DP d, const double* r1u, const double* L,
+                                                      double* pu) {
   extern __shared__ double y[];
-  const int n = d.nu;
-  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+  const int n = d.nu, lane = threadIdx.x;
+  for (int c = lane; c < n; c += 64) {
     double acc = -r1u[c];
     for (int k = 0; k < d.N; ++k) acc += d.rpart[(long long)k * n + c];
     y[c] = acc;
   }
-  __syncthreads();
-  // L y = rhs
+  wave_lds_sync();
+  // L y = rhs (column sweep)
   for (int j = 0; j < n; ++j) {
-    if (threadIdx.x == 0) y[j] /= L[(long long)j * n + j];
-    __syncthreads();
-    const double yj = y[j];
-    for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) y[i] -= L[(long long)i * n + j] * yj;
-    __syncthreads();
+    const double yj = y[j] / L[(long long)j * n + j];
+    wave_lds_sync();
+    if (lane == 0) y[j] = yj;
+    for (int i = j + 1 + lane; i < n; i += 64) y[i] -= L[(long long)i * n + j] * yj;
+    wave_lds_sync();
   }
-  // L^T p = y
+  // L^T p = y (column sweep of L^T = row sweep of L)
   for (int j = n - 1; j >= 0; --j) {
-    if (threadIdx.x == 0) y[j] /= L[(long long)j * n + j];
-    __syncthreads();
-    const double yj = y[j];
-    for (int i = threadIdx.x; i < j; i += blockDim.x) y[i] -= L[(long long)j * n + i] * yj;
-    __syncthreads();
+    const double yj = y[j] / L[(long long)j * n + j];
+    wave_lds_sync();
+    if (lane == 0) y[j] = yj;
+    for (int i = lane; i < j; i += 64) y[i] -= L[(long long)j * n + i] * yj;
+    wave_lds_sync();
   }
-  for (int c = threadIdx.x; c < n; c += blockDim.x) pu[c] = y[c];
+  for (int c = lane; c < n; c += 64) pu[c] = y[c];
 }
 
 }  // namespace
 
-void configure_dense_kernels() {
-  const int lds = 160 * 1024;
-  (void)hipFuncSetAttribute((const void*)k_chol_small, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  (void)hipFuncSetAttribute((const void*)k_reduced_solve, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+// raise the dynamic LDS limit of a kernel to what this problem needs (never lowered)
+static hipError_t allow_lds(const void* fn, int* cur, int need) {
+  if (need <= *cur) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, need);
+  if (e == hipSuccess) *cur = need;
+  return e;
+}
+
+hipError_t configure_dense_kernels(const DP& d) {
+  static int c1 = 0, c2 = 0;
+  hipError_t e = hipSuccess;
+  if (d.nu <= kSmallN) e = allow_lds((const void*)k_chol_small, &c1, 8 * d.nu * d.nu);
+  if (e == hipSuccess) e = allow_lds((const void*)k_reduced_solve, &c2, 8 * d.nu);
+  return e;
 }
 
 __global__ void k_copy(const double* a, double* b, long long n) {
@@ -209,7 +240,7 @@ void launch_cholesky(const DP& d, double* a, int* info, hipStream_t s) {
 void launch_reduced_solve(const DP& d, const double* r1u, const double* chol, double* pu,
                           hipStream_t s) {
   size_t lds = 8 * (size_t)d.nu;
-  k_reduced_solve<<<1, 1024, lds, s>>>(d, r1u, chol, pu);
+  k_reduced_solve<<<1, 64, lds, s>>>(d, r1u, chol, pu);
 }
 
 }  // namespace rkkt

@@ -395,10 +395,21 @@ __global__ __launch_bounds__(kThreads) void k_step_recover(DP d, const double* r
 
 }  // namespace
 
-void configure_lu_kernels() {
-  const int lds = 160 * 1024;
-  (void)hipFuncSetAttribute((const void*)k_refactor<true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  (void)hipFuncSetAttribute((const void*)k_reduce<true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+static hipError_t allow_lds(const void* fn, int* cur, int need) {
+  if (need <= *cur) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, need);
+  if (e == hipSuccess) *cur = need;
+  return e;
+}
+
+hipError_t configure_lu_kernels(const DP& d) {
+  static int c1 = 0, c2 = 0;
+  if (!d.lds) return hipSuccess;
+  const int lr = (int)(8 * ((size_t)d.nnz_f + 2 * (size_t)d.nx) + 4 * (size_t)kWaves * d.nx);
+  const int lc = (int)(8 * ((size_t)d.nnz_f + (size_t)d.nx + 2 * (size_t)d.nx * d.col_tile));
+  hipError_t e = allow_lds((const void*)k_refactor<true>, &c1, lr);
+  if (e == hipSuccess) e = allow_lds((const void*)k_reduce<true>, &c2, lc);
+  return e;
 }
 
 void launch_refactor(const DP& d, hipStream_t s) {

@@ -290,6 +290,7 @@ PRESETS = {
     "c1": (1, 118, 186, 54, 128, 99, 0.1, 1.0, 0),
     "c3": (3, 118, 186, 54, 1, 99, 0.15, 1.0, 0),
     "c4": (4, 9241, 16049, 1445, 16, "pq", 0.1, 0.15, 0),
+    "mid300": (92, 300, 450, 80, 4, "pq", 0.1, 1.0, 5),
     "tiny5": (90, 5, 6, 2, 2, "pq", 0.1, 1.0, 0),
     "tiny9": (91, 9, 12, 3, 3, "pq", 0.1, 1.0, 0),
 }

@@ -52,6 +52,8 @@ def test_c4_full_size_sampled():
     assert err.max() <= 1e-10
     rs = kkt.Resid(it["r1x"], it["r1u"], it["r2"], it["r3"], it["r4"])
     step = {k: np_(v) for k, v in run.out.items()}
-    r, s = kkt.augmented_residual(prob, ev, dg, rs, dw, step)
+    r, s, per = kkt.augmented_residual(prob, ev, dg, rs, dw, step, blocks=True)
     print(f"  step: augmented residual {r:.2e} relative {r / s:.2e}")
+    for k, (a, b) in per.items():
+        print(f"    block {k}: residual {a:.2e} scale {b:.2e} relative {a / b:.2e}")
     assert r <= 1e-10 * s

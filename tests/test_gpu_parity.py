@@ -23,7 +23,7 @@ def _need_gpu():
 
 
 CASES = [("tiny5", None, 0), ("tiny9", None, 0), ("c0", None, 0), ("c1", 8, 0),
-         ("c1", 8, 4), ("c1", 8, 64), ("c1", None, 0)]
+         ("c1", 8, 4), ("c1", 8, 64), ("c1", None, 0), ("mid300", None, 0)]
 
 
 def _ids(c):

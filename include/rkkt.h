@@ -118,6 +118,15 @@ int rkkt_create(const rkkt_network* net, int n_scen, const double* pd, const dou
 /* Host-only analysis: the sizes rkkt_create would produce, no device use. */
 int rkkt_analyze(const rkkt_network* net, int n_scen, const rkkt_options* opt, rkkt_dims* out);
 
+/*
+ * Host-only: the fill-reducing order and the filled LU pattern rkkt_create
+ * would use.  perm [n_x]: perm[i] is the external x index of internal row i;
+ * f_ptr [n_x+1], f_col [nnz_lu]: CSR of the filled pattern of P G_x P^T
+ * (sorted columns); sizes from rkkt_analyze.  The caller owns the buffers.
+ */
+int rkkt_analyze_lu(const rkkt_network* net, int n_scen, const rkkt_options* opt, int* perm,
+                    int* f_ptr, int* f_col);
+
 /* Replace the scenario loads with device arrays [N][n_load]. */
 int rkkt_set_loads(rkkt_problem* p, const double* pd_dev, const double* qd_dev, hipStream_t stream);
 
@@ -267,6 +276,32 @@ int rkkt_iterate(rkkt_problem* p, const rkkt_iteration* it, hipStream_t stream);
  */
 int rkkt_graph_capture(rkkt_problem* p, const rkkt_iteration* it);
 int rkkt_graph_launch(rkkt_problem* p, hipStream_t stream);
+
+/*
+ * Independent instances of uneven sizes in one launch: the passes of n
+ * handles (each with its own rkkt_iteration) are captured as n parallel
+ * branches of one HIP graph (fork from and join into one capture stream) and
+ * replayed with a single rkkt_batch_launch.  Each handle keeps its own
+ * reduced matrix (no sum across instances).  The batch does not own the
+ * handles; they must outlive it.  rkkt_batch_create allocates the graph and
+ * one capture stream per instance.
+ */
+typedef struct rkkt_batch rkkt_batch;
+
+/*
+ * Tile autotuner: builds one handle per candidate column tile (the automatic
+ * choice, then 4, 8, 16, 32, 64 up to n_u, each in the LDS or the global
+ * layout it implies), evaluates them at a fixed interior point (angles 0,
+ * magnitudes 1, outputs mid-range, multipliers 0, all IPM diagonals 1) and
+ * times `reps` condense calls with HIP events.  Writes the fastest tile and
+ * its mean time; allocates and frees device memory and synchronises.
+ */
+int rkkt_autotune(const rkkt_network* net, int n_scen, const double* pd, const double* qd,
+                  const rkkt_options* opt, int reps, int* best_col_tile, double* best_ms);
+int rkkt_batch_create(rkkt_problem* const* problems, const rkkt_iteration* its, int n,
+                      rkkt_batch** out);
+int rkkt_batch_launch(rkkt_batch* b, hipStream_t stream);
+int rkkt_batch_destroy(rkkt_batch* b);
 
 /*
  * Synchronise `stream`, read and clear the device status word:

@@ -24,7 +24,8 @@ ERRORS = {-1: "RKKT_ERR_ARG", -2: "RKKT_ERR_HIP", -3: "RKKT_ERR_SINGULAR_GX",
 EXPORTS = ("rkkt_create", "rkkt_analyze", "rkkt_set_loads", "rkkt_dims_get", "rkkt_evaluate",
            "rkkt_condense", "rkkt_factor", "rkkt_step", "rkkt_status", "rkkt_destroy",
            "rkkt_last_error", "rkkt_profile_begin", "rkkt_profile_end", "rkkt_solve",
-           "rkkt_iterate", "rkkt_graph_capture", "rkkt_graph_launch")
+           "rkkt_iterate", "rkkt_graph_capture", "rkkt_graph_launch", "rkkt_batch_create",
+           "rkkt_batch_launch", "rkkt_batch_destroy", "rkkt_autotune", "rkkt_analyze_lu")
 IPM_STATUS = {0: "converged", 1: "max_iter", 2: "line_search_failed",
               3: "inertia_correction_failed", 4: "device_error"}
 STAGES = ("evaluate", "condense_values", "refactor", "reduce", "scenario_sum", "factor",
@@ -121,6 +122,14 @@ def lib():
     L.rkkt_iterate.argtypes = [vp, ctypes.POINTER(Iteration), vp]
     L.rkkt_graph_capture.argtypes = [vp, ctypes.POINTER(Iteration)]
     L.rkkt_graph_launch.argtypes = [vp, vp]
+    L.rkkt_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Iteration), ctypes.c_int,
+                                    ctypes.POINTER(vp)]
+    L.rkkt_batch_launch.argtypes = [vp, vp]
+    L.rkkt_batch_destroy.argtypes = [vp]
+    L.rkkt_autotune.argtypes = [ctypes.POINTER(Network), ctypes.c_int, c_dbl_p, c_dbl_p,
+                                ctypes.POINTER(Options), ctypes.c_int, c_int_p, c_dbl_p]
+    L.rkkt_analyze_lu.argtypes = [ctypes.POINTER(Network), ctypes.c_int, ctypes.POINTER(Options),
+                                  c_int_p, c_int_p, c_int_p]
     L.rkkt_last_error.argtypes = [vp]
     L.rkkt_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -212,6 +221,32 @@ def rkkt_create(net, pd, qd, col_tile=0, device=0):
     d = Dims()
     _check(lib().rkkt_dims_get(h, ctypes.byref(d)), h)
     return Handle(h, d.as_dict())
+
+
+def rkkt_analyze_lu(net, n_scen, col_tile=0):
+    """Returns (perm, f_ptr, f_col) numpy int32 arrays of the filled LU pattern."""
+    d = rkkt_analyze(net, n_scen, col_tile)
+    s, keep = _host_network(net)
+    perm = np.zeros(d["n_x"], dtype=np.int32)
+    fp = np.zeros(d["n_x"] + 1, dtype=np.int32)
+    fc = np.zeros(d["nnz_lu"], dtype=np.int32)
+    _check(lib().rkkt_analyze_lu(ctypes.byref(s), int(n_scen), ctypes.byref(Options(col_tile, 0)),
+                                 perm.ctypes.data_as(c_int_p), fp.ctypes.data_as(c_int_p),
+                                 fc.ctypes.data_as(c_int_p)))
+    return perm, fp, fc
+
+
+def rkkt_autotune(net, pd, qd, reps=5, device=0):
+    """Returns (best column tile, mean condense milliseconds)."""
+    s, keep = _host_network(net)
+    pd = np.ascontiguousarray(pd, dtype=np.float64)
+    qd = np.ascontiguousarray(qd, dtype=np.float64)
+    w = ctypes.c_int()
+    ms = ctypes.c_double()
+    _check(lib().rkkt_autotune(ctypes.byref(s), pd.shape[0], pd.ctypes.data_as(c_dbl_p),
+                               qd.ctypes.data_as(c_dbl_p), ctypes.byref(Options(0, device)),
+                               int(reps), ctypes.byref(w), ctypes.byref(ms)))
+    return w.value, ms.value
 
 
 def rkkt_dims_get(p):
@@ -332,6 +367,38 @@ def rkkt_graph_capture(p, args):
 
 def rkkt_graph_launch(p, stream=None):
     _check(lib().rkkt_graph_launch(p.ptr, _stream(stream)), p.ptr)
+
+
+class Batch:
+    """An rkkt_batch* with the handles it captured (kept alive with it)."""
+
+    def __init__(self, ptr, handles):
+        self.ptr = ptr
+        self.handles = handles
+
+    def __del__(self):
+        if getattr(self, "ptr", None) and _lib is not None:
+            _lib.rkkt_batch_destroy(self.ptr)
+            self.ptr = None
+
+
+def rkkt_batch_create(handles, args_list):
+    n = len(handles)
+    arr = (ctypes.c_void_p * n)(*[h.ptr for h in handles])
+    its = (Iteration * n)(*[_iteration(h, a) for h, a in zip(handles, args_list)])
+    b = ctypes.c_void_p()
+    _check(lib().rkkt_batch_create(arr, its, n, ctypes.byref(b)))
+    return Batch(b, list(handles))
+
+
+def rkkt_batch_launch(b, stream=None):
+    _check(lib().rkkt_batch_launch(b.ptr, _stream(stream)))
+
+
+def rkkt_batch_destroy(b):
+    if b.ptr:
+        lib().rkkt_batch_destroy(b.ptr)
+        b.ptr = None
 
 
 def rkkt_destroy(p):

@@ -103,6 +103,18 @@ int rkkt_analyze(const rkkt_network* net, int n_scen, const rkkt_options* opt, r
   return RKKT_OK;
 }
 
+int rkkt_analyze_lu(const rkkt_network* net, int n_scen, const rkkt_options* opt, int* perm,
+                    int* f_ptr, int* f_col) {
+  if (!net || !perm || !f_ptr || !f_col) return fail(nullptr, RKKT_ERR_ARG, "rkkt_analyze_lu: null argument");
+  rkkt::Sym s;
+  std::string m = rkkt::build_symbolic(*net, n_scen, opt ? opt->col_tile : 0, s);
+  if (!m.empty()) return fail(nullptr, RKKT_ERR_ARG, "rkkt_analyze_lu: " + m);
+  std::memcpy(perm, s.perm.data(), s.perm.size() * sizeof(int));
+  std::memcpy(f_ptr, s.f_ptr.data(), s.f_ptr.size() * sizeof(int));
+  std::memcpy(f_col, s.f_col.data(), s.f_col.size() * sizeof(int));
+  return RKKT_OK;
+}
+
 int rkkt_create(const rkkt_network* net, int n_scen, const double* pd, const double* qd,
                 const rkkt_options* opt, rkkt_problem** out) {
   (void)hipGetLastError();
@@ -198,7 +210,7 @@ int rkkt_create(const rkkt_network* net, int n_scen, const double* pd, const dou
     if ((e = dalloc(p, &d.invd, N * s.nx)) != hipSuccess) goto hip_error;
     if ((e = dalloc(p, &d.part, N * s.nu * (size_t)s.nu)) != hipSuccess) goto hip_error;
     if ((e = dalloc(p, &d.panel, panel)) != hipSuccess) goto hip_error;
-    if ((e = dalloc(p, &d.imap, d.lds ? 1 : N * 4 * (size_t)s.nx)) != hipSuccess) goto hip_error;
+    if ((e = dalloc(p, &d.imap, d.lds ? 1 : N * 16 * (size_t)s.nx)) != hipSuccess) goto hip_error;
     if ((e = dalloc(p, &d.rhat1, N * s.nx)) != hipSuccess) goto hip_error;
     if ((e = dalloc(p, &d.rpart, N * s.nu)) != hipSuccess) goto hip_error;
     if ((e = dalloc(p, &d.status, 2)) != hipSuccess) goto hip_error;
@@ -370,6 +382,153 @@ int rkkt_graph_launch(rkkt_problem* p, hipStream_t stream) {
   if (!p || !p->gexec) return fail(p, RKKT_ERR_ARG, "rkkt_graph_launch: nothing captured");
   hipError_t e = hipGraphLaunch(p->gexec, stream);
   if (e != hipSuccess) return hip_fail(p, e, "rkkt_graph_launch");
+  return RKKT_OK;
+}
+
+struct rkkt_batch {
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> events;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+};
+
+int rkkt_batch_destroy(rkkt_batch* b) {
+  if (!b) return RKKT_OK;
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (hipEvent_t e : b->events) (void)hipEventDestroy(e);
+  for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
+  delete b;
+  return RKKT_OK;
+}
+
+int rkkt_batch_create(rkkt_problem* const* problems, const rkkt_iteration* its, int n,
+                      rkkt_batch** out) {
+  if (!problems || !its || !out || n < 1) return fail(nullptr, RKKT_ERR_ARG, "rkkt_batch_create: bad argument");
+  *out = nullptr;
+  for (int i = 0; i < n; ++i)
+    if (!problems[i]) return fail(nullptr, RKKT_ERR_ARG, "rkkt_batch_create: null handle");
+  (void)hipGetLastError();
+  rkkt_batch* b = new rkkt_batch();
+  hipError_t e = hipSuccess;
+  b->streams.resize(n + 1, nullptr);
+  b->events.resize(n + 1, nullptr);
+  for (int i = 0; i <= n && e == hipSuccess; ++i) {
+    e = hipStreamCreateWithFlags(&b->streams[i], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->events[i], hipEventDisableTiming);
+  }
+  if (e != hipSuccess) {
+    rkkt_batch_destroy(b);
+    return hip_fail(nullptr, e, "rkkt_batch_create: streams");
+  }
+  hipStream_t root = b->streams[n];
+  e = hipStreamBeginCapture(root, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) { rkkt_batch_destroy(b); return hip_fail(nullptr, e, "rkkt_batch_create: begin"); }
+  int rc = RKKT_OK;
+  e = hipEventRecord(b->events[n], root);
+  for (int i = 0; i < n && e == hipSuccess && rc == RKKT_OK; ++i) {
+    e = hipStreamWaitEvent(b->streams[i], b->events[n], 0);
+    if (e != hipSuccess) break;
+    const bool prof = problems[i]->prof;
+    problems[i]->prof = false;
+    rc = rkkt_iterate(problems[i], &its[i], b->streams[i]);
+    problems[i]->prof = prof;
+    if (rc != RKKT_OK) break;
+    e = hipEventRecord(b->events[i], b->streams[i]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(root, b->events[i], 0);
+  }
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(root, &g);
+  b->graph = g;
+  if (rc != RKKT_OK) {
+    std::string msg = problems[0]->err;
+    rkkt_batch_destroy(b);
+    return fail(nullptr, rc, "rkkt_batch_create: " + msg);
+  }
+  if (e == hipSuccess) e = e2;
+  if (e == hipSuccess) e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) { rkkt_batch_destroy(b); return hip_fail(nullptr, e, "rkkt_batch_create: capture"); }
+  *out = b;
+  return RKKT_OK;
+}
+
+int rkkt_autotune(const rkkt_network* net, int n_scen, const double* pd, const double* qd,
+                  const rkkt_options* opt, int reps, int* best_col_tile, double* best_ms) {
+  if (!net || !best_col_tile || !best_ms || reps < 1)
+    return fail(nullptr, RKKT_ERR_ARG, "rkkt_autotune: bad argument");
+  rkkt::Sym s0;
+  std::string m = rkkt::build_symbolic(*net, n_scen, 0, s0);
+  if (!m.empty()) return fail(nullptr, RKKT_ERR_ARG, "rkkt_autotune: " + m);
+  std::vector<int> cands = {s0.col_tile};
+  for (int w : {4, 8, 16, 32, 64})
+    if (w <= s0.nu && w != s0.col_tile) cands.push_back(w);
+  const int N = n_scen, nx = s0.nx, nu = s0.nu, mm = s0.m;
+  // fixed interior point (host), copied once
+  std::vector<double> hx((size_t)N * nx), hu(nu), hz((size_t)N * mm, 0.0), hy((size_t)N * nx, 0.0);
+  for (int k = 0; k < N; ++k)
+    for (int i = 0; i < nx; ++i) hx[(size_t)k * nx + i] = i < s0.nb - 1 ? 0.0 : 1.0;
+  for (int c = 0; c < nu; ++c) hu[c] = c < s0.ng ? 1.0 : 0.5 * (s0.ul[c] + s0.uu[c]);
+  std::vector<double> ones_x((size_t)N * nx, 1.0), ones_u(nu, 1.0), ones_s((size_t)N * mm, 1.0);
+  double* buf = nullptr;
+  const size_t nbuf = 3 * (size_t)N * nx + 2 * (size_t)N * mm + 2 * nu + (size_t)N * (1 + nx + nu + mm) +
+                      (size_t)N * nu + (size_t)nu * nu;
+  hipError_t e = hipMalloc((void**)&buf, nbuf * sizeof(double));
+  if (e != hipSuccess) return hip_fail(nullptr, e, "rkkt_autotune: buffers");
+  double* p = buf;
+  auto take = [&](size_t n) { double* q = p; p += n; return q; };
+  double *dx = take((size_t)N * nx), *dy = take((size_t)N * nx), *dsx = take((size_t)N * nx);
+  double *dz = take((size_t)N * mm), *dss = take((size_t)N * mm), *du = take(nu), *dsu = take(nu);
+  double *f = take(N), *gx = take((size_t)N * nx), *gu = take((size_t)N * nu), *g = take((size_t)N * nx);
+  double *h = take((size_t)N * mm), *kh = take((size_t)nu * nu);
+  auto up = [&](double* d, const std::vector<double>& v) {
+    return hipMemcpy(d, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice);
+  };
+  e = up(dx, hx);
+  if (e == hipSuccess) e = up(dy, hy);
+  if (e == hipSuccess) e = up(dz, hz);
+  if (e == hipSuccess) e = up(du, hu);
+  if (e == hipSuccess) e = up(dsx, ones_x);
+  if (e == hipSuccess) e = up(dss, ones_s);
+  if (e == hipSuccess) e = up(dsu, ones_u);
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if (e == hipSuccess) e = hipEventCreate(&t0);
+  if (e == hipSuccess) e = hipEventCreate(&t1);
+  int best = -1;
+  double bms = 1e300;
+  int rc = RKKT_OK;
+  for (size_t ci = 0; ci < cands.size() && e == hipSuccess && rc == RKKT_OK; ++ci) {
+    rkkt_options o = opt ? *opt : rkkt_options{0, 0};
+    o.col_tile = cands[ci];
+    rkkt_problem* q = nullptr;
+    rc = rkkt_create(net, n_scen, pd, qd, &o, &q);
+    if (rc != RKKT_OK) break;
+    rc = rkkt_evaluate(q, dx, du, dy, dz, 1.0 / N, f, gx, gu, g, h, nullptr);
+    if (rc == RKKT_OK) rc = rkkt_condense(q, dsx, dsu, dss, 1.0, kh, nullptr);
+    if (rc == RKKT_OK) e = hipEventRecord(t0, nullptr);
+    for (int r = 0; r < reps && rc == RKKT_OK && e == hipSuccess; ++r)
+      rc = rkkt_condense(q, dsx, dsu, dss, 1.0, kh, nullptr);
+    if (rc == RKKT_OK && e == hipSuccess) e = hipEventRecord(t1, nullptr);
+    if (rc == RKKT_OK && e == hipSuccess) e = hipEventSynchronize(t1);
+    float ms = 0.f;
+    if (rc == RKKT_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+    if (rc == RKKT_OK && e == hipSuccess && ms / reps < bms) { bms = ms / reps; best = cands[ci]; }
+    if (rc != RKKT_OK) g_err = q->err;
+    rkkt_destroy(q);
+  }
+  if (t0) (void)hipEventDestroy(t0);
+  if (t1) (void)hipEventDestroy(t1);
+  (void)hipFree(buf);
+  if (rc != RKKT_OK) return fail(nullptr, rc, "rkkt_autotune: " + g_err);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "rkkt_autotune");
+  *best_col_tile = best;
+  *best_ms = bms;
+  return RKKT_OK;
+}
+
+int rkkt_batch_launch(rkkt_batch* b, hipStream_t stream) {
+  if (!b || !b->gexec) return fail(nullptr, RKKT_ERR_ARG, "rkkt_batch_launch: no batch");
+  hipError_t e = hipGraphLaunch(b->gexec, stream);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "rkkt_batch_launch");
   return RKKT_OK;
 }
 

@@ -9,6 +9,7 @@
 #include <map>
 #include <numeric>
 #include <set>
+#include <tuple>
 #include <utility>
 
 namespace rkkt {
@@ -73,12 +74,13 @@ int find_pos(const std::vector<int>& ptr, const std::vector<int>& col, int row, 
 
 }  // namespace
 
-long long reduce_lds_bytes(const Sym& s, int w) {
-  return 8LL * ((long long)s.f_col.size() + 2LL * s.nx * w + s.nx);
-}
-
-long long refactor_lds_bytes(const Sym& s) {
-  return 8LL * ((long long)s.f_col.size() + 2LL * s.nx) + 4LL * 4 * s.nx;
+LdsSizes lds_sizes(const Sym& s, int w) {
+  LdsSizes z;
+  z.nx = s.nx; z.nu = s.nu; z.nz = s.nz;
+  z.nnz_f = (int)s.f_col.size(); z.nnz_k = (int)s.k_col.size(); z.nnz_gu = (int)s.gu_col.size();
+  z.nlu = (int)s.lvu_ptr.size() - 1; z.nld = (int)s.lvd_ptr.size() - 1;
+  z.w = w;
+  return z;
 }
 
 std::string build_symbolic(const rkkt_network& net, int N, int col_tile_req, Sym& s) {
@@ -247,6 +249,63 @@ std::string build_symbolic(const rkkt_network& net, int N, int col_tile_req, Sym
     {
       std::vector<int> cur(s.lvd_ptr.begin(), s.lvd_ptr.end() - 1);
       for (int i = 0; i < nx; ++i) s.lvd_rows[cur[lvl[i]]++] = i;
+    }
+  }
+
+  // ---- level-sliced pull structures
+  {
+    auto build = [&](bool up, std::vector<int>& lptr, std::vector<int>& desc, std::vector<int>& src,
+                     std::vector<int>& pos, std::vector<int>& tpos) {
+      const std::vector<int>& lv_ptr = up ? s.lvu_ptr : s.lvd_ptr;
+      const std::vector<int>& lv_rows = up ? s.lvu_rows : s.lvd_rows;
+      const int nlev = (int)lv_ptr.size() - 1;
+      // column lists: for every source j, the (dest i, position of (i, j))
+      std::vector<std::vector<std::pair<int, int>>> col(nx);
+      for (int i = 0; i < nx; ++i) {
+        const int e0 = up ? s.f_ptr[i] : s.f_diag[i] + 1;
+        const int e1 = up ? s.f_diag[i] : s.f_ptr[i + 1];
+        for (int e = e0; e < e1; ++e) col[s.f_col[e]].push_back({i, e});
+      }
+      lptr.assign(1, 0);
+      std::vector<std::tuple<int, int, int>> items;  // (dest, src, pos)
+      for (int q = 0; q < nlev; ++q) {
+        items.clear();
+        for (int r = lv_ptr[q]; r < lv_ptr[q + 1]; ++r) {
+          const int j = lv_rows[r];
+          for (auto& ip : col[j]) items.emplace_back(ip.first, j, ip.second);
+        }
+        std::sort(items.begin(), items.end());
+        size_t a = 0;
+        while (a < items.size()) {
+          size_t b = a;
+          while (b < items.size() && std::get<0>(items[b]) == std::get<0>(items[a])) ++b;
+          desc.push_back(std::get<0>(items[a]));
+          desc.push_back((int)src.size());
+          for (size_t t = a; t < b; ++t) {
+            src.push_back(std::get<1>(items[t]));
+            pos.push_back(std::get<2>(items[t]));
+            tpos.push_back(s.f_tpos[std::get<2>(items[t])]);
+          }
+          desc.push_back((int)src.size());
+          desc.push_back(0);
+          a = b;
+        }
+        lptr.push_back((int)desc.size() / 4);
+      }
+    };
+    build(true, s.up_lptr, s.up_desc, s.up_src, s.up_pos, s.up_tpos);
+    build(false, s.dn_lptr, s.dn_desc, s.dn_src, s.dn_pos, s.dn_tpos);
+    // refactorisation targets of every up entry
+    s.upd_ptr.assign(1, 0);
+    for (size_t e = 0; e < s.up_src.size(); ++e) {
+      const int k = s.up_src[e];
+      const int i = s.f_col[s.f_tpos[s.up_pos[e]]];  // column of (k, i) is i
+      for (int q = s.f_diag[k] + 1; q < s.f_ptr[k + 1]; ++q) {
+        const int t = find_pos(s.f_ptr, s.f_col, i, s.f_col[q]);
+        if (t < 0) return "internal: filled pattern not closed under elimination";
+        s.upd_dst.push_back(t);
+      }
+      s.upd_ptr.push_back((int)s.upd_dst.size());
     }
   }
 
@@ -481,17 +540,23 @@ std::string build_symbolic(const rkkt_network& net, int N, int col_tile_req, Sym
     }
   }
 
-  // column tile of the reduction
+  // column tile of the reduction: the fewest tiles whose workgroup fits in
+  // LDS (one workgroup per CU); global-memory panels of 64 columns otherwise
   const long long lds_max = 160 * 1024;
   if (col_tile_req > 0) {
     s.col_tile = col_tile_req;
   } else {
     s.col_tile = 0;
-    for (int w : {32, 16, 8, 4})
-      if (reduce_lds_bytes(s, w) <= 80 * 1024) { s.col_tile = w; break; }
+    for (int tiles = 1; tiles <= 64 && tiles <= nu; ++tiles) {
+      const int w = (nu + tiles - 1) / tiles;
+      if (w > 64) continue;
+      if (reduce_lds_bytes(lds_sizes(s, w)) <= lds_max) { s.col_tile = w; break; }
+    }
     if (s.col_tile == 0) s.col_tile = 64;
   }
-  s.lds_resident = reduce_lds_bytes(s, s.col_tile) <= lds_max && refactor_lds_bytes(s) <= lds_max;
+  const LdsSizes z = lds_sizes(s, s.col_tile);
+  s.lds_resident = reduce_lds_bytes(z) <= lds_max && refactor_lds_bytes(z) <= lds_max &&
+                   step_lds_bytes(z) <= lds_max;
   return "";
 }
 

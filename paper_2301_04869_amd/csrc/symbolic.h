@@ -69,17 +69,29 @@ struct Sym {
 
   // filled LU pattern of P G_x P^T (internal order), CSR with sorted columns
   std::vector<int> f_ptr, f_col, f_diag, f_tpos;
-  std::vector<int> upd_ptr, upd_src, upd_dst;  // per F position (L part): updates of row i by row k
   std::vector<int> gx2f;                       // F position of every G_x entry
   std::vector<int> lvu_ptr, lvu_rows, lvd_ptr, lvd_rows;
   long long lu_flops = 0;
+
+  // Level-sliced pulls.  Direction "up" (L and U^T solves, the refactorisation):
+  // when the rows of up-level q are final, every row i with an L entry (i, j),
+  // j in level q, pulls those entries.  Direction "down" (U and L^T solves):
+  // rows j of down-level q are pulled by every row i < j with a U entry (i, j).
+  // Per direction: lptr[nlev+1] -> descriptors; desc[4 d .. 4 d+3] =
+  // (dest row, first entry, end entry, 0); per entry: src row, position of
+  // (dest, src) in F and of (src, dest) in F.
+  std::vector<int> up_lptr, up_desc, up_src, up_pos, up_tpos;
+  std::vector<int> dn_lptr, dn_desc, dn_src, dn_pos, dn_tpos;
+  // refactorisation updates of every up entry e = (i, k): the targets in row i
+  // of the U part of row k, in order: upd_dst[upd_ptr[e] + t] is the position
+  // of (i, j_t), j_t the t-th U column of row k
+  std::vector<int> upd_ptr, upd_dst;
 };
 
 // Returns an empty string on success, else the error message.
 std::string build_symbolic(const rkkt_network& net, int n_scen, int col_tile_req, Sym& s);
 
-// LDS bytes of the reduction workgroup for a tile width.
-long long reduce_lds_bytes(const Sym& s, int w);
-long long refactor_lds_bytes(const Sym& s);
+// sizes fixing the LDS layouts, for a tile width
+LdsSizes lds_sizes(const Sym& s, int w);
 
 }  // namespace rkkt

@@ -331,3 +331,18 @@ def preset(name: str, attempt: int | None = None, n_scen: int | None = None,
         inst.scen = make_scenarios(inst.net, inst.scen.n_scen, inst.scen.sigma,
                                    3000 + attempt + 1)
     return inst
+
+
+def batch_instances(n: int = 64, seed: int = 2000, lo: int = 300, hi: int = 2000,
+                    sigma: float = 0.1) -> list:
+    """Independent single-scenario instances of uneven sizes: n_bus
+    log-uniform in [lo, hi], n_line = round(1.5 n_bus), n_gen = round(0.15 n_bus),
+    the parameter distributions of make_network."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        nb = int(round(np.exp(rng.uniform(np.log(lo), np.log(hi)))))
+        inst = make_instance(nb, int(round(1.5 * nb)), max(2, int(round(0.15 * nb))), 1,
+                             seed * 1000 + i, loads="pq", sigma=sigma, name=f"batch{i}")
+        out.append(inst)
+    return out

@@ -1,0 +1,69 @@
+"""Independent instances of uneven sizes in one graph launch: every
+instance's reduced matrix and step from the batch equal its own eager pass
+bit for bit and match the oracle; the tile autotuner returns a usable tile."""
+import numpy as np
+import pytest
+
+import gpu_common as gc
+import synthgrid as sg
+from synthgrid.iterates import random_iterate
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _args(run):
+    i, o = run.inp, run.out
+    return dict(x=i["x"], u=i["u"], y=i["y"], z=i["z"], obj_weight=run.w, f=run.f, grad_x=run.gx,
+                grad_u=run.gu, g=run.g, h=run.h, sigma_x=i["sigma_x"], sigma_u=i["sigma_u"],
+                sigma_s=i["sigma_s"], delta_w=run.delta_w, khat=run.khat, chol=run.chol,
+                info=run.info, r1x=i["r1x"], r1u=i["r1u"], r2=i["r2"], r3=i["r3"], r4=i["r4"],
+                px=o["px"], pu=o["pu"], ps=o["ps"], py=o["py"], pz=o["pz"])
+
+
+def test_batch_graph_matches_eager_and_oracle():
+    import paper_2301_04869_amd as R
+    insts = sg.batch_instances(5, seed=77, lo=40, hi=400)
+    runs, refs, orcs = [], [], []
+    for j, inst in enumerate(insts):
+        it = random_iterate(inst.net, 1, 500 + j)
+        prob, ev, dg, red, dw = gc.oracle_state(inst, it)
+        run = gc.GpuRun(inst, it, dw, torch)
+        run.chol = torch.zeros_like(run.khat)
+        R.rkkt_iterate(run.p, _args(run))
+        torch.cuda.synchronize()
+        refs.append({k: v.clone() for k, v in list(run.out.items()) + [("khat", run.khat)]})
+        orcs.append(red.khat)
+        runs.append(run)
+        print(f"\ninstance {j}: n_bus={inst.net.n_bus} n_u={prob.n_u} tile={run.p.dims['col_tile']}")
+    b = R.rkkt_batch_create([r.p for r in runs], [_args(r) for r in runs])
+    for rep in range(3):
+        for r in runs:
+            for v in list(r.out.values()) + [r.khat]:
+                v.fill_(float("nan"))
+        torch.cuda.synchronize()
+        R.rkkt_batch_launch(b)
+        torch.cuda.synchronize()
+        for r, ref, orc in zip(runs, refs, orcs):
+            for k, v in r.out.items():
+                assert torch.equal(v, ref[k]), (rep, k)
+            assert torch.equal(r.khat, ref["khat"])
+            assert gc.rel_fro(r.khat.cpu().numpy(), orc) <= 1e-10
+    del b
+
+
+def test_autotune_returns_a_working_tile():
+    import paper_2301_04869_amd as R
+    inst = sg.batch_instances(1, seed=78, lo=300, hi=400)[0]
+    w, ms = R.rkkt_autotune(inst.net, inst.scen.pd.T, inst.scen.qd.T, reps=2)
+    print(f"\nautotune: tile {w}, {ms:.3f} ms per condense")
+    assert w in (4, 8, 16, 32, 64) or w == R.rkkt_analyze(inst.net, 1)["col_tile"]
+    assert ms > 0
+    p = R.rkkt_create(inst.net, inst.scen.pd.T, inst.scen.qd.T, col_tile=w)
+    assert p.dims["col_tile"] == w

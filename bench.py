@@ -52,10 +52,10 @@ def batch_main(args):
     zf = lambda *s: torch.zeros(*s, dtype=torch.float64, device="cuda")  # noqa: E731
     keep = []
     for j, inst in enumerate(insts):
-        w, tms = R.rkkt_autotune(inst.net, inst.scen.pd.T, inst.scen.qd.T, reps=2)
-        tiles.append(w)
+        best, tms = R.rkkt_autotune(inst.net, inst.scen.pd.T, inst.scen.qd.T, reps=2)
+        tiles.append(best)
         tune_ms.append(tms)
-        p = R.rkkt_create(inst.net, inst.scen.pd.T, inst.scen.qd.T, col_tile=w)
+        p = R.rkkt_create(inst.net, inst.scen.pd.T, inst.scen.qd.T, **best)
         d = p.dims
         nx, nu, m = d["n_x"], d["n_u"], d["m"]
         it = random_iterate(inst.net, 1, 9000 + j)
@@ -104,7 +104,7 @@ def batch_main(args):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic",
            "config": {"workload": WORKLOADS["c2"], "n_bus": [i.net.n_bus for i in insts],
-                      "col_tiles": tiles, "autotune_condense_ms": tune_ms},
+                      "shapes": tiles, "autotune_condense_ms": tune_ms},
            "sequential_ms_per_step": seq_ms, "speedup_vs_sequential": seq_ms / bat_ms,
            "batch_equals_sequential": same}
     print(json.dumps(out), flush=True)
@@ -126,8 +126,16 @@ def stage_work(d):
                      + 8 * N * (1 + 2 * nx + m + nu) + 8 * N * (nev + nk))
     w["condense_values"] = (N * 3 * ntrip, 8 * N * (nk + nh + m + nx + nk) + 4 * 3 * ntrip)
     w["refactor"] = (N * 2 * d["lu_update_flops"], 8 * N * (ngx + nlu + nx) + 4 * 3 * nlu)
-    w["reduce"] = (N * nu * (4 * nlu + 2 * nkx + 2 * ngu),
-                   8 * N * (nlu + nx + nk + ngu + nu * nu) + 4 * (3 * nlu + 2 * nk))
+    nz = nx + nu
+    if d["variant"] == 2:
+        # forward solves and K products; Z and K Z written once
+        w["reduce"] = (N * nu * (2 * nlu + 2 * nkx),
+                       8 * N * (nlu + nx + nk + ngu + 2 * nz * nu) + 4 * (3 * nlu + 2 * nk))
+        # lower triangle of Z^T (K Z): Z and K Z read once, partials written
+        w["stacked_product"] = (N * nz * nu * (nu + 1), 8 * 2 * N * nz * nu + 8 * nu * nu)
+    else:
+        w["reduce"] = (N * nu * (4 * nlu + 2 * nkx + 2 * ngu),
+                       8 * N * (nlu + nx + nk + ngu + nu * nu) + 4 * (3 * nlu + 2 * nk))
     w["scenario_sum"] = (N * nu * nu, 8 * (N + 1) * nu * nu + 8 * nu)
     w["factor"] = (nu ** 3 / 3.0, 8 * 2 * nu * nu)
     w["step_rhs"] = (N * (8 * nlu + 4 * nkx + 4 * nh), 8 * N * (nlu + nk + nh + 2 * nx + 3 * m + nu))
@@ -211,6 +219,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="c1", choices=sorted(WORKLOADS))
     ap.add_argument("--col-tile", type=int, default=0)
+    ap.add_argument("--variant", type=int, default=0, choices=(0, 1, 2),
+                    help="reduction: 1 adjoint solves, 2 stacked product, 0 automatic")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--seed", type=int, default=2024)
@@ -244,7 +254,8 @@ def main():
     inst = sg.preset(args.config)
     net, N = inst.net, inst.scen.n_scen
     it = random_iterate(net, N, args.seed)
-    p = R.rkkt_create(net, inst.scen.pd.T, inst.scen.qd.T, col_tile=args.col_tile)
+    p = R.rkkt_create(net, inst.scen.pd.T, inst.scen.qd.T, col_tile=args.col_tile,
+                      variant=args.variant)
     d = p.dims
     nx, nu, m = d["n_x"], d["n_u"], d["m"]
     t = {k: torch.tensor(np.ascontiguousarray(v), dtype=torch.float64, device="cuda")
@@ -304,8 +315,8 @@ def main():
     graph_ms = e0.elapsed_time(e1) / args.steps
     ms = min(graph_ms, eager_ms)
     value = N / (ms * 1e-3)
-    cf_ms = sum(stages[s][0] for s in ("condense_values", "refactor", "reduce", "scenario_sum",
-                                       "factor")) / args.steps
+    cf_ms = sum(stages[s][0] for s in ("condense_values", "refactor", "reduce", "stacked_product",
+                                       "scenario_sum", "factor")) / args.steps
     dom = max((s for s in stages if stages[s][1] > 0), key=lambda s: stages[s][0])
     roof = roofline_entry(dom, stages[dom][0], stages[dom][1], d)
 
@@ -315,7 +326,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": WORKLOADS[args.config], "n_scen": N, "n_x": nx, "n_u": nu, "m": m,
-                   "nnz_lu": d["nnz_lu"], "col_tile": d["col_tile"], "delta_w": dw,
+                   "nnz_lu": d["nnz_lu"], "col_tile": d["col_tile"], "variant": d["variant"],
+                   "lds_reduce": d["lds_reduce"], "lds_group": d["lds_group"], "delta_w": dw,
                    "seed": args.seed},
         "graph_ms_per_step": graph_ms, "eager_ms_per_step": eager_ms,
         "condense_factor_value": N / (cf_ms * 1e-3),
@@ -326,7 +338,7 @@ def main():
     if not args.no_plain:
         # the same kernels, one scenario per handle and per launch, no batching
         handles = [R.rkkt_create(net, inst.scen.pd[:, k:k + 1].T, inst.scen.qd[:, k:k + 1].T,
-                                 col_tile=args.col_tile) for k in range(N)]
+                                 col_tile=args.col_tile, variant=args.variant) for k in range(N)]
         tk = [{n: t[n][k:k + 1].contiguous() for n in ("x", "y", "z", "sigma_x", "sigma_s")}
               for k in range(N)]
         su0 = zf(nu)

@@ -84,9 +84,17 @@ typedef struct {
 } rkkt_network;
 
 typedef struct {
-  int col_tile;   /* right-hand-side columns per workgroup in the reduction;
-                     0 picks one from the sizes                               */
+  int col_tile;   /* right-hand-side columns per workgroup in the reduction,
+                     1..64; 0 picks one from the sizes                        */
   int device;     /* HIP device ordinal                                        */
+  int variant;    /* how the reduction is closed (both give the same khat in
+                     exact arithmetic):
+                     1 adjoint: khat_i V = L_u - G_u^T G_x^-T L_x, two more
+                       sparse triangular solves per column (the paper's form);
+                     2 stacked product: khat = sum_i Z_i^T (K_i Z_i) as one
+                       dense FP64 matrix-core product over the stacked rows of
+                       all scenarios;
+                     0 picks 2 when the reduction's data fits on chip, else 1 */
 } rkkt_options;
 
 typedef struct {
@@ -99,6 +107,11 @@ typedef struct {
   int levels_up, levels_down;       /* level-schedule depths of the LU solves   */
   int col_tile;                     /* chosen column tile                       */
   long long workspace_bytes;        /* device bytes owned by the handle         */
+  int variant;                      /* chosen reduction variant (1 or 2)         */
+  int lds_reduce;                   /* reduction panels and factors in LDS       */
+  int lds_group;                    /* refactorisation data in LDS               */
+  int scen_per_group;               /* scenarios per workgroup of that kernel    */
+  int lds_step;                     /* step data in LDS                          */
 } rkkt_dims;
 
 /*
@@ -243,6 +256,7 @@ enum {
   RKKT_STAGE_STEP_RHS,            /* reduced right-hand side contributions      */
   RKKT_STAGE_REDUCED_SOLVE,       /* p_u                                        */
   RKKT_STAGE_STEP_RECOVER,        /* p_x, p_y, p_s, p_z                         */
+  RKKT_STAGE_STACKED_PRODUCT,     /* Z^T (K Z) over all scenarios (variant 2)   */
   RKKT_NSTAGES
 };
 int rkkt_profile_begin(rkkt_problem* p, int max_records);
@@ -289,15 +303,17 @@ int rkkt_graph_launch(rkkt_problem* p, hipStream_t stream);
 typedef struct rkkt_batch rkkt_batch;
 
 /*
- * Tile autotuner: builds one handle per candidate column tile (the automatic
- * choice, then 4, 8, 16, 32, 64 up to n_u, each in the LDS or the global
- * layout it implies), evaluates them at a fixed interior point (angles 0,
- * magnitudes 1, outputs mid-range, multipliers 0, all IPM diagonals 1) and
- * times `reps` condense calls with HIP events.  Writes the fastest tile and
- * its mean time; allocates and frees device memory and synchronises.
+ * Autotuner of the reduction's launch shape: builds one handle per candidate
+ * (reduction variant 1 and 2, each with the automatic column tile and with
+ * 8, 16, 32, 64 up to n_u, each in the LDS or global layout it implies;
+ * variant 2 only while its stacked panels stay under 4 GiB), evaluates them
+ * at a fixed interior point (angles 0, magnitudes 1, outputs mid-range,
+ * multipliers 0, all IPM diagonals 1) and times `reps` condense calls with
+ * HIP events.  Writes the fastest choice into *best (device copied from opt)
+ * and its mean time; allocates and frees device memory and synchronises.
  */
 int rkkt_autotune(const rkkt_network* net, int n_scen, const double* pd, const double* qd,
-                  const rkkt_options* opt, int reps, int* best_col_tile, double* best_ms);
+                  const rkkt_options* opt, int reps, rkkt_options* best, double* best_ms);
 int rkkt_batch_create(rkkt_problem* const* problems, const rkkt_iteration* its, int n,
                       rkkt_batch** out);
 int rkkt_batch_launch(rkkt_batch* b, hipStream_t stream);

@@ -29,7 +29,7 @@ EXPORTS = ("rkkt_create", "rkkt_analyze", "rkkt_set_loads", "rkkt_dims_get", "rk
 IPM_STATUS = {0: "converged", 1: "max_iter", 2: "line_search_failed",
               3: "inertia_correction_failed", 4: "device_error"}
 STAGES = ("evaluate", "condense_values", "refactor", "reduce", "scenario_sum", "factor",
-          "step_rhs", "reduced_solve", "step_recover")
+          "step_rhs", "reduced_solve", "step_recover", "stacked_product")
 
 
 class RkktError(RuntimeError):
@@ -50,7 +50,7 @@ class Network(ctypes.Structure):
 
 
 class Options(ctypes.Structure):
-    _fields_ = [("col_tile", ctypes.c_int), ("device", ctypes.c_int)]
+    _fields_ = [("col_tile", ctypes.c_int), ("device", ctypes.c_int), ("variant", ctypes.c_int)]
 
 
 class Dims(ctypes.Structure):
@@ -63,7 +63,10 @@ class Dims(ctypes.Structure):
                 ("nnz_kx", ctypes.c_longlong), ("n_ev", ctypes.c_longlong),
                 ("n_trip", ctypes.c_longlong),
                 ("levels_up", ctypes.c_int), ("levels_down", ctypes.c_int),
-                ("col_tile", ctypes.c_int), ("workspace_bytes", ctypes.c_longlong)]
+                ("col_tile", ctypes.c_int), ("workspace_bytes", ctypes.c_longlong),
+                ("variant", ctypes.c_int), ("lds_reduce", ctypes.c_int),
+                ("lds_group", ctypes.c_int), ("scen_per_group", ctypes.c_int),
+                ("lds_step", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -127,7 +130,8 @@ def lib():
     L.rkkt_batch_launch.argtypes = [vp, vp]
     L.rkkt_batch_destroy.argtypes = [vp]
     L.rkkt_autotune.argtypes = [ctypes.POINTER(Network), ctypes.c_int, c_dbl_p, c_dbl_p,
-                                ctypes.POINTER(Options), ctypes.c_int, c_int_p, c_dbl_p]
+                                ctypes.POINTER(Options), ctypes.c_int, ctypes.POINTER(Options),
+                                c_dbl_p]
     L.rkkt_analyze_lu.argtypes = [ctypes.POINTER(Network), ctypes.c_int, ctypes.POINTER(Options),
                                   c_int_p, c_int_p, c_int_p]
     L.rkkt_last_error.argtypes = [vp]
@@ -199,15 +203,15 @@ class Handle:
             self.ptr = None
 
 
-def rkkt_analyze(net, n_scen, col_tile=0):
+def rkkt_analyze(net, n_scen, col_tile=0, variant=0):
     s, keep = _host_network(net)
     d = Dims()
-    _check(lib().rkkt_analyze(ctypes.byref(s), int(n_scen), ctypes.byref(Options(col_tile, 0)),
-                              ctypes.byref(d)))
+    _check(lib().rkkt_analyze(ctypes.byref(s), int(n_scen),
+                              ctypes.byref(Options(col_tile, 0, variant)), ctypes.byref(d)))
     return d.as_dict()
 
 
-def rkkt_create(net, pd, qd, col_tile=0, device=0):
+def rkkt_create(net, pd, qd, col_tile=0, device=0, variant=0):
     """pd, qd: host [N][n_load] arrays (scenario-major)."""
     s, keep = _host_network(net)
     pd = np.ascontiguousarray(pd, dtype=np.float64)
@@ -216,7 +220,8 @@ def rkkt_create(net, pd, qd, col_tile=0, device=0):
         raise ValueError("pd, qd must be [N][n_load]")
     h = ctypes.c_void_p()
     _check(lib().rkkt_create(ctypes.byref(s), pd.shape[0], pd.ctypes.data_as(c_dbl_p),
-                             qd.ctypes.data_as(c_dbl_p), ctypes.byref(Options(col_tile, device)),
+                             qd.ctypes.data_as(c_dbl_p),
+                             ctypes.byref(Options(col_tile, device, variant)),
                              ctypes.byref(h)))
     d = Dims()
     _check(lib().rkkt_dims_get(h, ctypes.byref(d)), h)
@@ -237,16 +242,16 @@ def rkkt_analyze_lu(net, n_scen, col_tile=0):
 
 
 def rkkt_autotune(net, pd, qd, reps=5, device=0):
-    """Returns (best column tile, mean condense milliseconds)."""
+    """Returns ({"col_tile", "variant"} of the fastest shape, mean condense ms)."""
     s, keep = _host_network(net)
     pd = np.ascontiguousarray(pd, dtype=np.float64)
     qd = np.ascontiguousarray(qd, dtype=np.float64)
-    w = ctypes.c_int()
+    best = Options()
     ms = ctypes.c_double()
     _check(lib().rkkt_autotune(ctypes.byref(s), pd.shape[0], pd.ctypes.data_as(c_dbl_p),
-                               qd.ctypes.data_as(c_dbl_p), ctypes.byref(Options(0, device)),
-                               int(reps), ctypes.byref(w), ctypes.byref(ms)))
-    return w.value, ms.value
+                               qd.ctypes.data_as(c_dbl_p), ctypes.byref(Options(0, device, 0)),
+                               int(reps), ctypes.byref(best), ctypes.byref(ms)))
+    return {"col_tile": best.col_tile, "variant": best.variant}, ms.value
 
 
 def rkkt_dims_get(p):

@@ -3,6 +3,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -68,6 +69,34 @@ void fill_dims(const rkkt::Sym& s, rkkt_dims* o, long long bytes) {
   o->levels_down = (int)s.lvd_ptr.size() - 1;
   o->col_tile = s.col_tile;
   o->workspace_bytes = bytes;
+  o->variant = s.variant;
+  o->lds_reduce = s.lds_reduce ? 1 : 0;
+  o->lds_group = s.lds_group ? 1 : 0;
+  o->lds_step = s.lds_step ? 1 : 0;
+  o->scen_per_group = s.spw;
+}
+
+// Appends the entries of a level-sliced schedule packed as two words of
+// 16-bit pairs (the form the LDS kernels stage).
+void pack_entries(const rkkt::Sched& sc, std::vector<unsigned>& out) {
+  const size_t n = sc.ent.size() / 4;
+  for (size_t q = 0; q < n; ++q) {
+    out.push_back((unsigned)sc.ent[4 * q] | ((unsigned)sc.ent[4 * q + 1] << 16));
+    out.push_back((unsigned)sc.ent[4 * q + 2] | ((unsigned)sc.ent[4 * q + 3] << 16));
+  }
+}
+
+// Uploads a level-sliced schedule for global-memory kernels: the pointer
+// table and the entries as int4.
+hipError_t upload_sched(rkkt_problem* p, const rkkt::Sched& sc, bool packed, const int** ptr,
+                        const void** ent) {
+  (void)packed;
+  hipError_t e = upload(p, ptr, sc.ptr);
+  if (e != hipSuccess) return e;
+  const int* d = nullptr;
+  e = upload(p, &d, sc.ent);
+  *ent = d;
+  return e;
 }
 
 // Runs `launch` between two events on `stream` when profiling is on.
@@ -97,7 +126,7 @@ extern "C" {
 int rkkt_analyze(const rkkt_network* net, int n_scen, const rkkt_options* opt, rkkt_dims* out) {
   if (!net || !out) return fail(nullptr, RKKT_ERR_ARG, "rkkt_analyze: null argument");
   rkkt::Sym s;
-  std::string m = rkkt::build_symbolic(*net, n_scen, opt ? opt->col_tile : 0, s);
+  std::string m = rkkt::build_symbolic(*net, n_scen, opt ? opt->col_tile : 0, opt ? opt->variant : 0, s);
   if (!m.empty()) return fail(nullptr, RKKT_ERR_ARG, "rkkt_analyze: " + m);
   fill_dims(s, out, 0);
   return RKKT_OK;
@@ -107,7 +136,7 @@ int rkkt_analyze_lu(const rkkt_network* net, int n_scen, const rkkt_options* opt
                     int* f_ptr, int* f_col) {
   if (!net || !perm || !f_ptr || !f_col) return fail(nullptr, RKKT_ERR_ARG, "rkkt_analyze_lu: null argument");
   rkkt::Sym s;
-  std::string m = rkkt::build_symbolic(*net, n_scen, opt ? opt->col_tile : 0, s);
+  std::string m = rkkt::build_symbolic(*net, n_scen, opt ? opt->col_tile : 0, opt ? opt->variant : 0, s);
   if (!m.empty()) return fail(nullptr, RKKT_ERR_ARG, "rkkt_analyze_lu: " + m);
   std::memcpy(perm, s.perm.data(), s.perm.size() * sizeof(int));
   std::memcpy(f_ptr, s.f_ptr.data(), s.f_ptr.size() * sizeof(int));
@@ -123,7 +152,7 @@ int rkkt_create(const rkkt_network* net, int n_scen, const double* pd, const dou
   if (net->n_load > 0 && (!pd || !qd)) return fail(nullptr, RKKT_ERR_ARG, "rkkt_create: null loads");
   rkkt_problem* p = new rkkt_problem();
   p->device = opt ? opt->device : 0;
-  std::string m = rkkt::build_symbolic(*net, n_scen, opt ? opt->col_tile : 0, p->sym);
+  std::string m = rkkt::build_symbolic(*net, n_scen, opt ? opt->col_tile : 0, opt ? opt->variant : 0, p->sym);
   if (!m.empty()) {
     delete p;
     return fail(nullptr, RKKT_ERR_ARG, "rkkt_create: " + m);
@@ -143,10 +172,22 @@ int rkkt_create(const rkkt_network* net, int n_scen, const double* pd, const dou
   d.off_gu = s.off_gu; d.off_h = s.off_h;
   d.nnz_gx = (int)s.gx_col.size(); d.nnz_gu = (int)s.gu_col.size();
   d.nnz_h = (int)s.h_col.size(); d.nnz_k = (int)s.k_col.size(); d.nnz_f = (int)s.f_col.size();
+  d.nnz_l = s.nnz_l;
   d.nlev_up = (int)s.lvu_ptr.size() - 1;
   d.nlev_dn = (int)s.lvd_ptr.size() - 1;
+  d.nph_u = s.red_up.nphase;
+  d.nph_d = s.red_dn.nphase;
+  d.n_upd = (int)s.upd_dst.size();
+  d.lu_stride = d.nnz_f + s.nx;
   d.col_tile = s.col_tile;
-  d.lds = s.lds_resident ? 1 : 0;
+  d.lds_red = s.lds_reduce ? 1 : 0;
+  d.lds_grp = s.lds_group ? 1 : 0;
+  d.lds_stp = s.lds_step ? 1 : 0;
+  d.spw = s.spw;
+  d.upd_lds = s.upd_lds ? 1 : 0;
+  d.variant = s.variant;
+  d.nu_pad = s.nu_pad;
+  d.nchunk = s.nchunk;
   // per-unit line and cost data
   std::vector<double> gs(s.nl), bs(s.nl), bc(s.nl), ca(s.ng), cb(s.ng), cc(s.ng);
   for (int l = 0; l < s.nl; ++l) {
@@ -193,12 +234,55 @@ int rkkt_create(const rkkt_network* net, int n_scen, const double* pd, const dou
   UP(t_ptr, s.t_ptr) UP(t_row, s.t_row) UP(t_a, s.t_a) UP(t_b, s.t_b)
   UP(f_ptr, s.f_ptr) UP(f_col, s.f_col) UP(f_diag, s.f_diag) UP(f_tpos, s.f_tpos) UP(gx2f, s.gx2f)
   UP(lvu_ptr, s.lvu_ptr) UP(lvu_rows, s.lvu_rows) UP(lvd_ptr, s.lvd_ptr) UP(lvd_rows, s.lvd_rows)
+  UP(upd_dst, s.upd_dst)
 #undef UP
+  // schedules: LDS images (packed entries and every index array the kernel
+  // stages, in its LDS order) for the LDS kernels, int4 entries otherwise
+  if (s.lds_reduce && s.col_tile != 64) {
+    std::vector<unsigned> b;
+    pack_entries(s.red_up, b);
+    pack_entries(s.red_dn, b);
+    for (const std::vector<int>* v : {&s.red_up.ptr, &s.red_dn.ptr, &s.k_ptr, &s.k_usplit, &s.k_col,
+                                      &s.guc_ptr, &s.guc_row})
+      b.insert(b.end(), v->begin(), v->end());
+    if (b.size() % 2) b.push_back(0);  // whole 8-byte units
+    d.blob_red_words = (int)b.size();
+    if ((e = upload(p, &d.blob_red, b)) != hipSuccess) goto hip_error;
+  } else {
+    if ((e = upload_sched(p, s.red_up, false, &d.ru_ptr, &d.ru_ent)) != hipSuccess) goto hip_error;
+    if ((e = upload_sched(p, s.red_dn, false, &d.rd_ptr, &d.rd_ent)) != hipSuccess) goto hip_error;
+  }
+  if (s.lds_step) {
+    std::vector<unsigned> b;
+    pack_entries(s.stp_up, b);
+    pack_entries(s.stp_dn, b);
+    b.insert(b.end(), s.stp_up.ptr.begin(), s.stp_up.ptr.end());
+    b.insert(b.end(), s.stp_dn.ptr.begin(), s.stp_dn.ptr.end());
+    if (b.size() % 2) b.push_back(0);
+    d.blob_stp_words = (int)b.size();
+    if ((e = upload(p, &d.blob_stp, b)) != hipSuccess) goto hip_error;
+  } else {
+    if ((e = upload_sched(p, s.stp_up, false, &d.su_ptr, &d.su_ent)) != hipSuccess) goto hip_error;
+    if ((e = upload_sched(p, s.stp_dn, false, &d.sd_ptr, &d.sd_ent)) != hipSuccess) goto hip_error;
+  }
+  if (s.lds_group) {
+    std::vector<unsigned> f;
+    pack_entries(s.fac, f);
+    for (const std::vector<int>* v : {&s.fac.ptr, &s.lvu_ptr, &s.lvu_rows, &s.f_diag, &s.f_ptr})
+      f.insert(f.end(), v->begin(), v->end());
+    if (s.upd_lds) f.insert(f.end(), s.upd_dst.begin(), s.upd_dst.end());
+    if (f.size() % 2) f.push_back(0);
+    d.blob_fac_words = (int)f.size();
+    if ((e = upload(p, &d.blob_fac, f)) != hipSuccess) goto hip_error;
+  } else {
+    if ((e = upload_sched(p, s.fac, false, &d.fa_ptr, &d.fa_ent)) != hipSuccess) goto hip_error;
+  }
   {
     const size_t N = s.N;
     const int ntile = (s.nu + s.col_tile - 1) / s.col_tile;
-    size_t panel = 2 * N * (size_t)s.nx;
-    if (!d.lds) panel = std::max(panel, N * ntile * 2 * (size_t)s.nx * s.col_tile);
+    size_t panel = d.lds_stp ? 1 : 2 * N * (size_t)s.nx;
+    if (!d.lds_red && d.variant == 1) panel = std::max(panel, N * ntile * 2 * (size_t)s.nx * s.col_tile);
+    const size_t stacked = d.variant == 2 ? N * (size_t)s.nz * s.nu_pad : 1;
     if ((e = dalloc(p, &d.pdb, N * s.nb)) != hipSuccess) goto hip_error;
     if ((e = dalloc(p, &d.qdb, N * s.nb)) != hipSuccess) goto hip_error;
     if ((e = dalloc(p, &d.LV, N * s.nl * rkkt::kLVsize)) != hipSuccess) goto hip_error;
@@ -206,12 +290,23 @@ int rkkt_create(const rkkt_network* net, int n_scen, const double* pd, const dou
     if ((e = dalloc(p, &d.EV, N * s.n_ev)) != hipSuccess) goto hip_error;
     if ((e = dalloc(p, &d.W, N * s.k_col.size())) != hipSuccess) goto hip_error;
     if ((e = dalloc(p, &d.K, N * s.k_col.size())) != hipSuccess) goto hip_error;
-    if ((e = dalloc(p, &d.LU, N * s.f_col.size())) != hipSuccess) goto hip_error;
-    if ((e = dalloc(p, &d.invd, N * s.nx)) != hipSuccess) goto hip_error;
-    if ((e = dalloc(p, &d.part, N * s.nu * (size_t)s.nu)) != hipSuccess) goto hip_error;
+    if ((e = dalloc(p, &d.LU, N * (size_t)d.lu_stride)) != hipSuccess) goto hip_error;
+    if ((e = dalloc(p, &d.part, d.variant == 1 ? N * s.nu * (size_t)s.nu : 1)) != hipSuccess) goto hip_error;
     if ((e = dalloc(p, &d.panel, panel)) != hipSuccess) goto hip_error;
-    if ((e = dalloc(p, &d.imap, d.lds ? 1 : N * 16 * (size_t)s.nx)) != hipSuccess) goto hip_error;
+    if ((e = dalloc(p, &d.Zst, stacked)) != hipSuccess) goto hip_error;
+    if ((e = dalloc(p, &d.KZst, stacked)) != hipSuccess) goto hip_error;
+    if ((e = dalloc(p, &d.gpart, d.variant == 2 ? (size_t)s.nchunk * s.nu * s.nu : 1)) != hipSuccess)
+      goto hip_error;
+    if (d.variant == 2) {
+      // zero padding columns and the identity rows of Z, written once
+      if ((e = hipMemset(d.Zst, 0, stacked * sizeof(double))) != hipSuccess) goto hip_error;
+      if ((e = hipMemset(d.KZst, 0, stacked * sizeof(double))) != hipSuccess) goto hip_error;
+      rkkt::launch_identity_rows(d, nullptr);
+      if ((e = hipGetLastError()) != hipSuccess) goto hip_error;
+      if ((e = hipDeviceSynchronize()) != hipSuccess) goto hip_error;
+    }
     if ((e = dalloc(p, &d.rhat1, N * s.nx)) != hipSuccess) goto hip_error;
+    if ((e = dalloc(p, &d.wbuf, d.lds_stp ? 1 : N * (size_t)s.m)) != hipSuccess) goto hip_error;
     if ((e = dalloc(p, &d.rpart, N * s.nu)) != hipSuccess) goto hip_error;
     if ((e = dalloc(p, &d.status, 2)) != hipSuccess) goto hip_error;
     if ((e = rkkt::configure_lu_kernels(d)) != hipSuccess) goto hip_error;
@@ -287,6 +382,8 @@ int rkkt_condense(rkkt_problem* p, const double* sigma_x, const double* sigma_u,
         [&] { rkkt::launch_condense_values(p->d, sigma_x, sigma_s, delta_w, stream); });
   stage(p, RKKT_STAGE_REFACTOR, stream, [&] { rkkt::launch_refactor(p->d, stream); });
   stage(p, RKKT_STAGE_REDUCE, stream, [&] { rkkt::launch_reduce(p->d, stream); });
+  if (p->d.variant == 2)
+    stage(p, RKKT_STAGE_STACKED_PRODUCT, stream, [&] { rkkt::launch_stacked_product(p->d, stream); });
   stage(p, RKKT_STAGE_SCENARIO_SUM, stream,
         [&] { rkkt::launch_scenario_sum(p->d, sigma_u, delta_w, khat, stream); });
   return check_launch(p, "rkkt_condense");
@@ -453,16 +550,21 @@ int rkkt_batch_create(rkkt_problem* const* problems, const rkkt_iteration* its, 
 }
 
 int rkkt_autotune(const rkkt_network* net, int n_scen, const double* pd, const double* qd,
-                  const rkkt_options* opt, int reps, int* best_col_tile, double* best_ms) {
-  if (!net || !best_col_tile || !best_ms || reps < 1)
+                  const rkkt_options* opt, int reps, rkkt_options* best, double* best_ms) {
+  if (!net || !best || !best_ms || reps < 1)
     return fail(nullptr, RKKT_ERR_ARG, "rkkt_autotune: bad argument");
   rkkt::Sym s0;
-  std::string m = rkkt::build_symbolic(*net, n_scen, 0, s0);
+  std::string m = rkkt::build_symbolic(*net, n_scen, 0, 0, s0);
   if (!m.empty()) return fail(nullptr, RKKT_ERR_ARG, "rkkt_autotune: " + m);
-  std::vector<int> cands = {s0.col_tile};
-  for (int w : {4, 8, 16, 32, 64})
-    if (w <= s0.nu && w != s0.col_tile) cands.push_back(w);
   const int N = n_scen, nx = s0.nx, nu = s0.nu, mm = s0.m;
+  std::vector<std::pair<int, int>> cands;  // (variant, col_tile request)
+  const double stacked_bytes = 2.0 * 8.0 * N * (double)s0.nz * s0.nu_pad;
+  for (int v : {1, 2}) {
+    if (v == 2 && stacked_bytes > 4.0 * (1ull << 30)) continue;
+    cands.push_back({v, 0});
+    for (int w : {8, 16, 32, 64})
+      if (w <= nu) cands.push_back({v, w});
+  }
   // fixed interior point (host), copied once
   std::vector<double> hx((size_t)N * nx), hu(nu), hz((size_t)N * mm, 0.0), hy((size_t)N * nx, 0.0);
   for (int k = 0; k < N; ++k)
@@ -493,15 +595,23 @@ int rkkt_autotune(const rkkt_network* net, int n_scen, const double* pd, const d
   hipEvent_t t0 = nullptr, t1 = nullptr;
   if (e == hipSuccess) e = hipEventCreate(&t0);
   if (e == hipSuccess) e = hipEventCreate(&t1);
-  int best = -1;
+  rkkt_options bopt = opt ? *opt : rkkt_options{0, 0, 0};
   double bms = 1e300;
   int rc = RKKT_OK;
+  std::vector<std::pair<int, int>> seen;
   for (size_t ci = 0; ci < cands.size() && e == hipSuccess && rc == RKKT_OK; ++ci) {
-    rkkt_options o = opt ? *opt : rkkt_options{0, 0};
-    o.col_tile = cands[ci];
+    rkkt_options o = opt ? *opt : rkkt_options{0, 0, 0};
+    o.variant = cands[ci].first;
+    o.col_tile = cands[ci].second;
     rkkt_problem* q = nullptr;
     rc = rkkt_create(net, n_scen, pd, qd, &o, &q);
     if (rc != RKKT_OK) break;
+    const std::pair<int, int> got{q->sym.variant, q->sym.col_tile};
+    if (std::find(seen.begin(), seen.end(), got) != seen.end()) {
+      rkkt_destroy(q);
+      continue;
+    }
+    seen.push_back(got);
     rc = rkkt_evaluate(q, dx, du, dy, dz, 1.0 / N, f, gx, gu, g, h, nullptr);
     if (rc == RKKT_OK) rc = rkkt_condense(q, dsx, dsu, dss, 1.0, kh, nullptr);
     if (rc == RKKT_OK) e = hipEventRecord(t0, nullptr);
@@ -511,7 +621,11 @@ int rkkt_autotune(const rkkt_network* net, int n_scen, const double* pd, const d
     if (rc == RKKT_OK && e == hipSuccess) e = hipEventSynchronize(t1);
     float ms = 0.f;
     if (rc == RKKT_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
-    if (rc == RKKT_OK && e == hipSuccess && ms / reps < bms) { bms = ms / reps; best = cands[ci]; }
+    if (rc == RKKT_OK && e == hipSuccess && ms / reps < bms) {
+      bms = ms / reps;
+      bopt.variant = got.first;
+      bopt.col_tile = got.second;
+    }
     if (rc != RKKT_OK) g_err = q->err;
     rkkt_destroy(q);
   }
@@ -520,7 +634,7 @@ int rkkt_autotune(const rkkt_network* net, int n_scen, const double* pd, const d
   (void)hipFree(buf);
   if (rc != RKKT_OK) return fail(nullptr, rc, "rkkt_autotune: " + g_err);
   if (e != hipSuccess) return hip_fail(nullptr, e, "rkkt_autotune");
-  *best_col_tile = best;
+  *best = bopt;
   *best_ms = bms;
   return RKKT_OK;
 }

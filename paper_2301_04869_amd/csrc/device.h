@@ -12,8 +12,14 @@ namespace rkkt {
 struct DP {
   int nb, nl, ng, nload, ref, gref, nx, nu, m, nz, N;
   int n_ev, off_P, off_Q, off_gx, off_gu, off_h;
-  int nnz_gx, nnz_gu, nnz_h, nnz_k, nnz_f;
-  int nlev_up, nlev_dn, col_tile, lds;
+  int nnz_gx, nnz_gu, nnz_h, nnz_k, nnz_f, nnz_l;
+  int nlev_up, nlev_dn, col_tile;
+  int lds_red, lds_grp;   // reduction / refactorisation data in LDS
+  int lds_stp;            // step data in LDS
+  int spw;                // scenarios per workgroup of the LDS refactor and step
+  int upd_lds;            // LDS refactor stages its update targets
+  int variant;            // 1 adjoint solves, 2 stacked product
+  int nu_pad, nchunk;     // stacked panels: row pitch, contraction chunks
   double aref, bref;  // reference generator cost, per-unit coefficients
   // network
   const int *line_f, *line_t, *line_loc;
@@ -36,21 +42,89 @@ struct DP {
   const int *t_ptr, *t_row, *t_a, *t_b;
   const int *f_ptr, *f_col, *f_diag, *f_tpos, *gx2f;
   const int *lvu_ptr, *lvu_rows, *lvd_ptr, *lvd_rows;
+  // level-sliced schedules: pointer tables and entries (uint2 packed 16-bit
+  // pairs when the kernel stages them in LDS, int4 otherwise)
+  const int *ru_ptr, *rd_ptr, *su_ptr, *sd_ptr, *fa_ptr;
+  const void *ru_ent, *rd_ent, *su_ent, *sd_ent, *fa_ent;
+  int nph_u, nph_d, n_upd;
+  const int* upd_dst;
+  int lu_stride;          // nnz_f + nx
+  // LDS images of the shared index data of the reduction, the step and the
+  // refactorisation, laid out exactly as the kernels' LDS integer regions
+  const unsigned *blob_red, *blob_stp, *blob_fac;
+  int blob_red_words, blob_stp_words, blob_fac_words;
   // cached values and workspace
   double *LV;      // [N][nl][28]
   double *LH;      // [N][nl][10]
   double *EV;      // [N][n_ev]
   double *W;       // [N][nnz_k]
   double *K;       // [N][nnz_k]
-  double *LU;      // [N][nnz_f]
-  double *invd;    // [N][nx]
+  double *LU;      // [N][lu_stride]: factor values (nnz_f) then 1/u_ii (nx)
   double *part;    // [N][nu][nu] scenario contributions to the reduced matrix
   double *panel;   // global panels when not LDS-resident: [N][ntile][2][nx][col_tile]
-  int *imap;       // refactor column maps when not LDS-resident: [N][4][nx]
+  double *Zst;     // stacked product: [N][nz][nu_pad] Z = [-G_x^-1 G_u ; I]
+  double *KZst;    // stacked product: [N][nz][nu_pad] K Z
+  double *gpart;   // stacked product: [nchunk][nu][nu] lower-triangle partial sums
   double *rhat1;   // [N][nx] internal order
+  double *wbuf;    // [N][m] step work vector (global-memory step kernels)
   double *rpart;   // [N][nu]
   int *status;     // [2]: code, scenario
 };
+
+// Copy of n 8-byte units (doubles, or pairs of 32-bit words) from global
+// memory into LDS by the threads (start, start + stride, ...): every thread
+// issues kStageBatch loads before its first store, so its global round trips
+// overlap.  Source and destination are 8-byte aligned.
+constexpr int kStageBatch = 16;
+
+template <typename T>
+__device__ __forceinline__ void stage_copy(T* __restrict__ dst, const T* __restrict__ src, long long n,
+                                           int start, int stride) {
+  static_assert(sizeof(T) == 8, "8-byte units");
+  for (long long i0 = start; i0 < n; i0 += (long long)kStageBatch * stride) {
+    T v[kStageBatch];
+#pragma unroll
+    for (int u = 0; u < kStageBatch; ++u) {
+      const long long i = i0 + (long long)u * stride;
+      if (i < n) v[u] = src[i];
+    }
+#pragma unroll
+    for (int u = 0; u < kStageBatch; ++u) {
+      const long long i = i0 + (long long)u * stride;
+      if (i < n) dst[i] = v[u];
+    }
+  }
+}
+
+// the same for an array of 32-bit words padded to an even count
+__device__ __forceinline__ void stage_words(void* dst, const void* src, int words, int start, int stride) {
+  stage_copy(static_cast<uint2*>(dst), static_cast<const uint2*>(src), (words + 1) / 2, start, stride);
+}
+
+// dst[i * ldd + j] = src[i * lds + j] for i < rows, j < cols, kStageBatch
+// loads in flight per thread (dst in LDS)
+template <typename T>
+__device__ __forceinline__ void copy2d_overlapped(T* dst, int ldd, const T* __restrict__ src, long long lds,
+                                                  int rows, int cols, int start, int stride) {
+  const int total = rows * cols;
+  for (int t0 = start; t0 < total; t0 += kStageBatch * stride) {
+    T v[kStageBatch];
+    int o[kStageBatch];
+#pragma unroll
+    for (int u = 0; u < kStageBatch; ++u) {
+      const int t = t0 + u * stride;
+      o[u] = -1;
+      if (t < total) {
+        const int i = t / cols, j = t - i * cols;
+        v[u] = src[(long long)i * lds + j];
+        o[u] = i * ldd + j;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kStageBatch; ++u)
+      if (o[u] >= 0) dst[o[u]] = v[u];
+  }
+}
 
 // dynamic LDS limits of the kernels for this problem's sizes; called by rkkt_create
 hipError_t configure_lu_kernels(const DP& d);
@@ -66,6 +140,7 @@ void launch_condense_values(const DP& d, const double* sx, const double* ss, dou
                             hipStream_t s);
 // (k_lu.hip)
 void launch_refactor(const DP& d, hipStream_t s);
+void launch_identity_rows(const DP& d, hipStream_t s);
 void launch_reduce(const DP& d, hipStream_t s);
 void launch_step_rhs(const DP& d, const double* r1x, const double* r2, const double* r3,
                      const double* r4, const double* ss, hipStream_t s);
@@ -74,6 +149,7 @@ void launch_step_recover(const DP& d, const double* r2, const double* r3, const 
                          double* py, double* pz, hipStream_t s);
 // (k_dense.hip)
 void launch_scenario_sum(const DP& d, const double* su, double dw, double* khat, hipStream_t s);
+void launch_stacked_product(const DP& d, hipStream_t s);
 void launch_cholesky(const DP& d, double* a, int* info, hipStream_t s);
 void launch_reduced_solve(const DP& d, const double* r1u, const double* chol, double* pu,
                           hipStream_t s);

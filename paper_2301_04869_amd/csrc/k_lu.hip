@@ -1,35 +1,36 @@
-// Batched sparse LU refactorisation of G_x and the local reduction (paper,
-// parallel KKT solver section: the scenario blocks of G_x share one pattern,
-// so their LU factorisations can be batched; the reduced matrix is formed by
-// the three-step product K_hat V over column batches of the identity).
+// Batched sparse LU refactorisation of G_x, the local reduction and the
+// single-column solves of the step (paper, parallel KKT solver section: the
+// scenario blocks of G_x share one pattern, so their LU factorisations are
+// batched; the reduced matrix follows from the three-step product with the
+// columns of V = I taken in batches).
 //
-// G_x of every scenario is refactorised on one filled pattern with a fixed
-// symmetric fill-reducing permutation and static diagonal pivots.  Rows are
-// processed by an up-looking (row-by-row) elimination in level-schedule order:
-// rows of one level depend only on rows of earlier levels, so a level's rows
-// run concurrently (one wavefront per row, lanes over the row updates).
+// Factor layout.  G_x of every scenario is refactorised on one filled pattern
+// (fixed symmetric fill-reducing order, static diagonal pivots).  The stored
+// factor is L (unit lower), 1/u_ii, and the strict upper part of U with each
+// column j scaled by 1/u_jj.  With that scaling every triangular solve is a
+// unit-diagonal sweep plus one elementwise scaling:
+//   U x = y     : w = (I + U~)^-1 y, x = w / diag(U)
+//   U^T z = b   : z = (I + U~^T)^-1 (b / diag(U))
 //
-// The reduction of one scenario and one tile of W columns of V = I runs in one
-// workgroup: the right-hand-side panel -G_u[:, tile] is solved with L and U
-// (T = -G_x^-1 G_u, step 1), multiplied by K (L_x = K_xx T + K_xu, step 2),
-// solved with U^T and L^T and reduced with G_u^T (step 3,
-// K_hat V = L_u - G_u^T G_x^-T L_x).  Every level of every triangular solve
-// is one barrier-separated sweep.  Each thread keeps one fixed (row slot,
-// column) pair for the whole kernel.
+// Level-sliced sweeps.  Rows are grouped in levels of the elimination order
+// (rows of one level do not depend on each other).  Phase q starts when the
+// rows of level q are final; every row that depends on them subtracts those
+// contributions.  A phase's work is split over S slots ahead of time (longest
+// row first, to the least loaded slot), so the length of the dependency chain
+// is the number of phases plus the largest per-slot share of each phase,
+// rather than the sum over levels of the longest row.
 //
-// When the problem fits (kLDS), every value and index the sweeps touch -- LU
-// values, K values, G_u values, the filled pattern, the level schedules, the
-// K pattern -- is copied into LDS once per workgroup, so the dependent loads
-// on the critical path of a level are LDS loads; otherwise they read global
-// memory (large grids).
+// The refactorisation is the up-looking elimination taken the same way: in
+// phase q every entry l_ik with k in level q is divided by u_kk and row k's U
+// part is subtracted from row i at precomputed positions.
 #include "device.h"
 
 namespace rkkt {
 
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kRefactorWideThreads = 1024;
+constexpr int kRT = kRedThreads;  // reduction workgroup and global-mode scenario group
+constexpr int kGT = 256;          // LDS-mode refactor / step workgroup (up to 4 scenarios)
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -41,438 +42,673 @@ __device__ inline void raise_status(const DP& d, int code, int k) {
   if (atomicCAS(d.status, 0, code) == 0) d.status[1] = k;
 }
 
+// dst[idx[e]] = src[e] for e = start, start + stride, ... < n, with
+// kStageBatch loads in flight per thread
 template <typename T>
-__device__ __forceinline__ void copy_in(T* dst, const T* src, int n) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+__device__ __forceinline__ void scatter_overlapped(T* dst, const int* __restrict__ idx,
+                                                   const T* __restrict__ src, int n, int start,
+                                                   int stride) {
+  for (int e0 = start; e0 < n; e0 += kStageBatch * stride) {
+    int id[kStageBatch];
+    T v[kStageBatch];
+#pragma unroll
+    for (int u = 0; u < kStageBatch; ++u) {
+      const int e = e0 + u * stride;
+      id[u] = e < n ? idx[e] : -1;
+      v[u] = e < n ? src[e] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < kStageBatch; ++u)
+      if (id[u] >= 0) dst[id[u]] = v[u];
+  }
 }
+
+// factor values of scenario k, followed by its 1/u_ii
+__device__ __forceinline__ double* lu_of(const DP& d, int k) { return d.LU + (long long)k * d.lu_stride; }
 
 __host__ __device__ __forceinline__ LdsSizes sizes_of(const DP& d) {
   LdsSizes z;
   z.nx = d.nx; z.nu = d.nu; z.nz = d.nz; z.nnz_f = d.nnz_f; z.nnz_k = d.nnz_k;
-  z.nnz_gu = d.nnz_gu; z.nlu = d.nlev_up; z.nld = d.nlev_dn; z.w = d.col_tile;
+  z.nnz_gu = d.nnz_gu; z.nnz_l = d.nnz_l; z.nlu = d.nlev_up; z.nph_u = d.nph_u;
+  z.nph_d = d.nph_d; z.n_upd = d.n_upd; z.w = d.col_tile; z.variant = d.variant; z.spw = d.spw;
+  z.upd_lds = d.upd_lds;
+  z.nnz_h = d.nnz_h; z.m = d.m;
   return z;
 }
 
-// pattern of the filled LU and its level schedules
-struct SolveMeta {
-  const int *f_ptr, *f_diag, *f_col, *f_tpos, *lvu_ptr, *lvu_rows, *lvd_ptr, *lvd_rows;
-  int nlu, nld;
+// schedule entry: four fields, 16-bit packed (LDS copies) or plain int4
+struct Ent {
+  int a, b, c, d;
 };
 
-__device__ __forceinline__ SolveMeta global_meta(const DP& d) {
-  return SolveMeta{d.f_ptr, d.f_diag, d.f_col, d.f_tpos, d.lvu_ptr, d.lvu_rows, d.lvd_ptr,
-                   d.lvd_rows, d.nlev_up, d.nlev_dn};
-}
-
-// copies the solve metadata into LDS at `ip`; returns the pointer past it
-__device__ __forceinline__ int* stage_meta(const DP& d, int* ip, SolveMeta& m) {
-  const int nx = d.nx;
-  int* p = ip;
-  int* f_ptr = p; copy_in(f_ptr, d.f_ptr, nx + 1); p += nx + 1;
-  int* f_diag = p; copy_in(f_diag, d.f_diag, nx); p += nx;
-  int* f_col = p; copy_in(f_col, d.f_col, d.nnz_f); p += d.nnz_f;
-  int* f_tpos = p; copy_in(f_tpos, d.f_tpos, d.nnz_f); p += d.nnz_f;
-  int* lvu_ptr = p; copy_in(lvu_ptr, d.lvu_ptr, d.nlev_up + 1); p += d.nlev_up + 1;
-  int* lvu_rows = p; copy_in(lvu_rows, d.lvu_rows, nx); p += nx;
-  int* lvd_ptr = p; copy_in(lvd_ptr, d.lvd_ptr, d.nlev_dn + 1); p += d.nlev_dn + 1;
-  int* lvd_rows = p; copy_in(lvd_rows, d.lvd_rows, nx); p += nx;
-  m = SolveMeta{f_ptr, f_diag, f_col, f_tpos, lvu_ptr, lvu_rows, lvd_ptr, lvd_rows,
-                d.nlev_up, d.nlev_dn};
-  return p;
-}
-
-// One barrier-separated sweep per level; thread (slot, c) handles the rows
-// slot, slot + nslot, ... of every level.
-template <typename Row>
-__device__ __forceinline__ void sweep(const int* lv_ptr, const int* lv_rows, int nlev, int slot,
-                                      int nslot, bool active, Row row) {
-  for (int lev = 0; lev < nlev; ++lev) {
-    if (active) {
-      const int r1 = lv_ptr[lev + 1];
-      for (int ri = lv_ptr[lev] + slot; ri < r1; ri += nslot) row(lv_rows[ri]);
-    }
-    __syncthreads();
+template <bool kPacked>
+__device__ __forceinline__ Ent ent_at(const void* base, int e) {
+  if constexpr (kPacked) {
+    const uint2 v = static_cast<const uint2*>(base)[e];
+    return Ent{(int)(v.x & 0xffffu), (int)(v.x >> 16), (int)(v.y & 0xffffu), (int)(v.y >> 16)};
+  } else {
+    const int4 v = static_cast<const int4*>(base)[e];
+    return Ent{v.x, v.y, v.z, v.w};
   }
 }
 
-// X (nx x W, column c of this thread): X <- L^-1 X, then U^-1
-__device__ __forceinline__ void solve_LU(const SolveMeta& m, const double* lu, const double* invd,
-                                         double* X, int W, int c, int slot, int nslot, bool act) {
-  sweep(m.lvu_ptr, m.lvu_rows, m.nlu, slot, nslot, act, [&](int i) {
-    double acc = X[i * W + c];
-    const int e1 = m.f_diag[i];
-    for (int e = m.f_ptr[i]; e < e1; ++e) acc -= lu[e] * X[m.f_col[e] * W + c];
-    X[i * W + c] = acc;
-  });
-  sweep(m.lvd_ptr, m.lvd_rows, m.nld, slot, nslot, act, [&](int i) {
-    double acc = X[i * W + c];
-    const int e1 = m.f_ptr[i + 1];
-    for (int e = m.f_diag[i] + 1; e < e1; ++e) acc -= lu[e] * X[m.f_col[e] * W + c];
-    X[i * W + c] = acc * invd[i];
-  });
+// One level-sliced unit-diagonal sweep X <- (I + N)^-1 X, N the strict part
+// named by the schedule, with values lu[pos] (kTrans: lu[tpos], the mirrored
+// entry).  X is row-major with leading dimension ld; this thread owns column
+// c and slot `slot` of S.  Every phase ends with sync().
+//
+// Software pipelining: the schedule entries of the next phase and their
+// factor values do not depend on X, so they are loaded into registers (up to
+// kPre per thread) while the current phase works; a phase's critical path is
+// then the X loads, the multiply-adds and the X stores.  Each dependent row
+// is updated in place, X[dest] = ((X[dest] - v0 x0) - v1 x1) ..., in the
+// fixed order of the schedule.
+constexpr int kPre = 4;
+
+struct PhaseRegs {
+  int e0, n;
+  int dst[kPre], src[kPre];
+  double v[kPre];
+};
+
+template <bool kPacked, bool kTrans>
+__device__ __forceinline__ void load_phase(PhaseRegs& r, const int* __restrict__ ptr, const void* ent,
+                                           const double* __restrict__ lu, int q, int nphase, int S,
+                                           int slot, bool act) {
+  r.n = 0;
+  r.e0 = 0;
+  if (!act || q >= nphase) return;
+  r.e0 = ptr[q * S + slot];
+  r.n = ptr[q * S + slot + 1] - r.e0;
+#pragma unroll
+  for (int u = 0; u < kPre; ++u) {
+    if (u < r.n) {
+      const Ent t = ent_at<kPacked>(ent, r.e0 + u);
+      r.dst[u] = t.a;
+      r.src[u] = t.b;
+      r.v[u] = lu[kTrans ? t.d : t.c];
+    } else {
+      r.dst[u] = -1;
+      r.src[u] = 0;
+      r.v[u] = 0.0;
+    }
+  }
 }
 
-// X <- U^-T X, then L^-T (row i of U^T / L^T has the pattern of the L / U part of row i)
-__device__ __forceinline__ void solve_LUt(const SolveMeta& m, const double* lu, const double* invd,
-                                          double* X, int W, int c, int slot, int nslot, bool act) {
-  sweep(m.lvu_ptr, m.lvu_rows, m.nlu, slot, nslot, act, [&](int i) {
-    double acc = X[i * W + c];
-    const int e1 = m.f_diag[i];
-    for (int e = m.f_ptr[i]; e < e1; ++e) acc -= lu[m.f_tpos[e]] * X[m.f_col[e] * W + c];
-    X[i * W + c] = acc * invd[i];
-  });
-  sweep(m.lvd_ptr, m.lvd_rows, m.nld, slot, nslot, act, [&](int i) {
-    double acc = X[i * W + c];
-    const int e1 = m.f_ptr[i + 1];
-    for (int e = m.f_diag[i] + 1; e < e1; ++e) acc -= lu[m.f_tpos[e]] * X[m.f_col[e] * W + c];
-    X[i * W + c] = acc;
-  });
+template <bool kPacked, bool kTrans, typename Sync>
+__device__ __forceinline__ void sweep(const int* __restrict__ ptr, const void* ent, int nphase, int S,
+                                      int slot, bool act, const double* __restrict__ lu, double* X,
+                                      int ld, int c, Sync sync) {
+  PhaseRegs cur;
+  load_phase<kPacked, kTrans>(cur, ptr, ent, lu, 0, nphase, S, slot, act);
+  for (int q = 0; q < nphase; ++q) {
+    double xs[kPre], xd[kPre];
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+      xs[u] = u < cur.n ? X[(long long)cur.src[u] * ld + c] : 0.0;
+      xd[u] = u < cur.n ? X[(long long)cur.dst[u] * ld + c] : 0.0;
+    }
+    PhaseRegs nxt;
+    load_phase<kPacked, kTrans>(nxt, ptr, ent, lu, q + 1, nphase, S, slot, act);
+    if (cur.n > 0) {
+      double acc = xd[0];
+#pragma unroll
+      for (int u = 0; u < kPre; ++u) {
+        if (u < cur.n) {
+          acc = fma(-cur.v[u], xs[u], acc);
+          const bool last = u + 1 == kPre || u + 1 >= cur.n || cur.dst[u + 1] != cur.dst[u];
+          if (last) {
+            X[(long long)cur.dst[u] * ld + c] = acc;
+            if (u + 1 < kPre) acc = xd[u + 1];
+          }
+        }
+      }
+      // entries beyond the registered ones (long tasks), one at a time
+      for (int e = cur.e0 + kPre; e < cur.e0 + cur.n; ++e) {
+        const Ent t = ent_at<kPacked>(ent, e);
+        double* xdp = X + (long long)t.a * ld + c;
+        *xdp = fma(-lu[kTrans ? t.d : t.c], X[(long long)t.b * ld + c], *xdp);
+      }
+    }
+    sync();
+    cur = nxt;
+  }
 }
 
 // ------------------------------------------------------------ refactorisation
-template <bool kLDS, int kRT>
-__global__ __launch_bounds__(kRT) void k_refactor(DP d) {
-  constexpr int kRW = kRT / 64;
-  const int k = blockIdx.x;
-  const int nx = d.nx;
+// LDS mode: spw scenarios per workgroup, one wavefront each, with the shared
+// schedule staged once; global mode: one workgroup of kRT threads per scenario.
+template <bool kLDS, int kT, bool kUpdLds>
+__global__ __launch_bounds__(kT) void k_refactor(DP d) {
+  constexpr int G = kLDS ? kGroupLds : kT;
+  const int tid = threadIdx.x;
+  const int gi = kLDS ? tid / G : 0, gl = kLDS ? tid % G : tid;
+  const int k = blockIdx.x * (kLDS ? d.spw : 1) + gi;
+  const bool live = gi < (kLDS ? d.spw : 1) && k < d.N;
+  const int nx = d.nx, nf = d.nnz_f;
   extern __shared__ double smem[];
   double *lu, *invd, *rmax;
-  int* map;
-  const int *f_ptr, *f_diag, *f_col, *lvu_ptr, *lvu_rows;
+  const int *ptr, *upd, *lvu_ptr, *lvu_rows, *f_ptr, *f_diag, *f_col;
+  const void* ent;
   if (kLDS) {
-    lu = smem;
-    invd = lu + d.nnz_f;
+    double* mine = smem + (long long)gi * (nf + 2 * nx);
+    lu = mine;
+    invd = lu + nf;
     rmax = invd + nx;
-    int* p = reinterpret_cast<int*>(rmax + nx);
-    int* a = p; copy_in(a, d.f_ptr, nx + 1); f_ptr = a; p += nx + 1;
-    a = p; copy_in(a, d.f_diag, nx); f_diag = a; p += nx;
-    a = p; copy_in(a, d.f_col, d.nnz_f); f_col = a; p += d.nnz_f;
-    a = p; copy_in(a, d.lvu_ptr, d.nlev_up + 1); lvu_ptr = a; p += d.nlev_up + 1;
-    a = p; copy_in(a, d.lvu_rows, nx); lvu_rows = a; p += nx;
-    map = p;
+    unsigned* ue = reinterpret_cast<unsigned*>(smem + (long long)d.spw * (nf + 2 * nx));
+    int* q = reinterpret_cast<int*>(ue + 2 * d.nnz_l);
+    int* a_p = q; q += d.nph_u * G + 1;
+    int* a_lp = q; q += d.nlev_up + 1;
+    int* a_lr = q; q += nx;
+    int* a_fd = q; q += nx;
+    int* a_fp = q; q += nx + 1;
+    upd = kUpdLds ? q : d.upd_dst;
+    stage_words(ue, d.blob_fac, d.blob_fac_words, tid, blockDim.x);
+    ptr = a_p; lvu_ptr = a_lp; lvu_rows = a_lr; f_diag = a_fd; f_ptr = a_fp;
+    f_col = d.f_col;
+    ent = ue;
   } else {
-    lu = d.LU + (long long)k * d.nnz_f;
-    invd = d.invd + (long long)k * nx;
+    lu = lu_of(d, k);
+    invd = lu + nf;
     rmax = d.rhat1 + (long long)k * nx;
-    map = d.imap + (long long)k * kRW * nx;
-    f_ptr = d.f_ptr; f_diag = d.f_diag; f_col = d.f_col; lvu_ptr = d.lvu_ptr; lvu_rows = d.lvu_rows;
+    ptr = d.fa_ptr; ent = d.fa_ent; upd = d.upd_dst;
+    lvu_ptr = d.lvu_ptr; lvu_rows = d.lvu_rows; f_ptr = d.f_ptr; f_diag = d.f_diag; f_col = d.f_col;
   }
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const double* gv = d.EV + (long long)k * d.n_ev + d.off_gx;
-  for (int e = tid; e < d.nnz_f; e += kRT) lu[e] = 0.0;
+  auto gsync = [] {
+    if (kLDS) wave_sync();
+    else __syncthreads();
+  };
+  if (live) {
+    const double* gv = d.EV + (long long)k * d.n_ev + d.off_gx;
+    for (int e = gl; e < nf; e += G) lu[e] = 0.0;
+    gsync();
+    scatter_overlapped(lu, d.gx2f, gv, d.nnz_gx, gl, G);
+  }
   __syncthreads();
-  for (int e = tid; e < d.nnz_gx; e += kRT) lu[d.gx2f[e]] = gv[e];
-  for (int i = tid; i < nx; i += kRT) {
+  if (!live) return;
+  // largest |entry| of every row of G_x (fill positions hold zeros)
+  for (int i = gl; i < nx; i += G) {
     double mx = 0.0;
-    for (int e = d.gx_ptr[i]; e < d.gx_ptr[i + 1]; ++e) mx = fmax(mx, fabs(gv[e]));
+    const int e1 = f_ptr[i + 1];
+    for (int e = f_ptr[i]; e < e1; ++e) mx = fmax(mx, fabs(lu[e]));
     rmax[i] = mx;
   }
-  __syncthreads();
-  int* mp = map + wv * nx;
-  for (int lev = 0; lev < d.nlev_up; ++lev) {
-    const int r1 = lvu_ptr[lev + 1];
-    for (int ri = lvu_ptr[lev] + wv; ri < r1; ri += kRW) {
-      const int i = lvu_rows[ri];
-      const int f0 = f_ptr[i], fd = f_diag[i], f1 = f_ptr[i + 1];
-      for (int e = f0 + lane; e < f1; e += 64) mp[f_col[e]] = e;
-      wave_sync();
-      for (int e = f0; e < fd; ++e) {
-        const int kk = f_col[e];
-        const double l = lu[e] * invd[kk];
-        wave_sync();
-        if (lane == 0) lu[e] = l;
-        const int q1 = f_ptr[kk + 1];
-        for (int q = f_diag[kk] + 1 + lane; q < q1; q += 64) lu[mp[f_col[q]]] -= l * lu[q];
-        wave_sync();
-      }
-      if (lane == 0) {
-        const double p = lu[fd];
-        if (!(fabs(p) > 0.0 && fabs(p) >= 1e-10 * rmax[i]) || !isfinite(p))
-          raise_status(d, RKKT_ERR_SINGULAR_GX, k);
-        invd[i] = 1.0 / p;
-      }
-      wave_sync();
+  gsync();
+  for (int q = 0; q < d.nlev_up; ++q) {
+    // rows of level q are final: pivot test and reciprocal
+    for (int r = lvu_ptr[q] + gl; r < lvu_ptr[q + 1]; r += G) {
+      const int i = lvu_rows[r];
+      const double p = lu[f_diag[i]];
+      if (!(fabs(p) > 0.0 && fabs(p) >= 1e-10 * rmax[i]) || !isfinite(p))
+        raise_status(d, RKKT_ERR_SINGULAR_GX, k);
+      invd[i] = 1.0 / p;
     }
-    __syncthreads();
+    if (q < d.nph_u) {
+      const int e1 = ptr[q * G + gl + 1];
+      for (int e = ptr[q * G + gl]; e < e1; ++e) {
+        const Ent t = ent_at<kLDS>(ent, e);  // (position of l_ik, of u_kk, |U(k)|, first target)
+        const double l = lu[t.a] * (1.0 / lu[t.b]);
+        lu[t.a] = l;
+        const int* dst = upd + t.d;
+        const double* src = lu + t.b + 1;
+        int j = 0;
+        for (; j + 4 <= t.c; j += 4) {
+          const int d0 = dst[j], d1 = dst[j + 1], d2 = dst[j + 2], d3 = dst[j + 3];
+          const double s0 = src[j], s1 = src[j + 1], s2 = src[j + 2], s3 = src[j + 3];
+          const double o0 = lu[d0], o1 = lu[d1], o2 = lu[d2], o3 = lu[d3];
+          lu[d0] = fma(-l, s0, o0);
+          lu[d1] = fma(-l, s1, o1);
+          lu[d2] = fma(-l, s2, o2);
+          lu[d3] = fma(-l, s3, o3);
+        }
+        for (; j < t.c; ++j) lu[dst[j]] = fma(-l, src[j], lu[dst[j]]);
+      }
+    }
+    gsync();
+  }
+  // scale the columns of the strict upper part by 1/u_jj
+  for (int i = gl; i < nx; i += G) {
+    const int e1 = f_ptr[i + 1];
+    for (int e = f_diag[i] + 1; e < e1; ++e) lu[e] *= invd[f_col[e]];
   }
   if (kLDS) {
-    double* glu = d.LU + (long long)k * d.nnz_f;
-    for (int e = tid; e < d.nnz_f; e += kRT) glu[e] = lu[e];
-    double* gid = d.invd + (long long)k * nx;
-    for (int i = tid; i < nx; i += kRT) gid[i] = invd[i];
+    gsync();
+    double* glu = lu_of(d, k);  // factor values and 1/u_ii are contiguous in both places
+    for (int e = gl; e < nf + nx; e += G) glu[e] = lu[e];
   }
 }
 
 // ---------------------------------------------------------- local reduction
-template <bool kLDS>
-__global__ __launch_bounds__(kThreads) void k_reduce(DP d) {
+// One workgroup per (tile of W columns of V = I, scenario): slot = thread / W
+// (S = kRT / W slots), column = thread % W.
+//   step 1: T = -G_x^-1 G_u V            (L sweep, U sweep, scaling)
+//   step 2: L_x = K_xx T + K_xu V, L_u = K_ux T + K_uu V
+//   step 3 (adjoint, kVar 1): K_hat_k V = L_u - G_u^T G_x^-T L_x, written to part
+//   step 3 (product, kVar 2): Z = [T; I] and K Z written to the stacked panels;
+//          the stacked product Z^T (K Z) over all scenarios closes the reduction
+template <bool kLDS, int kVar>
+__global__ __launch_bounds__(kRT) void k_reduce(DP d) {
   const int k = blockIdx.y, tile = blockIdx.x;
-  const int W = d.col_tile, c0 = tile * W;
-  const int nx = d.nx, nu = d.nu;
-  const int ntile = gridDim.x;
-  const int tid = threadIdx.x;
-  const int nslot = kThreads / W, slot = tid / W, c = tid % W;
-  const bool act = slot < nslot;
+  const int W = d.col_tile, c0 = tile * W, nx = d.nx, nu = d.nu, nz = d.nz;
+  const int S = kRT / W;
+  const int tid = threadIdx.x, slot = tid / W, c = tid - slot * W;
+  const bool act = slot < S;
+  const bool colok = act && c0 + c < nu;
+  const int col = c0 + c;
   extern __shared__ double smem[];
   const double* ev = d.EV + (long long)k * d.n_ev;
-  const double *lu, *invd, *kv, *guv;
-  double *T, *Lx;
-  SolveMeta m;
-  const int *k_ptr, *k_usplit, *k_col, *guc_ptr, *guc_row;
+  const double *lu, *invd, *kv, *guv = nullptr;
+  double *T, *Lx = nullptr;
+  int ldT = W;
+  const int *uptr, *dptr, *k_ptr, *k_usplit, *k_col, *guc_ptr, *guc_row;
+  const void *uent, *dent;
+  double* zk = kVar == 2 ? d.Zst + (long long)k * nz * d.nu_pad : nullptr;
+  double* kzk = kVar == 2 ? d.KZst + (long long)k * nz * d.nu_pad : nullptr;
   if (kLDS) {
     const LdsSizes z = sizes_of(d);
     double* p = smem;
-    double* slu = p; copy_in(slu, d.LU + (long long)k * d.nnz_f, d.nnz_f); p += d.nnz_f;
-    double* sid = p; copy_in(sid, d.invd + (long long)k * nx, nx); p += nx;
-    double* skv = p; copy_in(skv, d.K + (long long)k * d.nnz_k, d.nnz_k); p += d.nnz_k;
-    double* sgu = p;
-    for (int j = tid; j < d.nnz_gu; j += kThreads) sgu[j] = ev[d.off_gu + d.guc_pos[j]];
-    p += d.nnz_gu;
-    T = p; p += nx * W;
-    Lx = p; p += nx * W;
-    int* ip = reinterpret_cast<int*>(smem + reduce_lds_doubles(z));
-    ip = stage_meta(d, ip, m);
-    int* a = ip; copy_in(a, d.k_ptr, d.nz + 1); k_ptr = a; ip += d.nz + 1;
-    a = ip; copy_in(a, d.k_usplit, d.nz); k_usplit = a; ip += d.nz;
-    a = ip; copy_in(a, d.k_col, d.nnz_k); k_col = a; ip += d.nnz_k;
-    a = ip; copy_in(a, d.guc_ptr, nu + 1); guc_ptr = a; ip += nu + 1;
-    a = ip; copy_in(a, d.guc_row, d.nnz_gu); guc_row = a;
+    double* slu = p; p += d.nnz_f;
+    double* sid = p; p += nx;
+    double* skv = p; p += d.nnz_k;
+    double* sgu = p; p += d.nnz_gu;
+    T = p; p += (long long)nx * W;
+    if (kVar == 1) { Lx = p; p += (long long)nx * W; }
+    unsigned* ue = reinterpret_cast<unsigned*>(smem + reduce_lds_doubles(z));
+    unsigned* de = ue + 2 * d.nnz_l;
+    int* ip = reinterpret_cast<int*>(de + 2 * d.nnz_l);
+    int* a_up = ip; ip += d.nph_u * S + 1;
+    int* a_dp = ip; ip += d.nph_d * S + 1;
+    int* a_kp = ip; ip += nz + 1;
+    int* a_ku = ip; ip += nz;
+    int* a_kc = ip; ip += d.nnz_k;
+    int* a_gp = ip; ip += nu + 1;
+    int* a_gr = ip;
+    stage_copy(slu, lu_of(d, k), d.nnz_f + nx, tid, kRT);  // factor values, then 1/u_ii into sid
+    stage_copy(skv, d.K + (long long)k * d.nnz_k, d.nnz_k, tid, kRT);
+    stage_words(ue, d.blob_red, d.blob_red_words, tid, kRT);
+    for (int j = tid; j < d.nnz_gu; j += kRT) sgu[j] = ev[d.off_gu + d.guc_pos[j]];
+    uptr = a_up; dptr = a_dp; k_ptr = a_kp; k_usplit = a_ku; k_col = a_kc; guc_ptr = a_gp; guc_row = a_gr;
     lu = slu; invd = sid; kv = skv; guv = sgu;
+    uent = ue; dent = de;
   } else {
-    lu = d.LU + (long long)k * d.nnz_f;
-    invd = d.invd + (long long)k * nx;
+    lu = lu_of(d, k);
+    invd = lu + d.nnz_f;
     kv = d.K + (long long)k * d.nnz_k;
-    guv = nullptr;
-    T = d.panel + ((long long)k * ntile + tile) * 2LL * nx * W;
-    Lx = T + (long long)nx * W;
-    m = global_meta(d);
+    if (kVar == 2) {
+      T = zk + c0;  // solved in place in the stacked panel
+      ldT = d.nu_pad;
+    } else {
+      T = d.panel + ((long long)k * gridDim.x + tile) * 2LL * nx * W;
+      Lx = T + (long long)nx * W;
+    }
+    uptr = d.ru_ptr; dptr = d.rd_ptr; uent = d.ru_ent; dent = d.rd_ent;
     k_ptr = d.k_ptr; k_usplit = d.k_usplit; k_col = d.k_col;
     guc_ptr = d.guc_ptr; guc_row = d.guc_row;
   }
+  auto bsync = [] { __syncthreads(); };
   auto gu_val = [&](int j) -> double { return kLDS ? guv[j] : ev[d.off_gu + d.guc_pos[j]]; };
-  auto k_ucol = [&](int r, int col) -> double {
+  auto k_ucol = [&](int r, int cc) -> double {
     const int e1 = k_ptr[r + 1];
     for (int e = k_usplit[r]; e < e1; ++e)
-      if (k_col[e] == col) return kv[e];
+      if (k_col[e] == cc) return kv[e];
     return 0.0;
   };
-  double* out = d.part + (long long)k * nu * nu;
-  const bool colok = c0 + c < nu;
 
-  // right-hand side -G_u[:, c0:c0+W]
-  for (int i = tid; i < nx * W; i += kThreads) T[i] = 0.0;
-  __syncthreads();
-  if (act && colok)
-    for (int j = guc_ptr[c0 + c] + slot; j < guc_ptr[c0 + c + 1]; j += nslot)
-      T[guc_row[j] * W + c] = -gu_val(j);
-  __syncthreads();
-  // step 1: T = -G_x^-1 G_u V
-  solve_LU(m, lu, invd, T, W, c, slot, nslot, act);
-  // step 2: L_x = K_xx T + K_xu V, L_u = K_ux T + K_uu V
-  if (act) {
-    for (int r = slot; r < nx; r += nslot) {
-      double acc = k_ucol(r, nx + c0 + c);
-      const int e1 = k_usplit[r];
-      for (int e = k_ptr[r]; e < e1; ++e) acc += kv[e] * T[k_col[e] * W + c];
-      Lx[r * W + c] = acc;
-    }
-    if (colok)
-      for (int ru = slot; ru < nu; ru += nslot) {
-        const int r = nx + ru;
-        double acc = k_ucol(r, nx + c0 + c);
-        const int e1 = k_usplit[r];
-        for (int e = k_ptr[r]; e < e1; ++e) acc += kv[e] * T[k_col[e] * W + c];
-        out[(long long)ru * nu + c0 + c] = acc;
-      }
-  }
-  __syncthreads();
-  // step 3: K_hat V = L_u - G_u^T G_x^-T L_x
-  solve_LUt(m, lu, invd, Lx, W, c, slot, nslot, act);
-  if (act && colok)
-    for (int ru = slot; ru < nu; ru += nslot) {
-      double acc = out[(long long)ru * nu + c0 + c];
-      const int j1 = guc_ptr[ru + 1];
-      for (int j = guc_ptr[ru]; j < j1; ++j) acc -= gu_val(j) * Lx[guc_row[j] * W + c];
-      out[(long long)ru * nu + c0 + c] = acc;
-    }
-}
-
-// ------------------------------------- local reduction, large grids (global)
-// One workgroup of 16 wavefronts per (scenario, tile of 64 columns); a
-// wavefront owns one row at a time and its lanes the 64 columns, so the row's
-// pattern and LU values are wavefront-uniform (one broadcast load each) and
-// the panel accesses X[col][lane] are coalesced.  Panels live in global memory.
-constexpr int kWideThreads = 1024, kWideWaves = kWideThreads / 64, kWideW = 64;
-
-template <bool kTrans, bool kUpper, bool kScale>
-__device__ __forceinline__ void wide_sweep(const DP& d, const double* __restrict__ lu,
-                                           const double* __restrict__ invd, double* X, int wv,
-                                           int lane) {
-  const int* lv_ptr = kUpper ? d.lvd_ptr : d.lvu_ptr;
-  const int* lv_rows = kUpper ? d.lvd_rows : d.lvu_rows;
-  const int nlev = kUpper ? d.nlev_dn : d.nlev_up;
-  for (int lev = 0; lev < nlev; ++lev) {
-    const int r1 = lv_ptr[lev + 1];
-    for (int ri = lv_ptr[lev] + wv; ri < r1; ri += kWideWaves) {
-      const int i = __builtin_amdgcn_readfirstlane(lv_rows[ri]);
-      const int e0 = kUpper ? d.f_diag[i] + 1 : d.f_ptr[i];
-      const int e1 = kUpper ? d.f_ptr[i + 1] : d.f_diag[i];
-      double acc = X[(long long)i * kWideW + lane];
-      double acc2 = 0.0;
-      int e = e0;
-      for (; e + 4 <= e1; e += 4) {
-        const int c0 = d.f_col[e], c1 = d.f_col[e + 1], c2 = d.f_col[e + 2], c3 = d.f_col[e + 3];
-        const double v0 = lu[kTrans ? d.f_tpos[e] : e], v1 = lu[kTrans ? d.f_tpos[e + 1] : e + 1];
-        const double v2 = lu[kTrans ? d.f_tpos[e + 2] : e + 2], v3 = lu[kTrans ? d.f_tpos[e + 3] : e + 3];
-        const double x0 = X[(long long)c0 * kWideW + lane], x1 = X[(long long)c1 * kWideW + lane];
-        const double x2 = X[(long long)c2 * kWideW + lane], x3 = X[(long long)c3 * kWideW + lane];
-        acc -= v0 * x0;
-        acc2 -= v1 * x1;
-        acc -= v2 * x2;
-        acc2 -= v3 * x3;
-      }
-      for (; e < e1; ++e) acc -= lu[kTrans ? d.f_tpos[e] : e] * X[(long long)d.f_col[e] * kWideW + lane];
-      acc += acc2;
-      X[(long long)i * kWideW + lane] = kScale ? acc * invd[i] : acc;
-    }
-    __syncthreads();
-  }
-}
-
-__global__ __launch_bounds__(kWideThreads) void k_reduce_wide(DP d) {
-  const int k = blockIdx.y, tile = blockIdx.x;
-  const int c0 = tile * kWideW, nx = d.nx, nu = d.nu;
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const double* ev = d.EV + (long long)k * d.n_ev;
-  const double* lu = d.LU + (long long)k * d.nnz_f;
-  const double* invd = d.invd + (long long)k * nx;
-  const double* kv = d.K + (long long)k * d.nnz_k;
-  double* T = d.panel + ((long long)k * gridDim.x + tile) * 2LL * nx * kWideW;
-  double* Lx = T + (long long)nx * kWideW;
-  double* out = d.part + (long long)k * nu * nu;
-  const int col = c0 + lane;
-  const bool colok = col < nu;
-  for (long long q = tid; q < (long long)nx * kWideW; q += kWideThreads) T[q] = 0.0;
+  // right-hand side -G_u[:, c0 + c]
+  if (colok)
+    for (int i = slot; i < nx; i += S) T[(long long)i * ldT + c] = 0.0;
   __syncthreads();
   if (colok)
-    for (int j = d.guc_ptr[col] + wv; j < d.guc_ptr[col + 1]; j += kWideWaves)
-      T[(long long)d.guc_row[j] * kWideW + lane] = -ev[d.off_gu + d.guc_pos[j]];
+    for (int j = guc_ptr[col] + slot; j < guc_ptr[col + 1]; j += S)
+      T[(long long)guc_row[j] * ldT + c] = -gu_val(j);
   __syncthreads();
-  wide_sweep<false, false, false>(d, lu, invd, T, wv, lane);
-  wide_sweep<false, true, true>(d, lu, invd, T, wv, lane);
-  auto k_ucol = [&](int r, int cc) -> double {
-    for (int e = d.k_usplit[r]; e < d.k_ptr[r + 1]; ++e)
-      if (d.k_col[e] == cc) return kv[e];
-    return 0.0;
+  // step 1
+  sweep<kLDS, false>(uptr, uent, d.nph_u, S, slot, colok, lu, T, ldT, c, bsync);
+  sweep<kLDS, false>(dptr, dent, d.nph_d, S, slot, colok, lu, T, ldT, c, bsync);
+  if (colok)
+    for (int i = slot; i < nx; i += S) T[(long long)i * ldT + c] *= invd[i];
+  __syncthreads();
+  if (kVar == 2) {
+    if (!colok) return;
+    if (kLDS)
+      for (int i = slot; i < nx; i += S) zk[(long long)i * d.nu_pad + col] = T[i * W + c];
+    for (int r = slot; r < nz; r += S) {
+      double acc = k_ucol(r, nx + col);
+      const int e1 = k_usplit[r];
+      for (int e = k_ptr[r]; e < e1; ++e) acc = fma(kv[e], T[(long long)k_col[e] * ldT + c], acc);
+      kzk[(long long)r * d.nu_pad + col] = acc;
+    }
+    return;
+  }
+  // step 2 (adjoint): L_x, prescaled by 1/u_ii for the U^T sweep; L_u into part
+  double* out = d.part + (long long)k * nu * nu;
+  if (colok)
+    for (int r = slot; r < nz; r += S) {
+      double acc = k_ucol(r, nx + col);
+      const int e1 = k_usplit[r];
+      for (int e = k_ptr[r]; e < e1; ++e) acc = fma(kv[e], T[(long long)k_col[e] * W + c], acc);
+      if (r < nx) Lx[(long long)r * W + c] = acc * invd[r];
+      else out[(long long)(r - nx) * nu + col] = acc;
+    }
+  __syncthreads();
+  // step 3: U^T sweep, L^T sweep, then L_u - G_u^T (G_x^-T L_x)
+  sweep<kLDS, true>(uptr, uent, d.nph_u, S, slot, colok, lu, Lx, W, c, bsync);
+  sweep<kLDS, true>(dptr, dent, d.nph_d, S, slot, colok, lu, Lx, W, c, bsync);
+  if (colok)
+    for (int ru = slot; ru < nu; ru += S) {
+      double acc = out[(long long)ru * nu + col];
+      const int j1 = guc_ptr[ru + 1];
+      for (int j = guc_ptr[ru]; j < j1; ++j) acc = fma(-gu_val(j), Lx[(long long)guc_row[j] * W + c], acc);
+      out[(long long)ru * nu + col] = acc;
+    }
+}
+
+// ------------------------------------- local reduction with 64-column tiles
+// One slot per wavefront (lane = column, S = 16 slots): the schedule entries,
+// the K pattern and the factor values a wavefront reads are the same for all
+// of its lanes, so the schedule and the pattern come through scalar loads
+// (wave-uniform indices) and the factor values as LDS broadcasts; only the
+// panel arithmetic runs on the vector unit.  Entries of a phase are taken
+// four at a time with all their loads issued first.
+constexpr int kW64 = 64, kS64 = kRT / kW64;
+
+template <bool kTrans, typename Sync>
+__device__ __forceinline__ void sweep64(const int* __restrict__ ptr, const int4* __restrict__ ent,
+                                        int nphase, int wv, const double* __restrict__ lu, double* X,
+                                        int ld, int c, Sync sync) {
+  int e0 = nphase > 0 ? ptr[wv] : 0, e1 = nphase > 0 ? ptr[wv + 1] : 0;
+  for (int q = 0; q < nphase; ++q) {
+    const int n0 = q + 1 < nphase ? ptr[(q + 1) * kS64 + wv] : 0;
+    const int n1 = q + 1 < nphase ? ptr[(q + 1) * kS64 + wv + 1] : 0;
+    int cur = -1;
+    double acc = 0.0;
+    int e = e0;
+    for (; e + 4 <= e1; e += 4) {
+      const int4 t0 = ent[e], t1 = ent[e + 1], t2 = ent[e + 2], t3 = ent[e + 3];
+      const double v0 = lu[kTrans ? t0.w : t0.z], v1 = lu[kTrans ? t1.w : t1.z];
+      const double v2 = lu[kTrans ? t2.w : t2.z], v3 = lu[kTrans ? t3.w : t3.z];
+      const double x0 = X[t0.y * ld + c], x1 = X[t1.y * ld + c];
+      const double x2 = X[t2.y * ld + c], x3 = X[t3.y * ld + c];
+      if (t0.x != cur) { if (cur >= 0) X[cur * ld + c] = acc; cur = t0.x; acc = X[cur * ld + c]; }
+      acc = fma(-v0, x0, acc);
+      if (t1.x != cur) { X[cur * ld + c] = acc; cur = t1.x; acc = X[cur * ld + c]; }
+      acc = fma(-v1, x1, acc);
+      if (t2.x != cur) { X[cur * ld + c] = acc; cur = t2.x; acc = X[cur * ld + c]; }
+      acc = fma(-v2, x2, acc);
+      if (t3.x != cur) { X[cur * ld + c] = acc; cur = t3.x; acc = X[cur * ld + c]; }
+      acc = fma(-v3, x3, acc);
+    }
+    for (; e < e1; ++e) {
+      const int4 t = ent[e];
+      const double v = lu[kTrans ? t.w : t.z];
+      const double x = X[t.y * ld + c];
+      if (t.x != cur) { if (cur >= 0) X[cur * ld + c] = acc; cur = t.x; acc = X[cur * ld + c]; }
+      acc = fma(-v, x, acc);
+    }
+    if (cur >= 0) X[cur * ld + c] = acc;
+    sync();
+    e0 = n0;
+    e1 = n1;
+  }
+}
+
+template <bool kLDS, int kVar>
+__global__ __launch_bounds__(kRT) void k_reduce64(DP d) {
+  const int k = blockIdx.y, tile = blockIdx.x;
+  const int c0 = tile * kW64, nx = d.nx, nu = d.nu, nz = d.nz;
+  const int tid = threadIdx.x, c = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int col = c0 + c;
+  const bool colok = col < nu;
+  extern __shared__ double smem[];
+  const double* ev = d.EV + (long long)k * d.n_ev;
+  const double *lu, *invd, *kv, *guv = nullptr;
+  double *T, *Lx = nullptr;
+  int ldT = kW64;
+  double* zk = kVar == 2 ? d.Zst + (long long)k * nz * d.nu_pad : nullptr;
+  double* kzk = kVar == 2 ? d.KZst + (long long)k * nz * d.nu_pad : nullptr;
+  const int* __restrict__ k_ptr = d.k_ptr;
+  const int* __restrict__ k_usplit = d.k_usplit;
+  const int* __restrict__ k_col = d.k_col;
+  if (kLDS) {
+    double* p = smem;
+    double* slu = p; p += d.nnz_f + nx;
+    double* skv = p; p += d.nnz_k;
+    double* sgu = p; p += d.nnz_gu;
+    T = p; p += (long long)nx * kW64;
+    if (kVar == 1) Lx = p;
+    stage_copy(slu, lu_of(d, k), d.nnz_f + nx, tid, kRT);
+    stage_copy(skv, d.K + (long long)k * d.nnz_k, d.nnz_k, tid, kRT);
+    for (int j = tid; j < d.nnz_gu; j += kRT) sgu[j] = ev[d.off_gu + d.guc_pos[j]];
+    lu = slu; invd = slu + d.nnz_f; kv = skv; guv = sgu;
+  } else {
+    lu = lu_of(d, k);
+    invd = lu + d.nnz_f;
+    kv = d.K + (long long)k * d.nnz_k;
+    if (kVar == 2) {
+      T = zk + c0;  // solved in place in the stacked panel
+      ldT = d.nu_pad;
+    } else {
+      T = d.panel + ((long long)k * gridDim.x + tile) * 2LL * nx * kW64;
+      Lx = T + (long long)nx * kW64;
+    }
+  }
+  auto bsync = [] { __syncthreads(); };
+  auto gu_val = [&](int j) -> double { return kLDS ? guv[j] : ev[d.off_gu + d.guc_pos[j]]; };
+  // right-hand side -G_u[:, c0 + c] (padding columns: zero)
+  for (int i = wv; i < nx; i += kS64) T[(long long)i * ldT + c] = 0.0;
+  __syncthreads();
+  if (colok)
+    for (int j = d.guc_ptr[col] + wv; j < d.guc_ptr[col + 1]; j += kS64)
+      T[(long long)d.guc_row[j] * ldT + c] = -gu_val(j);
+  __syncthreads();
+  // step 1: T = -G_x^-1 G_u V
+  const int4* uent = static_cast<const int4*>(d.ru_ent);
+  const int4* dent = static_cast<const int4*>(d.rd_ent);
+  // every lane sweeps (barriers stay uniform); lanes past n_u work on
+  // padding columns inside the panel, which nothing reads
+  sweep64<false>(d.ru_ptr, uent, d.nph_u, wv, lu, T, ldT, c, bsync);
+  sweep64<false>(d.rd_ptr, dent, d.nph_d, wv, lu, T, ldT, c, bsync);
+  if (colok)
+    for (int i = wv; i < nx; i += kS64) T[(long long)i * ldT + c] *= invd[i];
+  __syncthreads();
+  // step 2: rows of K, one row per wavefront at a time
+  auto k_row = [&](int r) -> double {
+    double acc = 0.0;
+    const int eu = k_usplit[r], e1 = k_ptr[r + 1];
+    for (int e = eu; e < e1; ++e)
+      if (k_col[e] == nx + col) acc = kv[e];
+    int e = k_ptr[r];
+    double acc2 = 0.0;
+    for (; e + 2 <= eu; e += 2) {
+      acc = fma(kv[e], T[(long long)k_col[e] * ldT + c], acc);
+      acc2 = fma(kv[e + 1], T[(long long)k_col[e + 1] * ldT + c], acc2);
+    }
+    if (e < eu) acc = fma(kv[e], T[(long long)k_col[e] * ldT + c], acc);
+    return acc + acc2;
   };
-  for (int r = wv; r < nx + nu; r += kWideWaves) {
-    const int rr = __builtin_amdgcn_readfirstlane(r);
-    double acc = k_ucol(rr, nx + col);
-    const int e1 = d.k_usplit[rr];
-    for (int e = d.k_ptr[rr]; e < e1; ++e) acc += kv[e] * T[(long long)d.k_col[e] * kWideW + lane];
-    if (rr < nx) Lx[(long long)rr * kWideW + lane] = acc;
-    else if (colok) out[(long long)(rr - nx) * nu + col] = acc;
+  if (kVar == 2) {
+    if (!colok) return;
+    if (kLDS)
+      for (int i = wv; i < nx; i += kS64) zk[(long long)i * d.nu_pad + col] = T[i * kW64 + c];
+    for (int r = wv; r < nz; r += kS64) kzk[(long long)r * d.nu_pad + col] = k_row(r);
+    return;
   }
+  // adjoint: L_x (prescaled by 1/u_ii for the U^T sweep), L_u into part
+  double* out = d.part + (long long)k * nu * nu;
+  if (colok)
+    for (int r = wv; r < nz; r += kS64) {
+      const double acc = k_row(r);
+      if (r < nx) Lx[(long long)r * kW64 + c] = acc * invd[r];
+      else out[(long long)(r - nx) * nu + col] = acc;
+    }
   __syncthreads();
-  wide_sweep<true, false, true>(d, lu, invd, Lx, wv, lane);
-  wide_sweep<true, true, false>(d, lu, invd, Lx, wv, lane);
-  for (int ru = wv; ru < nu; ru += kWideWaves) {
-    const int rr = __builtin_amdgcn_readfirstlane(ru);
-    if (!colok) continue;
-    double acc = out[(long long)rr * nu + col];
-    for (int j = d.guc_ptr[rr]; j < d.guc_ptr[rr + 1]; ++j)
-      acc -= ev[d.off_gu + d.guc_pos[j]] * Lx[(long long)d.guc_row[j] * kWideW + lane];
-    out[(long long)rr * nu + col] = acc;
-  }
+  sweep64<true>(d.ru_ptr, uent, d.nph_u, wv, lu, Lx, kW64, c, bsync);
+  sweep64<true>(d.rd_ptr, dent, d.nph_d, wv, lu, Lx, kW64, c, bsync);
+  if (colok)
+    for (int ru = wv; ru < nu; ru += kS64) {
+      double acc = out[(long long)ru * nu + col];
+      const int j1 = d.guc_ptr[ru + 1];
+      for (int j = d.guc_ptr[ru]; j < j1; ++j) acc = fma(-gu_val(j), Lx[(long long)d.guc_row[j] * kW64 + c], acc);
+      out[(long long)ru * nu + col] = acc;
+    }
 }
 
 // ------------------------------------------------ single-column solves (step)
-// Workspace of a step workgroup: LU values, 1/u_ii and three nx vectors in LDS
-// (with the solve metadata) when they fit, else per-scenario global memory.
-struct StepWs {
-  const double *lu, *invd;
-  double *v0, *v1, *v2;
-  SolveMeta m;
+// LDS mode: one workgroup of kGT threads per scenario stages everything the
+// scenario's step reads (factor and 1/u_ii, K, H and G_u values, the
+// residual vectors, the schedules) in one overlapped pass; the elementwise
+// work uses all threads on LDS data and the triangular sweeps run on
+// wavefront 0 (one slot per lane, wavefront-scope synchronisation).  Global
+// mode: one workgroup of kRT threads per scenario on global data, sweeps on
+// all threads.
+struct StepView {
+  const double *lu, *invd, *Kv, *hv, *guv;
+  const double *ra, *r3, *r2, *r4, *ss, *pu;  // ra: r1x (rhs) or rhat1 (recovery)
+  double *v0, *v1, *v2, *wv;
+  const int *uptr, *dptr;
+  const void *uent, *dent;
 };
 
 template <bool kLDS>
-__device__ __forceinline__ StepWs step_ws(const DP& d, int k, double* smem) {
-  StepWs w;
-  const int nx = d.nx;
+__device__ __forceinline__ StepView step_view(const DP& d, int k, double* smem, const double* ra,
+                                              const double* r3, const double* r2, const double* r4,
+                                              const double* ss, const double* pu) {
+  StepView w;
+  const int nx = d.nx, nf = d.nnz_f, m = d.m;
+  const double* ev = d.EV + (long long)k * d.n_ev;
   if (kLDS) {
     double* p = smem;
-    double* slu = p; copy_in(slu, d.LU + (long long)k * d.nnz_f, d.nnz_f); p += d.nnz_f;
-    double* sid = p; copy_in(sid, d.invd + (long long)k * nx, nx); p += nx;
+    double* lu = p; p += nf + nx;
+    double* kv = p; p += d.nnz_k;
+    double* hv = p; p += d.nnz_h;
+    double* gu = p; p += d.nnz_gu;
+    double* sra = p; p += nx;
+    double* sr3 = p; p += nx;
+    double* sr2 = p; p += m;
+    double* sr4 = p; p += m;
+    double* sss = p; p += m;
+    w.wv = p; p += m;
     w.v0 = p; p += nx;
     w.v1 = p; p += nx;
     w.v2 = p; p += nx;
-    stage_meta(d, reinterpret_cast<int*>(p), w.m);
-    w.lu = slu;
-    w.invd = sid;
+    double* spu = p; p += d.nu;
+    unsigned* ue = reinterpret_cast<unsigned*>(p);
+    unsigned* de = ue + 2 * d.nnz_l;
+    int* ip = reinterpret_cast<int*>(de + 2 * d.nnz_l);
+    w.uptr = ip;
+    w.dptr = ip + d.nph_u * kGroupLds + 1;
+    w.uent = ue;
+    w.dent = de;
+    const int t0 = threadIdx.x, ts = blockDim.x;
+    stage_copy(lu, lu_of(d, k), nf + nx, t0, ts);
+    stage_copy(kv, d.K + (long long)k * d.nnz_k, d.nnz_k, t0, ts);
+    stage_copy(hv, ev + d.off_h, d.nnz_h, t0, ts);
+    stage_copy(gu, ev + d.off_gu, d.nnz_gu, t0, ts);
+    stage_copy(sra, ra + (long long)k * nx, nx, t0, ts);
+    stage_copy(sr3, r3 + (long long)k * nx, nx, t0, ts);
+    stage_copy(sr2, r2 + (long long)k * m, m, t0, ts);
+    stage_copy(sr4, r4 + (long long)k * m, m, t0, ts);
+    stage_copy(sss, ss + (long long)k * m, m, t0, ts);
+    if (pu) stage_copy(spu, pu, d.nu, t0, ts);
+    stage_words(ue, d.blob_stp, d.blob_stp_words, t0, ts);
+    w.lu = lu; w.invd = lu + nf; w.Kv = kv; w.hv = hv; w.guv = gu;
+    w.ra = sra; w.r3 = sr3; w.r2 = sr2; w.r4 = sr4; w.ss = sss; w.pu = spu;
   } else {
-    w.lu = d.LU + (long long)k * d.nnz_f;
-    w.invd = d.invd + (long long)k * nx;
+    w.lu = lu_of(d, k);
+    w.invd = w.lu + nf;
+    w.Kv = d.K + (long long)k * d.nnz_k;
+    w.hv = ev + d.off_h;
+    w.guv = ev + d.off_gu;
+    w.ra = ra + (long long)k * nx;
+    w.r3 = r3 + (long long)k * nx;
+    w.r2 = r2 + (long long)k * m;
+    w.r4 = r4 + (long long)k * m;
+    w.ss = ss + (long long)k * m;
+    w.pu = pu;
     w.v0 = d.panel + (long long)k * 2 * nx;
     w.v1 = w.v0 + nx;
     w.v2 = d.rhat1 + (long long)k * nx;
-    w.m = global_meta(d);
+    w.wv = d.wbuf + (long long)k * m;
+    w.uptr = d.su_ptr; w.dptr = d.sd_ptr; w.uent = d.su_ent; w.dent = d.sd_ent;
   }
   __syncthreads();
   return w;
+}
+
+// X <- G_x^-1 X (internal order) by the sweep group (G threads, slot gl)
+template <bool kLDS, typename Sync>
+__device__ __forceinline__ void solve_fwd(const DP& d, const StepView& w, double* X, int gl, Sync sync) {
+  constexpr int G = kLDS ? kGroupLds : kRT;
+  sweep<kLDS, false>(w.uptr, w.uent, d.nph_u, G, gl, true, w.lu, X, 1, 0, sync);
+  sweep<kLDS, false>(w.dptr, w.dent, d.nph_d, G, gl, true, w.lu, X, 1, 0, sync);
+  for (int i = gl; i < d.nx; i += G) X[i] *= w.invd[i];
+  sync();
+}
+
+// X <- G_x^-T X for X already scaled by 1/u_ii
+template <bool kLDS, typename Sync>
+__device__ __forceinline__ void solve_adj_scaled(const DP& d, const StepView& w, double* X, int gl, Sync sync) {
+  constexpr int G = kLDS ? kGroupLds : kRT;
+  sweep<kLDS, true>(w.uptr, w.uent, d.nph_u, G, gl, true, w.lu, X, 1, 0, sync);
+  sweep<kLDS, true>(w.dptr, w.dent, d.nph_d, G, gl, true, w.lu, X, 1, 0, sync);
+  sync();
+}
+
+// runs a sweep-group solve: wavefront 0 in LDS mode, every thread otherwise
+template <bool kLDS, typename F>
+__device__ __forceinline__ void in_sweep_group(F f) {
+  if (kLDS) {
+    if ((threadIdx.x >> 6) == 0) f(threadIdx.x & 63, [] { wave_sync(); });
+  } else {
+    f(threadIdx.x, [] { __syncthreads(); });
+  }
+  __syncthreads();
 }
 
 // Reduced right-hand side contributions of one scenario (eq. "kkt:reduced"):
 //   rhat1 = r1x + H_x^T (Sigma_s r4 - r2),  q = G_x^-1 r3,
 //   a = G_x^-T (rhat1 - K_xx q),
 //   rpart = -H_u^T (Sigma_s r4 - r2) + G_u^T a + K_ux q
-template <bool kLDS>
-__global__ __launch_bounds__(kThreads) void k_step_rhs(DP d, const double* r1x, const double* r2,
-                                                       const double* r3, const double* r4,
-                                                       const double* ss) {
+template <bool kLDS, int kT>
+__global__ __launch_bounds__(kT) void k_step_rhs(DP d, const double* r1x, const double* r2,
+                                                 const double* r3, const double* r4,
+                                                 const double* ss) {
   extern __shared__ double smem[];
   const int k = blockIdx.x, tid = threadIdx.x;
+  const StepView w = step_view<kLDS>(d, k, smem, r1x, r3, r2, r4, ss, nullptr);
   const int nx = d.nx, nu = d.nu;
-  const StepWs w = step_ws<kLDS>(d, k, smem);
-  const double* Kv = d.K + (long long)k * d.nnz_k;
-  const double* ev = d.EV + (long long)k * d.n_ev;
-  const double* hv = ev + d.off_h;
-  const double* guv = ev + d.off_gu;
-  const double* r2k = r2 + (long long)k * d.m;
-  const double* r4k = r4 + (long long)k * d.m;
-  const double* ssk = ss + (long long)k * d.m;
   double* rh1 = w.v2;  // rhat1; the global copy is kept for the recovery
   double* q = w.v0;
   double* a = w.v1;
   double* grh1 = d.rhat1 + (long long)k * nx;
-  for (int i = tid; i < nx; i += kThreads) {
-    double acc = r1x[(long long)k * nx + d.perm[i]];
-    for (int j = d.ht_ptr[i]; j < d.ht_ptr[i + 1]; ++j) {
-      const int r = d.ht_row[j];
-      acc += hv[d.ht_pos[j]] * (ssk[r] * r4k[r] - r2k[r]);
-    }
+  for (int r = tid; r < d.m; r += kT) w.wv[r] = w.ss[r] * w.r4[r] - w.r2[r];
+  __syncthreads();
+  for (int i = tid; i < nx; i += kT) {
+    const int pi = d.perm[i];
+    double acc = w.ra[pi];
+    const int j1 = d.ht_ptr[i + 1];
+    for (int j = d.ht_ptr[i]; j < j1; ++j) acc = fma(w.hv[d.ht_pos[j]], w.wv[d.ht_row[j]], acc);
     rh1[i] = acc;
-    q[i] = r3[(long long)k * nx + d.perm[i]];
+    q[i] = w.r3[pi];
   }
   __syncthreads();
-  solve_LU(w.m, w.lu, w.invd, q, 1, 0, tid, kThreads, true);
-  for (int i = tid; i < nx; i += kThreads) {
+  in_sweep_group<kLDS>([&](int gl, auto sync) { solve_fwd<kLDS>(d, w, q, gl, sync); });
+  for (int i = tid; i < nx; i += kT) {
     double acc = rh1[i];
-    for (int e = d.k_ptr[i]; e < d.k_usplit[i]; ++e) acc -= Kv[e] * q[d.k_col[e]];
-    a[i] = acc;
+    const int e1 = d.k_usplit[i];
+    for (int e = d.k_ptr[i]; e < e1; ++e) acc = fma(-w.Kv[e], q[d.k_col[e]], acc);
+    a[i] = acc * w.invd[i];
     if (kLDS) grh1[i] = rh1[i];
   }
   __syncthreads();
-  solve_LUt(w.m, w.lu, w.invd, a, 1, 0, tid, kThreads, true);
-  for (int c = tid; c < nu; c += kThreads) {
+  in_sweep_group<kLDS>([&](int gl, auto sync) { solve_adj_scaled<kLDS>(d, w, a, gl, sync); });
+  for (int c = tid; c < nu; c += kT) {
     const int v = nx + c;
     double acc = 0.0;
-    for (int j = d.ht_ptr[v]; j < d.ht_ptr[v + 1]; ++j) {
-      const int r = d.ht_row[j];
-      acc -= hv[d.ht_pos[j]] * (ssk[r] * r4k[r] - r2k[r]);
-    }
-    for (int j = d.guc_ptr[c]; j < d.guc_ptr[c + 1]; ++j) acc += guv[d.guc_pos[j]] * a[d.guc_row[j]];
-    for (int e = d.k_ptr[v]; e < d.k_usplit[v]; ++e) acc += Kv[e] * q[d.k_col[e]];
+    for (int j = d.ht_ptr[v]; j < d.ht_ptr[v + 1]; ++j) acc = fma(-w.hv[d.ht_pos[j]], w.wv[d.ht_row[j]], acc);
+    for (int j = d.guc_ptr[c]; j < d.guc_ptr[c + 1]; ++j) acc = fma(w.guv[d.guc_pos[j]], a[d.guc_row[j]], acc);
+    for (int e = d.k_ptr[v]; e < d.k_usplit[v]; ++e) acc = fma(w.Kv[e], q[d.k_col[e]], acc);
     d.rpart[(long long)k * nu + c] = acc;
   }
 }
@@ -480,53 +716,56 @@ __global__ __launch_bounds__(kThreads) void k_step_rhs(DP d, const double* r1x, 
 // Recovery of one scenario (propositions "Reduction" and "Condensed KKT system"):
 //   p_x = -G_x^-1 (r3 + G_u p_u), p_y = -G_x^-T (rhat1 + K_xx p_x + K_xu p_u),
 //   p_s = -(r4 + H p_d), p_z = Sigma_s (H p_d + r4) - r2
-template <bool kLDS>
-__global__ __launch_bounds__(kThreads) void k_step_recover(DP d, const double* r2, const double* r3,
-                                                           const double* r4, const double* ss,
-                                                           const double* pu, double* px, double* ps,
-                                                           double* py, double* pz) {
+template <bool kLDS, int kT>
+__global__ __launch_bounds__(kT) void k_step_recover(DP d, const double* r2, const double* r3,
+                                                     const double* r4, const double* ss,
+                                                     const double* pu, double* px, double* ps,
+                                                     double* py, double* pz) {
   extern __shared__ double smem[];
   const int k = blockIdx.x, tid = threadIdx.x;
+  const StepView w = step_view<kLDS>(d, k, smem, d.rhat1, r3, r2, r4, ss, pu);
   const int nx = d.nx;
-  const StepWs w = step_ws<kLDS>(d, k, smem);
-  const double* Kv = d.K + (long long)k * d.nnz_k;
-  const double* ev = d.EV + (long long)k * d.n_ev;
-  const double* hv = ev + d.off_h;
-  const double* guv = ev + d.off_gu;
-  const double* rh1 = d.rhat1 + (long long)k * nx;
   double* xv = w.v0;
   double* yv = w.v1;
-  for (int i = tid; i < nx; i += kThreads) {
-    double acc = r3[(long long)k * nx + d.perm[i]];
-    for (int e = d.gu_ptr[i]; e < d.gu_ptr[i + 1]; ++e) acc += guv[e] * pu[d.gu_col[e]];
+  for (int i = tid; i < nx; i += kT) {
+    double acc = w.r3[d.perm[i]];
+    const int e1 = d.gu_ptr[i + 1];
+    for (int e = d.gu_ptr[i]; e < e1; ++e) acc = fma(w.guv[e], w.pu[d.gu_col[e]], acc);
     xv[i] = -acc;
   }
   __syncthreads();
-  solve_LU(w.m, w.lu, w.invd, xv, 1, 0, tid, kThreads, true);
-  for (int i = tid; i < nx; i += kThreads) {
+  in_sweep_group<kLDS>([&](int gl, auto sync) { solve_fwd<kLDS>(d, w, xv, gl, sync); });
+  for (int i = tid; i < nx; i += kT) {
     px[(long long)k * nx + d.perm[i]] = xv[i];
-    double acc = rh1[i];
-    for (int e = d.k_ptr[i]; e < d.k_ptr[i + 1]; ++e) {
+    double acc = w.ra[i];
+    const int e1 = d.k_ptr[i + 1];
+    for (int e = d.k_ptr[i]; e < e1; ++e) {
       const int cc = d.k_col[e];
-      acc += Kv[e] * (cc < nx ? xv[cc] : pu[cc - nx]);
+      acc = fma(w.Kv[e], cc < nx ? xv[cc] : w.pu[cc - nx], acc);
     }
-    yv[i] = -acc;
+    yv[i] = -acc * w.invd[i];
   }
   __syncthreads();
-  solve_LUt(w.m, w.lu, w.invd, yv, 1, 0, tid, kThreads, true);
-  for (int i = tid; i < nx; i += kThreads) py[(long long)k * nx + d.perm[i]] = yv[i];
-  const double* r2k = r2 + (long long)k * d.m;
-  const double* r4k = r4 + (long long)k * d.m;
-  const double* ssk = ss + (long long)k * d.m;
-  for (int r = tid; r < d.m; r += kThreads) {
+  in_sweep_group<kLDS>([&](int gl, auto sync) { solve_adj_scaled<kLDS>(d, w, yv, gl, sync); });
+  for (int i = tid; i < nx; i += kT) py[(long long)k * nx + d.perm[i]] = yv[i];
+  for (int r = tid; r < d.m; r += kT) {
     double hp = 0.0;
-    for (int e = d.h_ptr[r]; e < d.h_ptr[r + 1]; ++e) {
+    const int e1 = d.h_ptr[r + 1];
+    for (int e = d.h_ptr[r]; e < e1; ++e) {
       const int cc = d.h_col[e];
-      hp += hv[e] * (cc < nx ? xv[cc] : pu[cc - nx]);
+      hp = fma(w.hv[e], cc < nx ? xv[cc] : w.pu[cc - nx], hp);
     }
-    ps[(long long)k * d.m + r] = -(r4k[r] + hp);
-    pz[(long long)k * d.m + r] = ssk[r] * (hp + r4k[r]) - r2k[r];
+    ps[(long long)k * d.m + r] = -(w.r4[r] + hp);
+    pz[(long long)k * d.m + r] = w.ss[r] * (hp + w.r4[r]) - w.r2[r];
   }
+}
+
+// rows nx .. nz of every scenario block of the stacked Z are the identity
+__global__ void k_identity_rows(DP d) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)d.N * d.nu) return;
+  const int k = (int)(t / d.nu), j = (int)(t % d.nu);
+  d.Zst[((long long)k * d.nz + d.nx + j) * d.nu_pad + j] = 1.0;
 }
 
 hipError_t allow_lds(const void* fn, int* cur, long long need) {
@@ -536,53 +775,88 @@ hipError_t allow_lds(const void* fn, int* cur, long long need) {
   return e;
 }
 
+int ntiles(const DP& d) { return (d.nu + d.col_tile - 1) / d.col_tile; }
+
 }  // namespace
 
 hipError_t configure_lu_kernels(const DP& d) {
-  static int c1 = 0, c2 = 0, c3 = 0, c4 = 0;
-  if (!d.lds) return hipSuccess;
+  static int c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0, c6 = 0, c7 = 0, c8 = 0;
   const LdsSizes z = sizes_of(d);
-  hipError_t e = allow_lds((const void*)k_refactor<true, kThreads>, &c1, refactor_lds_bytes(z));
-  if (e == hipSuccess) e = allow_lds((const void*)k_reduce<true>, &c2, reduce_lds_bytes(z));
-  if (e == hipSuccess) e = allow_lds((const void*)k_step_rhs<true>, &c3, step_lds_bytes(z));
-  if (e == hipSuccess) e = allow_lds((const void*)k_step_recover<true>, &c4, step_lds_bytes(z));
+  hipError_t e = hipSuccess;
+  if (d.lds_grp) {
+    if (d.upd_lds) e = allow_lds((const void*)k_refactor<true, kGT, true>, &c1, refactor_lds_bytes(z));
+    else e = allow_lds((const void*)k_refactor<true, kGT, false>, &c6, refactor_lds_bytes(z));
+  }
+  if (e == hipSuccess && d.lds_stp) {
+    e = allow_lds((const void*)k_step_rhs<true, kGT>, &c3, step_lds_bytes(z));
+    if (e == hipSuccess) e = allow_lds((const void*)k_step_recover<true, kGT>, &c4, step_lds_bytes(z));
+  }
+  if (e == hipSuccess && d.lds_red) {
+    if (d.col_tile == kW64) {
+      if (d.variant == 2) e = allow_lds((const void*)k_reduce64<true, 2>, &c7, reduce_lds_bytes(z));
+      else e = allow_lds((const void*)k_reduce64<true, 1>, &c8, reduce_lds_bytes(z));
+    } else {
+      if (d.variant == 2) e = allow_lds((const void*)k_reduce<true, 2>, &c5, reduce_lds_bytes(z));
+      else e = allow_lds((const void*)k_reduce<true, 1>, &c2, reduce_lds_bytes(z));
+    }
+  }
   return e;
 }
 
+void launch_identity_rows(const DP& d, hipStream_t s) {
+  const long long n = (long long)d.N * d.nu;
+  k_identity_rows<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(d);
+}
+
 void launch_refactor(const DP& d, hipStream_t s) {
-  if (d.lds)
-    k_refactor<true, kThreads><<<d.N, kThreads, refactor_lds_bytes(sizes_of(d)), s>>>(d);
+  const unsigned grid = (d.N + d.spw - 1) / d.spw;
+  const size_t lds = refactor_lds_bytes(sizes_of(d));
+  if (d.lds_grp && d.upd_lds)
+    k_refactor<true, kGT, true><<<grid, kGroupLds * d.spw, lds, s>>>(d);
+  else if (d.lds_grp)
+    k_refactor<true, kGT, false><<<grid, kGroupLds * d.spw, lds, s>>>(d);
   else
-    k_refactor<false, kRefactorWideThreads><<<d.N, kRefactorWideThreads, 0, s>>>(d);
+    k_refactor<false, kRT, false><<<d.N, kRT, 0, s>>>(d);
 }
 
 void launch_reduce(const DP& d, hipStream_t s) {
-  const int ntile = (d.nu + d.col_tile - 1) / d.col_tile;
-  dim3 grid(ntile, d.N);
-  if (d.lds)
-    k_reduce<true><<<grid, kThreads, reduce_lds_bytes(sizes_of(d)), s>>>(d);
-  else if (d.col_tile == kWideW)
-    k_reduce_wide<<<grid, kWideThreads, 0, s>>>(d);
-  else
-    k_reduce<false><<<grid, kThreads, 0, s>>>(d);
+  dim3 grid(ntiles(d), d.N);
+  const size_t lds = d.lds_red ? reduce_lds_bytes(sizes_of(d)) : 0;
+  if (d.col_tile == kW64) {
+    if (d.variant == 2) {
+      if (d.lds_red) k_reduce64<true, 2><<<grid, kRT, lds, s>>>(d);
+      else k_reduce64<false, 2><<<grid, kRT, 0, s>>>(d);
+    } else {
+      if (d.lds_red) k_reduce64<true, 1><<<grid, kRT, lds, s>>>(d);
+      else k_reduce64<false, 1><<<grid, kRT, 0, s>>>(d);
+    }
+    return;
+  }
+  if (d.variant == 2) {
+    if (d.lds_red) k_reduce<true, 2><<<grid, kRT, lds, s>>>(d);
+    else k_reduce<false, 2><<<grid, kRT, 0, s>>>(d);
+  } else {
+    if (d.lds_red) k_reduce<true, 1><<<grid, kRT, lds, s>>>(d);
+    else k_reduce<false, 1><<<grid, kRT, 0, s>>>(d);
+  }
 }
 
 void launch_step_rhs(const DP& d, const double* r1x, const double* r2, const double* r3,
                      const double* r4, const double* ss, hipStream_t s) {
-  if (d.lds)
-    k_step_rhs<true><<<d.N, kThreads, step_lds_bytes(sizes_of(d)), s>>>(d, r1x, r2, r3, r4, ss);
+  if (d.lds_stp)
+    k_step_rhs<true, kGT><<<d.N, kGT, step_lds_bytes(sizes_of(d)), s>>>(d, r1x, r2, r3, r4, ss);
   else
-    k_step_rhs<false><<<d.N, kThreads, 0, s>>>(d, r1x, r2, r3, r4, ss);
+    k_step_rhs<false, kRT><<<d.N, kRT, 0, s>>>(d, r1x, r2, r3, r4, ss);
 }
 
 void launch_step_recover(const DP& d, const double* r2, const double* r3, const double* r4,
                          const double* ss, const double* pu, double* px, double* ps, double* py,
                          double* pz, hipStream_t s) {
-  if (d.lds)
-    k_step_recover<true><<<d.N, kThreads, step_lds_bytes(sizes_of(d)), s>>>(
-        d, r2, r3, r4, ss, pu, px, ps, py, pz);
+  if (d.lds_stp)
+    k_step_recover<true, kGT><<<d.N, kGT, step_lds_bytes(sizes_of(d)), s>>>(d, r2, r3, r4, ss, pu, px,
+                                                                           ps, py, pz);
   else
-    k_step_recover<false><<<d.N, kThreads, 0, s>>>(d, r2, r3, r4, ss, pu, px, ps, py, pz);
+    k_step_recover<false, kRT><<<d.N, kRT, 0, s>>>(d, r2, r3, r4, ss, pu, px, ps, py, pz);
 }
 
 }  // namespace rkkt

@@ -23,36 +23,51 @@ namespace rkkt {
 
 // Sizes that fix the LDS layouts of the level-scheduled kernels.
 struct LdsSizes {
-  int nx, nu, nz, nnz_f, nnz_k, nnz_gu, nlu, nld, w;
+  int nx, nu, nz, nnz_f, nnz_k, nnz_gu, nnz_l, nlu, nph_u, nph_d, n_upd, w, variant, spw;
+  int upd_lds;  // refactorisation update targets staged in LDS (else read from global)
+  int nnz_h, m;
 };
 
-// Local reduction workgroup (one scenario, one tile of w columns):
-// doubles lu[nnz_f] invd[nx] kv[nnz_k] guv[nnz_gu] T[nx w] Lx[nx w], then
-// ints f_ptr[nx+1] f_diag[nx] f_col[nnz_f] f_tpos[nnz_f] lvu_ptr[nlu+1]
-// lvu_rows[nx] lvd_ptr[nld+1] lvd_rows[nx] k_ptr[nz+1] k_usplit[nz]
-// k_col[nnz_k] guc_ptr[nu+1] guc_row[nnz_gu].
+constexpr int kRedThreads = 1024;  // reduction workgroup
+constexpr int kGroupLds = 64;      // threads per scenario in the LDS-mode refactor / step
+
+__host__ __device__ inline int red_slots(const LdsSizes& z) { return kRedThreads / z.w; }
+
+// Local reduction workgroup (one scenario, one tile of w columns): doubles
+// lu[nnz_f] invd[nx] kv[nnz_k] guv[nnz_gu] T[nx w] (adjoint variant also
+// Lx[nx w]); then packed entries of both solve schedules (2 words each),
+// their pointer tables, k_ptr[nz+1] k_usplit[nz] k_col[nnz_k] guc_ptr[nu+1]
+// guc_row[nnz_gu].
 __host__ __device__ inline long long reduce_lds_doubles(const LdsSizes& z) {
-  return (long long)z.nnz_f + z.nx + z.nnz_k + z.nnz_gu + 2LL * z.nx * z.w;
-}
-__host__ __device__ inline long long solve_meta_ints(const LdsSizes& z) {
-  return (long long)(z.nx + 1) + z.nx + 2LL * z.nnz_f + (z.nlu + 1) + z.nx + (z.nld + 1) + z.nx;
+  return (long long)z.nnz_f + z.nx + z.nnz_k + z.nnz_gu + (z.variant == 2 ? 1LL : 2LL) * z.nx * z.w;
 }
 __host__ __device__ inline long long reduce_lds_ints(const LdsSizes& z) {
-  return solve_meta_ints(z) + (z.nz + 1) + z.nz + z.nnz_k + (z.nu + 1) + z.nnz_gu;
+  const long long S = red_slots(z);
+  return 4LL * z.nnz_l + (z.nph_u * S + 1) + (z.nph_d * S + 1) + (z.nz + 1) + z.nz + z.nnz_k +
+         (z.nu + 1) + z.nnz_gu + 2;  // + padding to whole 8-byte units
 }
+// With 64-column tiles the schedule and the K pattern are read from global
+// memory (scalar loads) and only the doubles are staged.
 __host__ __device__ inline long long reduce_lds_bytes(const LdsSizes& z) {
+  if (z.w == 64) return 8 * reduce_lds_doubles(z);
   return 8 * reduce_lds_doubles(z) + 4 * reduce_lds_ints(z);
 }
-// Refactorisation workgroup: doubles lu[nnz_f] invd[nx] rmax[nx], ints
-// f_ptr f_diag f_col lvu_ptr lvu_rows and 4 column maps of nx.
+// Refactorisation workgroup (spw scenarios, one wavefront each): per scenario
+// doubles lu[nnz_f] invd[nx] rmax[nx]; shared packed items (2 words each),
+// their pointer table, lvu_ptr lvu_rows f_diag f_ptr, and the update targets
+// when upd_lds.
 __host__ __device__ inline long long refactor_lds_bytes(const LdsSizes& z) {
-  return 8LL * (z.nnz_f + 2LL * z.nx) +
-         4LL * ((z.nx + 1) + z.nx + z.nnz_f + (z.nlu + 1) + z.nx + 4LL * z.nx);
+  return 8LL * z.spw * (z.nnz_f + 2LL * z.nx) +
+         4LL * (2LL * z.nnz_l + (z.nph_u * (long long)kGroupLds + 1) + (z.nlu + 1) + z.nx + z.nx +
+                (z.nx + 1) + (z.upd_lds ? (long long)z.n_upd : 0LL) + 2);
 }
-// Single-column step workgroup: doubles lu invd and three nx vectors, then the
-// solve metadata.
+// Single-column step workgroup (one scenario): doubles lu[nnz_f] invd[nx]
+// K[nnz_k] H[nnz_h] G_u[nnz_gu] ra[nx] r3[nx] r2[m] r4[m] ss[m] w[m] v0 v1
+// v2 [nx each] pu[nu]; then packed entries of both solve schedules and their
+// pointer tables.
 __host__ __device__ inline long long step_lds_bytes(const LdsSizes& z) {
-  return 8LL * (z.nnz_f + 4LL * z.nx) + 4 * solve_meta_ints(z);
+  return 8LL * ((long long)z.nnz_f + z.nx + z.nnz_k + z.nnz_h + z.nnz_gu + 5LL * z.nx + 4LL * z.m + z.nu) +
+         4LL * (4LL * z.nnz_l + (z.nph_u * (long long)kGroupLds + 1) + (z.nph_d * (long long)kGroupLds + 1) + 2);
 }
 
 }  // namespace rkkt

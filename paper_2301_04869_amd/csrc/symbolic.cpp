@@ -8,6 +8,7 @@
 #include <limits>
 #include <map>
 #include <numeric>
+#include <queue>
 #include <set>
 #include <tuple>
 #include <utility>
@@ -72,18 +73,147 @@ int find_pos(const std::vector<int>& ptr, const std::vector<int>& col, int row, 
   return (int)(it - col.begin());
 }
 
+
+// Assigns the tasks of one phase to S slots, longest first to the least
+// loaded slot (ties to the lowest slot), and returns each slot's task list.
+void assign_tasks(const std::vector<long long>& cost, int S, std::vector<std::vector<int>>& slot_tasks) {
+  std::vector<int> order(cost.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  for (auto& v : slot_tasks) v.clear();
+  using Item = std::pair<long long, int>;
+  std::priority_queue<Item, std::vector<Item>, std::greater<Item>> heap;
+  for (int t = 0; t < S; ++t) heap.push({0, t});
+  for (int t : order) {
+    Item it = heap.top();
+    heap.pop();
+    slot_tasks[it.second].push_back(t);
+    heap.push({it.first + cost[t], it.second});
+  }
+}
+
+// Sources of the level-sliced pulls of one direction: for every row j, the
+// rows i that read it, with the position of (i, j).  Up: (i, j) in the strict
+// lower part (j < i); down: in the strict upper part (j > i).
+std::vector<std::vector<std::pair<int, int>>> dependents(const Sym& s, bool up) {
+  std::vector<std::vector<std::pair<int, int>>> dep(s.nx);
+  for (int i = 0; i < s.nx; ++i) {
+    const int e0 = up ? s.f_ptr[i] : s.f_diag[i] + 1;
+    const int e1 = up ? s.f_diag[i] : s.f_ptr[i + 1];
+    for (int e = e0; e < e1; ++e) dep[s.f_col[e]].push_back({i, e});
+  }
+  return dep;
+}
+
+// Tasks of phase q: (dest, source, position) sorted by dest then source,
+// split into runs of one dest.
+void phase_tasks(const Sym& s, const std::vector<std::vector<std::pair<int, int>>>& dep,
+                 const std::vector<int>& lv_ptr, const std::vector<int>& lv_rows, int q,
+                 std::vector<std::array<int, 3>>& items, std::vector<std::pair<int, int>>& tasks) {
+  items.clear();
+  tasks.clear();
+  for (int r = lv_ptr[q]; r < lv_ptr[q + 1]; ++r) {
+    const int j = lv_rows[r];
+    for (auto& d : dep[j]) items.push_back({d.first, j, d.second});
+  }
+  std::sort(items.begin(), items.end());
+  for (size_t a = 0; a < items.size();) {
+    size_t b = a;
+    while (b < items.size() && items[b][0] == items[a][0]) ++b;
+    tasks.push_back({(int)a, (int)b});
+    a = b;
+  }
+  (void)s;
+}
+
+void build_solve_sched(const Sym& s, bool up, int S, Sched& out) {
+  const std::vector<int>& lv_ptr = up ? s.lvu_ptr : s.lvd_ptr;
+  const std::vector<int>& lv_rows = up ? s.lvu_rows : s.lvd_rows;
+  const auto dep = dependents(s, up);
+  out = Sched();
+  out.S = S;
+  out.nphase = std::max(0, (int)lv_ptr.size() - 2);
+  out.ptr.assign(1, 0);
+  std::vector<std::array<int, 3>> items;
+  std::vector<std::pair<int, int>> tasks;
+  std::vector<std::vector<int>> slot_tasks(S);
+  std::vector<long long> cost;
+  for (int q = 0; q < out.nphase; ++q) {
+    phase_tasks(s, dep, lv_ptr, lv_rows, q, items, tasks);
+    cost.resize(tasks.size());
+    for (size_t t = 0; t < tasks.size(); ++t) cost[t] = tasks[t].second - tasks[t].first;
+    assign_tasks(cost, S, slot_tasks);
+    for (int sl = 0; sl < S; ++sl) {
+      for (int t : slot_tasks[sl])
+        for (int a = tasks[t].first; a < tasks[t].second; ++a) {
+          const int pos = items[a][2];
+          out.ent.insert(out.ent.end(), {items[a][0], items[a][1], pos, s.f_tpos[pos]});
+        }
+      out.ptr.push_back((int)(out.ent.size() / 4));
+    }
+  }
+}
+
+// Refactorisation items: the entry l_ik of row i, taken when row k (level q)
+// is final, costs one multiply by 1/u_kk and one update of row i per entry of
+// the U part of row k.  upd receives, per item, the positions of (i, j) for
+// the U columns j of row k in order.
+std::string build_fac_sched(const Sym& s, int S, Sched& out, std::vector<int>& upd) {
+  const auto dep = dependents(s, true);
+  out = Sched();
+  out.S = S;
+  out.nphase = std::max(0, (int)s.lvu_ptr.size() - 2);
+  out.ptr.assign(1, 0);
+  upd.clear();
+  std::vector<std::array<int, 3>> items;
+  std::vector<std::pair<int, int>> tasks;
+  std::vector<std::vector<int>> slot_tasks(S);
+  std::vector<long long> cost;
+  for (int q = 0; q < out.nphase; ++q) {
+    phase_tasks(s, dep, s.lvu_ptr, s.lvu_rows, q, items, tasks);
+    cost.assign(tasks.size(), 0);
+    for (size_t t = 0; t < tasks.size(); ++t)
+      for (int a = tasks[t].first; a < tasks[t].second; ++a) {
+        const int k = items[a][1];
+        cost[t] += 1 + (s.f_ptr[k + 1] - s.f_diag[k] - 1);
+      }
+    assign_tasks(cost, S, slot_tasks);
+    for (int sl = 0; sl < S; ++sl) {
+      for (int t : slot_tasks[sl])
+        for (int a = tasks[t].first; a < tasks[t].second; ++a) {
+          const int i = items[a][0], k = items[a][1], pos = items[a][2];
+          const int ulen = s.f_ptr[k + 1] - s.f_diag[k] - 1;
+          out.ent.insert(out.ent.end(), {pos, s.f_diag[k], ulen, (int)upd.size()});
+          for (int e = s.f_diag[k] + 1; e < s.f_ptr[k + 1]; ++e) {
+            const int tgt = find_pos(s.f_ptr, s.f_col, i, s.f_col[e]);
+            if (tgt < 0) return "internal: filled pattern not closed under elimination";
+            upd.push_back(tgt);
+          }
+        }
+      out.ptr.push_back((int)(out.ent.size() / 4));
+    }
+  }
+  return "";
+}
 }  // namespace
 
-LdsSizes lds_sizes(const Sym& s, int w) {
+LdsSizes lds_sizes(const Sym& s, int w, int variant, int spw) {
   LdsSizes z;
   z.nx = s.nx; z.nu = s.nu; z.nz = s.nz;
   z.nnz_f = (int)s.f_col.size(); z.nnz_k = (int)s.k_col.size(); z.nnz_gu = (int)s.gu_col.size();
-  z.nlu = (int)s.lvu_ptr.size() - 1; z.nld = (int)s.lvd_ptr.size() - 1;
-  z.w = w;
+  z.nnz_l = s.nnz_l;
+  z.nlu = (int)s.lvu_ptr.size() - 1;
+  z.nph_u = std::max(0, z.nlu - 1);
+  z.nph_d = std::max(0, (int)s.lvd_ptr.size() - 2);
+  z.n_upd = (int)(s.lu_flops - s.nnz_l);
+  z.w = w; z.variant = variant; z.spw = spw;
+  z.upd_lds = s.upd_lds ? 1 : 0;
+  z.nnz_h = (int)s.h_col.size(); z.m = s.m;
   return z;
 }
 
-std::string build_symbolic(const rkkt_network& net, int N, int col_tile_req, Sym& s) {
+std::string build_symbolic(const rkkt_network& net, int N, int col_tile_req, int variant_req,
+                           Sym& s) {
   char msg[256];
   const int nb = net.n_bus, nl = net.n_line, ng = net.n_gen, nload = net.n_load;
   if (nb < 2 || nl < 1 || ng < 1 || nload < 0 || N < 1) return "bad sizes";
@@ -252,62 +382,8 @@ std::string build_symbolic(const rkkt_network& net, int N, int col_tile_req, Sym
     }
   }
 
-  // ---- level-sliced pull structures
-  {
-    auto build = [&](bool up, std::vector<int>& lptr, std::vector<int>& desc, std::vector<int>& src,
-                     std::vector<int>& pos, std::vector<int>& tpos) {
-      const std::vector<int>& lv_ptr = up ? s.lvu_ptr : s.lvd_ptr;
-      const std::vector<int>& lv_rows = up ? s.lvu_rows : s.lvd_rows;
-      const int nlev = (int)lv_ptr.size() - 1;
-      // column lists: for every source j, the (dest i, position of (i, j))
-      std::vector<std::vector<std::pair<int, int>>> col(nx);
-      for (int i = 0; i < nx; ++i) {
-        const int e0 = up ? s.f_ptr[i] : s.f_diag[i] + 1;
-        const int e1 = up ? s.f_diag[i] : s.f_ptr[i + 1];
-        for (int e = e0; e < e1; ++e) col[s.f_col[e]].push_back({i, e});
-      }
-      lptr.assign(1, 0);
-      std::vector<std::tuple<int, int, int>> items;  // (dest, src, pos)
-      for (int q = 0; q < nlev; ++q) {
-        items.clear();
-        for (int r = lv_ptr[q]; r < lv_ptr[q + 1]; ++r) {
-          const int j = lv_rows[r];
-          for (auto& ip : col[j]) items.emplace_back(ip.first, j, ip.second);
-        }
-        std::sort(items.begin(), items.end());
-        size_t a = 0;
-        while (a < items.size()) {
-          size_t b = a;
-          while (b < items.size() && std::get<0>(items[b]) == std::get<0>(items[a])) ++b;
-          desc.push_back(std::get<0>(items[a]));
-          desc.push_back((int)src.size());
-          for (size_t t = a; t < b; ++t) {
-            src.push_back(std::get<1>(items[t]));
-            pos.push_back(std::get<2>(items[t]));
-            tpos.push_back(s.f_tpos[std::get<2>(items[t])]);
-          }
-          desc.push_back((int)src.size());
-          desc.push_back(0);
-          a = b;
-        }
-        lptr.push_back((int)desc.size() / 4);
-      }
-    };
-    build(true, s.up_lptr, s.up_desc, s.up_src, s.up_pos, s.up_tpos);
-    build(false, s.dn_lptr, s.dn_desc, s.dn_src, s.dn_pos, s.dn_tpos);
-    // refactorisation targets of every up entry
-    s.upd_ptr.assign(1, 0);
-    for (size_t e = 0; e < s.up_src.size(); ++e) {
-      const int k = s.up_src[e];
-      const int i = s.f_col[s.f_tpos[s.up_pos[e]]];  // column of (k, i) is i
-      for (int q = s.f_diag[k] + 1; q < s.f_ptr[k + 1]; ++q) {
-        const int t = find_pos(s.f_ptr, s.f_col, i, s.f_col[q]);
-        if (t < 0) return "internal: filled pattern not closed under elimination";
-        s.upd_dst.push_back(t);
-      }
-      s.upd_ptr.push_back((int)s.upd_dst.size());
-    }
-  }
+  s.nnz_l = 0;
+  for (int i = 0; i < nx; ++i) s.nnz_l += s.f_diag[i] - s.f_ptr[i];
 
   // ---- internal z index of the locals of every line
   auto zvar = [&](int b, int which) -> int {
@@ -540,23 +616,70 @@ std::string build_symbolic(const rkkt_network& net, int N, int col_tile_req, Sym
     }
   }
 
-  // column tile of the reduction: the fewest tiles whose workgroup fits in
-  // LDS (one workgroup per CU); global-memory panels of 64 columns otherwise
+  // ---- launch shapes.  Packed 16-bit schedule entries need every index
+  // below 2^16, which holds whenever the data they index fits in LDS.
   const long long lds_max = 160 * 1024;
-  if (col_tile_req > 0) {
-    s.col_tile = col_tile_req;
-  } else {
-    s.col_tile = 0;
+  const bool pack_ok = nx < 65536 && s.f_col.size() < 65536 && s.lu_flops < 65536;
+  // refactorisation and step: up to 4 scenarios per workgroup, one
+  // wavefront each, when a scenario's LU values and vectors fit in LDS
+  s.spw = 0;
+  for (int spw : {4, 2, 1}) {
+    for (int staged : {1, 0}) {
+      s.upd_lds = staged;
+      if (pack_ok && refactor_lds_bytes(lds_sizes(s, 1, 1, spw)) <= lds_max) {
+        s.spw = spw;
+        break;
+      }
+    }
+    if (s.spw) break;
+  }
+  s.lds_group = s.spw > 0;
+  if (!s.lds_group) s.spw = 1;
+  s.group = s.lds_group ? kGroupLds : kRedThreads;
+  s.lds_step = pack_ok && step_lds_bytes(lds_sizes(s, 1, 1, 1)) <= lds_max;
+  s.step_group = s.lds_step ? kGroupLds : kRedThreads;
+  // reduction: the fewest column tiles whose workgroup fits in LDS, else
+  // panels of 64 columns in global memory
+  if (variant_req < 0 || variant_req > 2) return "variant must be 0, 1 or 2";
+  if (col_tile_req < 0 || col_tile_req > 64) return "col_tile must be in [0, 64]";
+  auto fits = [&](int w, int v) { return pack_ok && reduce_lds_bytes(lds_sizes(s, w, v, 1)) <= lds_max; };
+  auto pick_tile = [&](int v) {
+    if (nu > 32 && fits(64, v)) return 64;  // one slot per wavefront
     for (int tiles = 1; tiles <= 64 && tiles <= nu; ++tiles) {
       const int w = (nu + tiles - 1) / tiles;
-      if (w > 64) continue;
-      if (reduce_lds_bytes(lds_sizes(s, w)) <= lds_max) { s.col_tile = w; break; }
+      if (w <= 64 && fits(w, v)) return w;
     }
-    if (s.col_tile == 0) s.col_tile = 64;
+    return 0;
+  };
+  if (variant_req == 0) s.variant = pick_tile(2) > 0 ? 2 : 1;  // stacked product when it stays on chip
+  else s.variant = variant_req;
+  if (col_tile_req > 0) s.col_tile = std::min(col_tile_req, nu);
+  else {
+    s.col_tile = pick_tile(s.variant);
+    if (s.col_tile == 0) s.col_tile = std::min(64, nu);
   }
-  const LdsSizes z = lds_sizes(s, s.col_tile);
-  s.lds_resident = reduce_lds_bytes(z) <= lds_max && refactor_lds_bytes(z) <= lds_max &&
-                   step_lds_bytes(z) <= lds_max;
+  s.lds_reduce = fits(s.col_tile, s.variant);
+  s.lds_resident = s.lds_reduce && s.lds_group && s.lds_step;
+  // stacked panels of the product variant: rows (x rows then u rows) of every
+  // scenario, columns padded to a multiple of 64 (the reduction's widest tile)
+  s.nu_pad = (nu + 63) / 64 * 64;
+  {
+    const long long rows = (long long)N * s.nz;
+    const int T = s.nu_pad / 32;
+    const long long tiles = (long long)T * (T + 1) / 2;
+    long long nc = std::max(1LL, 512 / tiles);
+    nc = std::min(nc, std::max(1LL, rows / 256));
+    s.nchunk = (int)nc;
+  }
+  // schedules
+  build_solve_sched(s, true, kRedThreads / s.col_tile, s.red_up);
+  build_solve_sched(s, false, kRedThreads / s.col_tile, s.red_dn);
+  build_solve_sched(s, true, s.step_group, s.stp_up);
+  build_solve_sched(s, false, s.step_group, s.stp_dn);
+  {
+    std::string m = build_fac_sched(s, s.group, s.fac, s.upd_dst);
+    if (!m.empty()) return m;
+  }
   return "";
 }
 

@@ -14,11 +14,28 @@
 
 namespace rkkt {
 
+// Level-sliced schedule of a triangular sweep over S slots.  Phase q starts
+// once the rows of level q are final; every task of the phase is one
+// dependent row together with its entries whose source row lies in level q,
+// and a slot runs its tasks of the phase one after another.  The entries of
+// (phase q, slot t) are ent[4 ptr[q S + t] .. 4 ptr[q S + t + 1]); solve
+// entries are (dest row, source row, position of (dest, source) in the filled
+// pattern, position of (source, dest)); refactorisation entries are (position
+// of l_ik, position of u_kk, length of the U part of row k, first update
+// target in upd_dst).
+struct Sched {
+  int S = 0, nphase = 0;
+  std::vector<int> ptr, ent;
+};
+
 struct Sym {
   int nb = 0, nl = 0, ng = 0, nload = 0, ref = 0, gref = 0;
   int nx = 0, nu = 0, m = 0, nz = 0, N = 0;
   int col_tile = 0;
-  bool lds_resident = true;
+  bool lds_resident = true;  // every level-scheduled kernel keeps its data in LDS
+  bool lds_reduce = true;    // the reduction's panels and factors sit in LDS
+  bool lds_group = true;     // the refactorisation keeps its scenarios in LDS
+  bool lds_step = true;      // the step keeps its scenario in LDS
 
   // internal x order: xhat = perm applied to the external order
   std::vector<int> perm;  // perm[ihat] = i_ext
@@ -73,25 +90,28 @@ struct Sym {
   std::vector<int> lvu_ptr, lvu_rows, lvd_ptr, lvd_rows;
   long long lu_flops = 0;
 
-  // Level-sliced pulls.  Direction "up" (L and U^T solves, the refactorisation):
-  // when the rows of up-level q are final, every row i with an L entry (i, j),
-  // j in level q, pulls those entries.  Direction "down" (U and L^T solves):
-  // rows j of down-level q are pulled by every row i < j with a U entry (i, j).
-  // Per direction: lptr[nlev+1] -> descriptors; desc[4 d .. 4 d+3] =
-  // (dest row, first entry, end entry, 0); per entry: src row, position of
-  // (dest, src) in F and of (src, dest) in F.
-  std::vector<int> up_lptr, up_desc, up_src, up_pos, up_tpos;
-  std::vector<int> dn_lptr, dn_desc, dn_src, dn_pos, dn_tpos;
-  // refactorisation updates of every up entry e = (i, k): the targets in row i
-  // of the U part of row k, in order: upd_dst[upd_ptr[e] + t] is the position
-  // of (i, j_t), j_t the t-th U column of row k
-  std::vector<int> upd_ptr, upd_dst;
+  int nnz_l = 0;  // strictly lower entries of the filled pattern (= strictly upper)
+
+  // Level-sliced schedules (see Sched): the reduction's solves (S = 1024 /
+  // col_tile slots), the single-column solves of the step and the
+  // refactorisation items (S = threads per scenario group: 64 when the
+  // scenario's data sits in LDS, 1024 otherwise).
+  Sched red_up, red_dn, stp_up, stp_dn, fac;
+  std::vector<int> upd_dst;  // refactorisation update targets (see build_fac_sched)
+  int group = 64;            // threads per scenario in the refactorisation
+  int step_group = 64;       // threads per scenario in the step's sweeps
+  int spw = 1;               // scenarios per workgroup in those kernels (LDS mode)
+  bool upd_lds = true;       // LDS refactorisation stages its update targets
+  int variant = 1;           // reduction: 1 adjoint solves, 2 stacked product
+  int nu_pad = 0;            // row pitch of the stacked panels (multiple of 32)
+  int nchunk = 1;            // contraction chunks of the stacked product
 };
 
 // Returns an empty string on success, else the error message.
-std::string build_symbolic(const rkkt_network& net, int n_scen, int col_tile_req, Sym& s);
+std::string build_symbolic(const rkkt_network& net, int n_scen, int col_tile_req, int variant_req,
+                           Sym& s);
 
 // sizes fixing the LDS layouts, for a tile width
-LdsSizes lds_sizes(const Sym& s, int w);
+LdsSizes lds_sizes(const Sym& s, int w, int variant, int spw);
 
 }  // namespace rkkt

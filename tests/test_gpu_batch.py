@@ -58,12 +58,12 @@ def test_batch_graph_matches_eager_and_oracle():
     del b
 
 
-def test_autotune_returns_a_working_tile():
+def test_autotune_returns_a_working_shape():
     import paper_2301_04869_amd as R
     inst = sg.batch_instances(1, seed=78, lo=300, hi=400)[0]
-    w, ms = R.rkkt_autotune(inst.net, inst.scen.pd.T, inst.scen.qd.T, reps=2)
-    print(f"\nautotune: tile {w}, {ms:.3f} ms per condense")
-    assert w in (4, 8, 16, 32, 64) or w == R.rkkt_analyze(inst.net, 1)["col_tile"]
+    best, ms = R.rkkt_autotune(inst.net, inst.scen.pd.T, inst.scen.qd.T, reps=2)
+    print(f"\nautotune: {best}, {ms:.3f} ms per condense")
+    assert best["variant"] in (1, 2) and 1 <= best["col_tile"] <= 64
     assert ms > 0
-    p = R.rkkt_create(inst.net, inst.scen.pd.T, inst.scen.qd.T, col_tile=w)
-    assert p.dims["col_tile"] == w
+    p = R.rkkt_create(inst.net, inst.scen.pd.T, inst.scen.qd.T, **best)
+    assert p.dims["col_tile"] == best["col_tile"] and p.dims["variant"] == best["variant"]

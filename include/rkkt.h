@@ -112,6 +112,9 @@ typedef struct {
   int lds_group;                    /* refactorisation data in LDS               */
   int scen_per_group;               /* scenarios per workgroup of that kernel    */
   int lds_step;                     /* step data in LDS                          */
+  int chain_rows;                   /* rows at the top of the elimination order,
+                                       each alone in its level, that the solves
+                                       and the refactorisation take sequentially */
 } rkkt_dims;
 
 /*
@@ -139,6 +142,28 @@ int rkkt_analyze(const rkkt_network* net, int n_scen, const rkkt_options* opt, r
  */
 int rkkt_analyze_lu(const rkkt_network* net, int n_scen, const rkkt_options* opt, int* perm,
                     int* f_ptr, int* f_col);
+
+/*
+ * Host-only: one of the level-sliced schedules rkkt_create would build, for
+ * testing and inspection.  which: 0 reduction up (L and U^T solves), 1
+ * reduction down (U and L^T solves), 2 step up, 3 step down, 4
+ * refactorisation.  First call with ptr, ent, chain_pos NULL to get the
+ * sizes: *nphase phases, *slots slots, *n_ent entries, *chain_rows rows in
+ * the chain (the last chain_rows rows of the internal order, solved
+ * sequentially after the up phases and before the down phases).  Second call
+ * fills ptr [nphase * slots + 1] (entries of phase q, slot s:
+ * [ptr[q slots + s], ptr[q slots + s + 1])), ent [4 n_ent] (solves: dest row,
+ * source row, position of (dest, source) and of (source, dest) in f_col of
+ * rkkt_analyze_lu; refactorisation: position of l_ik, position of u_kk,
+ * length of the U part of row k, first index into the update targets) and
+ * chain_pos [chain_rows^2] (position of (c0 + a, c0 + b), -1 if absent).
+ * For the refactorisation *n_upd gets the number of update targets and upd
+ * [n_upd] the targets (position of (i, j) for each U column j of row k, per
+ * entry); n_upd and upd may be NULL for the other schedules.
+ */
+int rkkt_analyze_schedule(const rkkt_network* net, int n_scen, const rkkt_options* opt, int which,
+                          int* nphase, int* slots, int* n_ent, int* chain_rows, int* ptr, int* ent,
+                          int* chain_pos, int* n_upd, int* upd);
 
 /* Replace the scenario loads with device arrays [N][n_load]. */
 int rkkt_set_loads(rkkt_problem* p, const double* pd_dev, const double* qd_dev, hipStream_t stream);

@@ -25,7 +25,8 @@ EXPORTS = ("rkkt_create", "rkkt_analyze", "rkkt_set_loads", "rkkt_dims_get", "rk
            "rkkt_condense", "rkkt_factor", "rkkt_step", "rkkt_status", "rkkt_destroy",
            "rkkt_last_error", "rkkt_profile_begin", "rkkt_profile_end", "rkkt_solve",
            "rkkt_iterate", "rkkt_graph_capture", "rkkt_graph_launch", "rkkt_batch_create",
-           "rkkt_batch_launch", "rkkt_batch_destroy", "rkkt_autotune", "rkkt_analyze_lu")
+           "rkkt_batch_launch", "rkkt_batch_destroy", "rkkt_autotune", "rkkt_analyze_lu",
+           "rkkt_analyze_schedule")
 IPM_STATUS = {0: "converged", 1: "max_iter", 2: "line_search_failed",
               3: "inertia_correction_failed", 4: "device_error"}
 STAGES = ("evaluate", "condense_values", "refactor", "reduce", "scenario_sum", "factor",
@@ -66,7 +67,7 @@ class Dims(ctypes.Structure):
                 ("col_tile", ctypes.c_int), ("workspace_bytes", ctypes.c_longlong),
                 ("variant", ctypes.c_int), ("lds_reduce", ctypes.c_int),
                 ("lds_group", ctypes.c_int), ("scen_per_group", ctypes.c_int),
-                ("lds_step", ctypes.c_int)]
+                ("lds_step", ctypes.c_int), ("chain_rows", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -134,6 +135,8 @@ def lib():
                                 c_dbl_p]
     L.rkkt_analyze_lu.argtypes = [ctypes.POINTER(Network), ctypes.c_int, ctypes.POINTER(Options),
                                   c_int_p, c_int_p, c_int_p]
+    L.rkkt_analyze_schedule.argtypes = [ctypes.POINTER(Network), ctypes.c_int, ctypes.POINTER(Options),
+                                        ctypes.c_int] + [c_int_p] * 9
     L.rkkt_last_error.argtypes = [vp]
     L.rkkt_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -239,6 +242,33 @@ def rkkt_analyze_lu(net, n_scen, col_tile=0):
                                  perm.ctypes.data_as(c_int_p), fp.ctypes.data_as(c_int_p),
                                  fc.ctypes.data_as(c_int_p)))
     return perm, fp, fc
+
+
+SCHEDULES = ("reduce_up", "reduce_down", "step_up", "step_down", "refactor")
+
+
+def rkkt_analyze_schedule(net, n_scen, which, col_tile=0, variant=0):
+    """Host-only export of a level-sliced schedule: dict with nphase, slots,
+    ptr [nphase*slots+1], ent [n_ent][4], chain_rows, chain_pos [t][t]."""
+    s, keep = _host_network(net)
+    w = SCHEDULES.index(which) if isinstance(which, str) else int(which)
+    o = Options(col_tile, 0, variant)
+    nph, sl, ne, ct, nu_ = (ctypes.c_int() for _ in range(5))
+    L = lib()
+    _check(L.rkkt_analyze_schedule(ctypes.byref(s), int(n_scen), ctypes.byref(o), w, ctypes.byref(nph),
+                                   ctypes.byref(sl), ctypes.byref(ne), ctypes.byref(ct), None, None, None,
+                                   ctypes.byref(nu_), None))
+    ptr = np.zeros(nph.value * sl.value + 1, dtype=np.int32)
+    ent = np.zeros((ne.value, 4), dtype=np.int32)
+    cp = np.zeros((ct.value, ct.value), dtype=np.int32)
+    upd = np.zeros(max(nu_.value, 1), dtype=np.int32)
+    _check(L.rkkt_analyze_schedule(ctypes.byref(s), int(n_scen), ctypes.byref(o), w, ctypes.byref(nph),
+                                   ctypes.byref(sl), ctypes.byref(ne), ctypes.byref(ct),
+                                   ptr.ctypes.data_as(c_int_p), ent.ctypes.data_as(c_int_p),
+                                   cp.ctypes.data_as(c_int_p), ctypes.byref(nu_),
+                                   upd.ctypes.data_as(c_int_p)))
+    return {"nphase": nph.value, "slots": sl.value, "ptr": ptr, "ent": ent, "chain_rows": ct.value,
+            "chain_pos": cp, "upd": upd[:nu_.value]}
 
 
 def rkkt_autotune(net, pd, qd, reps=5, device=0):

@@ -73,6 +73,7 @@ void fill_dims(const rkkt::Sym& s, rkkt_dims* o, long long bytes) {
   o->lds_reduce = s.lds_reduce ? 1 : 0;
   o->lds_group = s.lds_group ? 1 : 0;
   o->lds_step = s.lds_step ? 1 : 0;
+  o->chain_rows = s.chain_t;
   o->scen_per_group = s.spw;
 }
 
@@ -144,6 +145,28 @@ int rkkt_analyze_lu(const rkkt_network* net, int n_scen, const rkkt_options* opt
   return RKKT_OK;
 }
 
+int rkkt_analyze_schedule(const rkkt_network* net, int n_scen, const rkkt_options* opt, int which,
+                          int* nphase, int* slots, int* n_ent, int* chain_rows, int* ptr, int* ent,
+                          int* chain_pos, int* n_upd, int* upd) {
+  if (!net || !nphase || !slots || !n_ent || !chain_rows || which < 0 || which > 4)
+    return fail(nullptr, RKKT_ERR_ARG, "rkkt_analyze_schedule: bad argument");
+  rkkt::Sym s;
+  std::string m = rkkt::build_symbolic(*net, n_scen, opt ? opt->col_tile : 0, opt ? opt->variant : 0, s);
+  if (!m.empty()) return fail(nullptr, RKKT_ERR_ARG, "rkkt_analyze_schedule: " + m);
+  const rkkt::Sched* sc[5] = {&s.red_up, &s.red_dn, &s.stp_up, &s.stp_dn, &s.fac};
+  const rkkt::Sched& q = *sc[which];
+  *nphase = q.nphase;
+  *slots = q.S;
+  *n_ent = (int)(q.ent.size() / 4);
+  *chain_rows = s.chain_t;
+  if (ptr) std::memcpy(ptr, q.ptr.data(), q.ptr.size() * sizeof(int));
+  if (ent) std::memcpy(ent, q.ent.data(), q.ent.size() * sizeof(int));
+  if (chain_pos) std::memcpy(chain_pos, s.chain_pos.data(), s.chain_pos.size() * sizeof(int));
+  if (n_upd) *n_upd = which == 4 ? (int)s.upd_dst.size() : 0;
+  if (upd && which == 4) std::memcpy(upd, s.upd_dst.data(), s.upd_dst.size() * sizeof(int));
+  return RKKT_OK;
+}
+
 int rkkt_create(const rkkt_network* net, int n_scen, const double* pd, const double* qd,
                 const rkkt_options* opt, rkkt_problem** out) {
   (void)hipGetLastError();
@@ -178,6 +201,10 @@ int rkkt_create(const rkkt_network* net, int n_scen, const double* pd, const dou
   d.nph_u = s.red_up.nphase;
   d.nph_d = s.red_dn.nphase;
   d.n_upd = (int)s.upd_dst.size();
+  d.n_sent = (int)(s.red_up.ent.size() / 4);
+  d.chain_t = s.chain_t;
+  d.chain_c0 = s.nx - s.chain_t;
+  d.fac_npiv = s.chain_t > 0 ? (int)s.lvu_ptr.size() - 1 - s.chain_t : (int)s.lvu_ptr.size() - 1;
   d.lu_stride = d.nnz_f + s.nx;
   d.col_tile = s.col_tile;
   d.lds_red = s.lds_reduce ? 1 : 0;
@@ -234,7 +261,7 @@ int rkkt_create(const rkkt_network* net, int n_scen, const double* pd, const dou
   UP(t_ptr, s.t_ptr) UP(t_row, s.t_row) UP(t_a, s.t_a) UP(t_b, s.t_b)
   UP(f_ptr, s.f_ptr) UP(f_col, s.f_col) UP(f_diag, s.f_diag) UP(f_tpos, s.f_tpos) UP(gx2f, s.gx2f)
   UP(lvu_ptr, s.lvu_ptr) UP(lvu_rows, s.lvu_rows) UP(lvd_ptr, s.lvd_ptr) UP(lvd_rows, s.lvd_rows)
-  UP(upd_dst, s.upd_dst)
+  UP(upd_dst, s.upd_dst) UP(chain_pos, s.chain_pos)
 #undef UP
   // schedules: LDS images (packed entries and every index array the kernel
   // stages, in its LDS order) for the LDS kernels, int4 entries otherwise

@@ -47,6 +47,10 @@ struct DP {
   const int *ru_ptr, *rd_ptr, *su_ptr, *sd_ptr, *fa_ptr;
   const void *ru_ent, *rd_ent, *su_ent, *sd_ent, *fa_ent;
   int nph_u, nph_d, n_upd;
+  int n_sent;             // entries of every schedule (pairs outside the chain)
+  int fac_npiv;           // levels whose pivots the refactorisation's phases take
+  int chain_t, chain_c0;  // chain rows chain_c0 .. nx - 1
+  const int* chain_pos;   // [chain_t][chain_t] filled-pattern positions, -1 absent
   const int* upd_dst;
   int lu_stride;          // nnz_f + nx
   // LDS images of the shared index data of the reduction, the step and the
@@ -80,7 +84,6 @@ constexpr int kStageBatch = 16;
 template <typename T>
 __device__ __forceinline__ void stage_copy(T* __restrict__ dst, const T* __restrict__ src, long long n,
                                            int start, int stride) {
-  static_assert(sizeof(T) == 8, "8-byte units");
   for (long long i0 = start; i0 < n; i0 += (long long)kStageBatch * stride) {
     T v[kStageBatch];
 #pragma unroll
@@ -99,6 +102,14 @@ __device__ __forceinline__ void stage_copy(T* __restrict__ dst, const T* __restr
 // the same for an array of 32-bit words padded to an even count
 __device__ __forceinline__ void stage_words(void* dst, const void* src, int words, int start, int stride) {
   stage_copy(static_cast<uint2*>(dst), static_cast<const uint2*>(src), (words + 1) / 2, start, stride);
+}
+
+// value of v in lane `lane` (wave-uniform) of the calling wavefront
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
 // dst[i * ldd + j] = src[i * lds + j] for i < rows, j < cols, kStageBatch

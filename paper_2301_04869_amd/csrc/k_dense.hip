@@ -127,28 +127,43 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// value of v in lane `lane` (wave-uniform) of the calling wavefront
-__device__ __forceinline__ double readlane_d(double v, int lane) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)b, lane);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+
+// 1/sqrt(d) for d > 0: the hardware reciprocal square root estimate refined by
+// two Newton-Raphson steps r <- r (3 - d r^2) / 2 (quadratic convergence from
+// the estimate's accuracy to double precision).
+__device__ __forceinline__ double rsqrt_nr(double d) {
+  double r = __builtin_amdgcn_rsq(d);
+  double e = fma(-d * r, r, 1.0);
+  r = fma(0.5 * r, e, r);
+  e = fma(-d * r, r, 1.0);
+  return fma(0.5 * r, e, r);
+}
+
+// 1/d: the hardware reciprocal estimate refined by two Newton-Raphson steps
+// r <- r (2 - d r).
+__device__ __forceinline__ double rcp_nr(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  return fma(r, fma(-d, r, 1.0), r);
 }
 
 // Right-looking blocked Cholesky of the lower triangle of an n x n block held
-// in LDS (row-major, leading dimension ld), n <= kSmallN, by a workgroup of
-// kThreads.  Panels of kPB columns: wavefront 0 factorises the panel in
-// registers (lane l holds rows jb + l + 64 t; the diagonal row jb + p is in
-// lane p, so its entries are broadcast with readlane and no synchronisation
-// is needed inside the panel); then the trailing lower triangle is updated in
+// in LDS (row-major, leading dimension ld), n <= 64 kR, by a workgroup of
+// 64 kWaves threads.  Panels of kPB columns: wavefront 0 factorises the panel
+// in registers (lane l holds rows jb + l + 64 t; the diagonal row jb + p is
+// in lane p, so its entries are broadcast with readlane and no
+// synchronisation is needed inside the panel).  Inside the panel the
+// elimination runs in the square-root-free form A = W D^-1 W^T (column p of W
+// is the updated column p of A, D its diagonal), so the dependency chain from
+// one column to the next holds one reciprocal; the panel's columns are then
+// scaled to L = W D^-1/2 together.  The trailing lower triangle is updated in
 // 16 x 16 tiles on the FP64 matrix cores (v_mfma_f64_16x16x4f64: A operand
 // lane holds row lane%16, k = lane/16; B operand k = lane/16, column lane%16;
 // result register r of a lane is row lane/16 + 4 r, column lane%16).
 // Returns 0 or the 1-based first column whose pivot is not positive.
 constexpr int kPB = 16;
-constexpr int kRowsPerLane = (kSmallN + 63) / 64;
 
-template <int kWaves>
+template <int kWaves, int kR>
 __device__ int chol_blocked_lds(double* sa, int n, int ld, int* sflag) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (tid == 0) *sflag = 0;
@@ -156,34 +171,31 @@ __device__ int chol_blocked_lds(double* sa, int n, int ld, int* sflag) {
   for (int jb = 0; jb < n; jb += kPB) {
     const int nb = min(kPB, n - jb);
     if (wv == 0) {
-      double x[kRowsPerLane][kPB];
+      double x[kR][kPB];
 #pragma unroll
-      for (int t = 0; t < kRowsPerLane; ++t) {
+      for (int t = 0; t < kR; ++t) {
         const int r = jb + lane + 64 * t;
 #pragma unroll
         for (int p = 0; p < kPB; ++p) x[t][p] = (r < n && p < nb) ? sa[r * ld + jb + p] : 0.0;
       }
       int bad = 0;
+      double dpiv[kPB];
 #pragma unroll
       for (int p = 0; p < kPB; ++p) {
+        dpiv[p] = 1.0;
         if (p < nb && !bad) {
           const double dv = readlane_d(x[0][p], p);
           if (!(dv > 0.0) || !isfinite(dv)) {
             bad = jb + p + 1;
           } else {
-            const double sq = sqrt(dv);
-            const double inv = 1.0 / sq;
-#pragma unroll
-            for (int t = 0; t < kRowsPerLane; ++t) {
-              const int r = jb + lane + 64 * t;
-              x[t][p] = r > jb + p ? x[t][p] * inv : (r == jb + p ? sq : x[t][p]);
-            }
+            dpiv[p] = dv;
+            const double inv = rcp_nr(dv);
 #pragma unroll
             for (int q = p + 1; q < kPB; ++q) {
               if (q < nb) {
-                const double lq = readlane_d(x[0][p], q);
+                const double lq = readlane_d(x[0][p], q) * inv;  // w_qp / d_p
 #pragma unroll
-                for (int t = 0; t < kRowsPerLane; ++t) x[t][q] = fma(-x[t][p], lq, x[t][q]);
+                for (int t = 0; t < kR; ++t) x[t][q] = fma(-x[t][p], lq, x[t][q]);
               }
             }
           }
@@ -192,12 +204,15 @@ __device__ int chol_blocked_lds(double* sa, int n, int ld, int* sflag) {
       if (bad) {
         if (lane == 0) *sflag = bad;
       } else {
+        // L = W D^-1/2 for the whole panel (independent chains)
 #pragma unroll
-        for (int t = 0; t < kRowsPerLane; ++t) {
-          const int r = jb + lane + 64 * t;
+        for (int p = 0; p < kPB; ++p) {
+          const double rs = rsqrt_nr(dpiv[p]);
 #pragma unroll
-          for (int p = 0; p < kPB; ++p)
-            if (r < n && p < nb && jb + p <= r) sa[r * ld + jb + p] = x[t][p];
+          for (int t = 0; t < kR; ++t) {
+            const int r = jb + lane + 64 * t;
+            if (r < n && p < nb && jb + p <= r) sa[r * ld + jb + p] = r == jb + p ? dpiv[p] * rs : x[t][p] * rs;
+          }
         }
       }
     }
@@ -230,16 +245,18 @@ __device__ int chol_blocked_lds(double* sa, int n, int ld, int* sflag) {
   return 0;
 }
 
-// whole matrix in LDS (leading dimension n + 1)
+// whole matrix in LDS (leading dimension n + 1); kR = rows per lane of the
+// panel factorisation (n <= 64 kR)
 constexpr int kCholSmallThreads = 512;
 
+template <int kR>
 __global__ __launch_bounds__(kCholSmallThreads) void k_chol_small(double* A, int n, int* info) {
   extern __shared__ double sa[];
   __shared__ int sflag;
   const int ld = n + 1, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   copy2d_overlapped(sa, ld, A, n, n, n, threadIdx.x, kCholSmallThreads);
   __syncthreads();
-  const int r = chol_blocked_lds<kCholSmallThreads / 64>(sa, n, ld, &sflag);
+  const int r = chol_blocked_lds<kCholSmallThreads / 64, kR>(sa, n, ld, &sflag);
   for (int i = wv; i < n; i += kCholSmallThreads / 64)
     for (int l = lane; l <= i; l += 64) A[(long long)i * n + l] = sa[i * ld + l];
   if (threadIdx.x == 0) *info = r;
@@ -254,7 +271,7 @@ __global__ __launch_bounds__(kThreads) void k_chol_diag(double* A, int n, int jb
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   copy2d_overlapped(sa, ld, A + (long long)jb * n + jb, n, nb, nb, threadIdx.x, kThreads);
   __syncthreads();
-  const int r = chol_blocked_lds<kWavesD>(sa, nb, ld, &sflag);
+  const int r = chol_blocked_lds<kWavesD, 1>(sa, nb, ld, &sflag);
   for (int i = wv; i < nb; i += kWavesD)
     for (int l = lane; l <= i; l += 64) A[(long long)(jb + i) * n + jb + l] = sa[i * ld + l];
   if (threadIdx.x == 0 && r) *info = jb + r;
@@ -407,12 +424,12 @@ __global__ __launch_bounds__(kRThreads) void k_reduced_solve(DP d, const double*
       double lrow[kRB];
 #pragma unroll
       for (int p = 0; p < kRB; ++p) lrow[p] = (r < nb && p <= r) ? L[(long long)(jb + r) * ld + jb + p] : 0.0;
+      const double myinv = r < nb ? rcp_nr(L[(long long)(jb + r) * ld + jb + r]) : 0.0;  // 1/L_rr
       double v = r < nb ? y[jb + r] : 0.0;
 #pragma unroll
       for (int p = 0; p < kRB; ++p) {
         if (p < nb) {
-          const double dp = readlane_d(lrow[p], p);
-          const double vp = readlane_d(v, p) / dp;
+          const double vp = readlane_d(v, p) * readlane_d(myinv, p);
           if (r == p) v = vp;
           else if (r > p) v = fma(-lrow[p], vp, v);
         }
@@ -437,12 +454,12 @@ __global__ __launch_bounds__(kRThreads) void k_reduced_solve(DP d, const double*
       double lcol[kRB];
 #pragma unroll
       for (int p = 0; p < kRB; ++p) lcol[p] = (r < nb && p < nb && p >= r) ? L[(long long)(jb + p) * ld + jb + r] : 0.0;
+      const double myinv = r < nb ? rcp_nr(L[(long long)(jb + r) * ld + jb + r]) : 0.0;
       double v = r < nb ? y[jb + r] : 0.0;
 #pragma unroll
       for (int p = kRB - 1; p >= 0; --p) {
         if (p < nb) {
-          const double dp = readlane_d(lcol[p], p);
-          const double vp = readlane_d(v, p) / dp;
+          const double vp = readlane_d(v, p) * readlane_d(myinv, p);
           if (r == p) v = vp;
           else if (r < p) v = fma(-lcol[p], vp, v);
         }
@@ -465,9 +482,14 @@ static hipError_t allow_lds(const void* fn, int* cur, int need) {
 }
 
 hipError_t configure_dense_kernels(const DP& d) {
-  static int c1 = 0, c2 = 0, c3 = 0;
+  static int c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0;
   hipError_t e = hipSuccess;
-  if (d.nu <= kSmallN) e = allow_lds((const void*)k_chol_small, &c1, 8 * d.nu * (d.nu + 1));
+  if (d.nu <= kSmallN) {
+    const void* f = d.nu <= 64 ? (const void*)k_chol_small<1>
+                    : d.nu <= 128 ? (const void*)k_chol_small<2> : (const void*)k_chol_small<3>;
+    int* cur = d.nu <= 64 ? &c1 : d.nu <= 128 ? &c4 : &c5;
+    e = allow_lds(f, cur, 8 * d.nu * (d.nu + 1));
+  }
   if (e == hipSuccess) {
     if (rsolve_lds(d.nu))
       e = allow_lds((const void*)k_reduced_solve<true>, &c2, 8 * (d.nu * (d.nu + 1) + d.nu));
@@ -504,7 +526,9 @@ void launch_cholesky(const DP& d, double* a, int* info, hipStream_t s) {
   const int n = d.nu;
   if (n <= kSmallN) {
     size_t lds = 8 * (size_t)n * (n + 1);
-    k_chol_small<<<1, kCholSmallThreads, lds, s>>>(a, n, info);
+    if (n <= 64) k_chol_small<1><<<1, kCholSmallThreads, lds, s>>>(a, n, info);
+    else if (n <= 128) k_chol_small<2><<<1, kCholSmallThreads, lds, s>>>(a, n, info);
+    else k_chol_small<3><<<1, kCholSmallThreads, lds, s>>>(a, n, info);
     return;
   }
   k_set_int<<<1, 1, 0, s>>>(info, 0);

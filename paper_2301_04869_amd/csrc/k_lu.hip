@@ -69,10 +69,11 @@ __device__ __forceinline__ double* lu_of(const DP& d, int k) { return d.LU + (lo
 __host__ __device__ __forceinline__ LdsSizes sizes_of(const DP& d) {
   LdsSizes z;
   z.nx = d.nx; z.nu = d.nu; z.nz = d.nz; z.nnz_f = d.nnz_f; z.nnz_k = d.nnz_k;
-  z.nnz_gu = d.nnz_gu; z.nnz_l = d.nnz_l; z.nlu = d.nlev_up; z.nph_u = d.nph_u;
+  z.nnz_gu = d.nnz_gu; z.nnz_l = d.n_sent; z.nlu = d.nlev_up; z.nph_u = d.nph_u;
   z.nph_d = d.nph_d; z.n_upd = d.n_upd; z.w = d.col_tile; z.variant = d.variant; z.spw = d.spw;
   z.upd_lds = d.upd_lds;
   z.nnz_h = d.nnz_h; z.m = d.m;
+  z.chain_t = d.chain_t;
   return z;
 }
 
@@ -175,6 +176,132 @@ __device__ __forceinline__ void sweep(const int* __restrict__ ptr, const void* e
   }
 }
 
+// ------------------------------------------------------------------ chain
+// The chain rows c0 .. nx - 1 (each alone in its level in both directions)
+// are solved sequentially in registers instead of one barrier-separated
+// phase per row.  Coefficient of (chain row a, chain row b): lu[pos(a, b)];
+// the transposed solves read lu[pos(b, a)].
+
+// One column, lanes 0 .. t-1 of the calling wavefront hold chain rows a;
+// x_b is broadcast with readlane.  Up: b increasing, rows a > b update;
+// down: b decreasing, rows a < b update.
+template <bool kUp, bool kTrans>
+__device__ __forceinline__ void chain_solve1(const DP& d, const double* lu, double* X, int lane) {
+  const int t = d.chain_t, c0 = d.chain_c0;
+  const int* __restrict__ P = d.chain_pos;
+  const bool own = lane < t;
+  double x = own ? X[c0 + lane] : 0.0;
+  double coef[kChainMax];
+#pragma unroll
+  for (int b = 0; b < kChainMax; ++b) {
+    const int pp = own && b < t ? (kTrans ? P[b * t + lane] : P[lane * t + b]) : -1;
+    coef[b] = pp >= 0 ? lu[pp] : 0.0;
+  }
+  if (kUp) {
+#pragma unroll
+    for (int b = 0; b < kChainMax; ++b)
+      if (b < t) {
+        const double xb = readlane_d(x, b);
+        if (lane > b) x = fma(-coef[b], xb, x);
+      }
+  } else {
+#pragma unroll
+    for (int b = kChainMax - 1; b >= 0; --b)
+      if (b < t) {
+        const double xb = readlane_d(x, b);
+        if (lane < b) x = fma(-coef[b], xb, x);
+      }
+  }
+  if (own) X[c0 + lane] = x;
+}
+
+// Many columns: the calling thread solves its own column c of X (leading
+// dimension ld) over the chain rows.  cv[a t + b] holds the chain block's
+// values (zero where the pattern has no entry), staged in LDS once per
+// workgroup, so every coefficient is one broadcast read.
+template <bool kUp, bool kTrans>
+__device__ __forceinline__ void chain_solveW(const DP& d, const double* cv, double* X, int ld, int c) {
+  const int t = d.chain_t, c0 = d.chain_c0;
+  double x[kChainMax];
+#pragma unroll
+  for (int a = 0; a < kChainMax; ++a) x[a] = a < t ? X[(long long)(c0 + a) * ld + c] : 0.0;
+  // column order: once x_b is final, every later row subtracts its term; the
+  // updates of one step are independent, and each row still subtracts its
+  // terms in the order of b
+  if (kUp) {
+#pragma unroll
+    for (int b = 0; b < kChainMax - 1; ++b)
+      if (b + 1 < t) {
+#pragma unroll
+        for (int a = b + 1; a < kChainMax; ++a)
+          if (a < t) x[a] = fma(-(kTrans ? cv[b * t + a] : cv[a * t + b]), x[b], x[a]);
+      }
+  } else {
+#pragma unroll
+    for (int b = kChainMax - 1; b >= 1; --b)
+      if (b < t) {
+#pragma unroll
+        for (int a = 0; a < b; ++a) x[a] = fma(-(kTrans ? cv[b * t + a] : cv[a * t + b]), x[b], x[a]);
+      }
+  }
+#pragma unroll
+  for (int a = 0; a < kChainMax; ++a)
+    if (a < t) X[(long long)(c0 + a) * ld + c] = x[a];
+}
+
+// chain block values of one scenario into cv (all threads of the workgroup)
+__device__ __forceinline__ void chain_gather(const DP& d, const double* lu, double* cv) {
+  const int tt = d.chain_t * d.chain_t;
+  for (int e = threadIdx.x; e < tt; e += blockDim.x) {
+    const int pp = d.chain_pos[e];
+    cv[e] = pp >= 0 ? lu[pp] : 0.0;
+  }
+}
+
+// Up-looking elimination of the chain block after the phases have applied
+// every contribution from rows before the chain: lane a holds chain row a
+// (zeros where the filled pattern has no entry; the pattern is closed under
+// elimination, so they stay zero); row j's pivot and U part are broadcast
+// with readlane.  Same pivot test as the phases.
+__device__ __forceinline__ void chain_factor(const DP& d, double* lu, double* invd, const double* rmax,
+                                             int k, int lane) {
+  const int t = d.chain_t, c0 = d.chain_c0;
+  const int* __restrict__ P = d.chain_pos;
+  const bool own = lane < t;
+  double row[kChainMax];
+#pragma unroll
+  for (int b = 0; b < kChainMax; ++b) {
+    const int pp = own && b < t ? P[lane * t + b] : -1;
+    row[b] = pp >= 0 ? lu[pp] : 0.0;
+  }
+#pragma unroll
+  for (int j = 0; j < kChainMax; ++j) {
+    if (j < t) {
+      const double ujj = readlane_d(row[j], j);
+      const double inv = 1.0 / ujj;
+      if (lane == j) {
+        if (!(fabs(ujj) > 0.0 && fabs(ujj) >= 1e-10 * rmax[c0 + j]) || !isfinite(ujj))
+          raise_status(d, RKKT_ERR_SINGULAR_GX, k);
+        invd[c0 + j] = inv;
+      }
+      double ub[kChainMax];
+#pragma unroll
+      for (int b = j + 1; b < kChainMax; ++b) ub[b] = readlane_d(row[b], j);
+      if (own && lane > j) {
+        const double l = row[j] * inv;
+        row[j] = l;
+#pragma unroll
+        for (int b = j + 1; b < kChainMax; ++b) row[b] = fma(-l, ub[b], row[b]);
+      }
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < kChainMax; ++b) {
+    const int pp = own && b < t ? P[lane * t + b] : -1;
+    if (pp >= 0) lu[pp] = row[b];
+  }
+}
+
 // ------------------------------------------------------------ refactorisation
 // LDS mode: spw scenarios per workgroup, one wavefront each, with the shared
 // schedule staged once; global mode: one workgroup of kRT threads per scenario.
@@ -188,7 +315,7 @@ __global__ __launch_bounds__(kT) void k_refactor(DP d) {
   const int nx = d.nx, nf = d.nnz_f;
   extern __shared__ double smem[];
   double *lu, *invd, *rmax;
-  const int *ptr, *upd, *lvu_ptr, *lvu_rows, *f_ptr, *f_diag, *f_col;
+  const int *ptr, *upd, *f_ptr, *f_diag, *f_col;
   const void* ent;
   if (kLDS) {
     double* mine = smem + (long long)gi * (nf + 2 * nx);
@@ -196,7 +323,7 @@ __global__ __launch_bounds__(kT) void k_refactor(DP d) {
     invd = lu + nf;
     rmax = invd + nx;
     unsigned* ue = reinterpret_cast<unsigned*>(smem + (long long)d.spw * (nf + 2 * nx));
-    int* q = reinterpret_cast<int*>(ue + 2 * d.nnz_l);
+    int* q = reinterpret_cast<int*>(ue + 2 * d.n_sent);
     int* a_p = q; q += d.nph_u * G + 1;
     int* a_lp = q; q += d.nlev_up + 1;
     int* a_lr = q; q += nx;
@@ -204,7 +331,9 @@ __global__ __launch_bounds__(kT) void k_refactor(DP d) {
     int* a_fp = q; q += nx + 1;
     upd = kUpdLds ? q : d.upd_dst;
     stage_words(ue, d.blob_fac, d.blob_fac_words, tid, blockDim.x);
-    ptr = a_p; lvu_ptr = a_lp; lvu_rows = a_lr; f_diag = a_fd; f_ptr = a_fp;
+    (void)a_lp;
+    (void)a_lr;
+    ptr = a_p; f_diag = a_fd; f_ptr = a_fp;
     f_col = d.f_col;
     ent = ue;
   } else {
@@ -212,7 +341,7 @@ __global__ __launch_bounds__(kT) void k_refactor(DP d) {
     invd = lu + nf;
     rmax = d.rhat1 + (long long)k * nx;
     ptr = d.fa_ptr; ent = d.fa_ent; upd = d.upd_dst;
-    lvu_ptr = d.lvu_ptr; lvu_rows = d.lvu_rows; f_ptr = d.f_ptr; f_diag = d.f_diag; f_col = d.f_col;
+    f_ptr = d.f_ptr; f_diag = d.f_diag; f_col = d.f_col;
   }
   auto gsync = [] {
     if (kLDS) wave_sync();
@@ -234,16 +363,8 @@ __global__ __launch_bounds__(kT) void k_refactor(DP d) {
     rmax[i] = mx;
   }
   gsync();
-  for (int q = 0; q < d.nlev_up; ++q) {
-    // rows of level q are final: pivot test and reciprocal
-    for (int r = lvu_ptr[q] + gl; r < lvu_ptr[q + 1]; r += G) {
-      const int i = lvu_rows[r];
-      const double p = lu[f_diag[i]];
-      if (!(fabs(p) > 0.0 && fabs(p) >= 1e-10 * rmax[i]) || !isfinite(p))
-        raise_status(d, RKKT_ERR_SINGULAR_GX, k);
-      invd[i] = 1.0 / p;
-    }
-    if (q < d.nph_u) {
+  for (int q = 0; q < d.nph_u; ++q) {
+    {
       const int e1 = ptr[q * G + gl + 1];
       for (int e = ptr[q * G + gl]; e < e1; ++e) {
         const Ent t = ent_at<kLDS>(ent, e);  // (position of l_ik, of u_kk, |U(k)|, first target)
@@ -266,6 +387,17 @@ __global__ __launch_bounds__(kT) void k_refactor(DP d) {
     }
     gsync();
   }
+  // the chain block, sequentially in registers (one wavefront)
+  if (d.chain_t > 0) {
+    if (gl < 64) chain_factor(d, lu, invd, rmax, k, gl);
+  }
+  // pivots of the rows before the chain: test and reciprocal
+  for (int i = gl; i < d.chain_c0; i += G) {
+    const double p = lu[f_diag[i]];
+    if (!(fabs(p) > 0.0 && fabs(p) >= 1e-10 * rmax[i]) || !isfinite(p)) raise_status(d, RKKT_ERR_SINGULAR_GX, k);
+    invd[i] = 1.0 / p;
+  }
+  gsync();
   // scale the columns of the strict upper part by 1/u_jj
   for (int i = gl; i < nx; i += G) {
     const int e1 = f_ptr[i + 1];
@@ -302,6 +434,7 @@ __global__ __launch_bounds__(kRT) void k_reduce(DP d) {
   int ldT = W;
   const int *uptr, *dptr, *k_ptr, *k_usplit, *k_col, *guc_ptr, *guc_row;
   const void *uent, *dent;
+  double* cv;  // chain block values
   double* zk = kVar == 2 ? d.Zst + (long long)k * nz * d.nu_pad : nullptr;
   double* kzk = kVar == 2 ? d.KZst + (long long)k * nz * d.nu_pad : nullptr;
   if (kLDS) {
@@ -314,8 +447,8 @@ __global__ __launch_bounds__(kRT) void k_reduce(DP d) {
     T = p; p += (long long)nx * W;
     if (kVar == 1) { Lx = p; p += (long long)nx * W; }
     unsigned* ue = reinterpret_cast<unsigned*>(smem + reduce_lds_doubles(z));
-    unsigned* de = ue + 2 * d.nnz_l;
-    int* ip = reinterpret_cast<int*>(de + 2 * d.nnz_l);
+    unsigned* de = ue + 2 * d.n_sent;
+    int* ip = reinterpret_cast<int*>(de + 2 * d.n_sent);
     int* a_up = ip; ip += d.nph_u * S + 1;
     int* a_dp = ip; ip += d.nph_d * S + 1;
     int* a_kp = ip; ip += nz + 1;
@@ -330,7 +463,9 @@ __global__ __launch_bounds__(kRT) void k_reduce(DP d) {
     uptr = a_up; dptr = a_dp; k_ptr = a_kp; k_usplit = a_ku; k_col = a_kc; guc_ptr = a_gp; guc_row = a_gr;
     lu = slu; invd = sid; kv = skv; guv = sgu;
     uent = ue; dent = de;
+    cv = smem + (reduce_lds_bytes(z) / 8 - (long long)d.chain_t * d.chain_t);
   } else {
+    cv = smem;
     lu = lu_of(d, k);
     invd = lu + d.nnz_f;
     kv = d.K + (long long)k * d.nnz_k;
@@ -361,9 +496,17 @@ __global__ __launch_bounds__(kRT) void k_reduce(DP d) {
   if (colok)
     for (int j = guc_ptr[col] + slot; j < guc_ptr[col + 1]; j += S)
       T[(long long)guc_row[j] * ldT + c] = -gu_val(j);
+  chain_gather(d, lu, cv);
   __syncthreads();
   // step 1
+  const bool chain_lane = slot == 0 && (kLDS || colok);
   sweep<kLDS, false>(uptr, uent, d.nph_u, S, slot, colok, lu, T, ldT, c, bsync);
+  if (d.chain_t > 0) {
+    if (chain_lane) chain_solveW<true, false>(d, cv, T, ldT, c);
+    __syncthreads();
+    if (chain_lane) chain_solveW<false, false>(d, cv, T, ldT, c);
+    __syncthreads();
+  }
   sweep<kLDS, false>(dptr, dent, d.nph_d, S, slot, colok, lu, T, ldT, c, bsync);
   if (colok)
     for (int i = slot; i < nx; i += S) T[(long long)i * ldT + c] *= invd[i];
@@ -393,6 +536,12 @@ __global__ __launch_bounds__(kRT) void k_reduce(DP d) {
   __syncthreads();
   // step 3: U^T sweep, L^T sweep, then L_u - G_u^T (G_x^-T L_x)
   sweep<kLDS, true>(uptr, uent, d.nph_u, S, slot, colok, lu, Lx, W, c, bsync);
+  if (d.chain_t > 0) {
+    if (chain_lane) chain_solveW<true, true>(d, cv, Lx, W, c);
+    __syncthreads();
+    if (chain_lane) chain_solveW<false, true>(d, cv, Lx, W, c);
+    __syncthreads();
+  }
   sweep<kLDS, true>(dptr, dent, d.nph_d, S, slot, colok, lu, Lx, W, c, bsync);
   if (colok)
     for (int ru = slot; ru < nu; ru += S) {
@@ -416,39 +565,62 @@ template <bool kTrans, typename Sync>
 __device__ __forceinline__ void sweep64(const int* __restrict__ ptr, const int4* __restrict__ ent,
                                         int nphase, int wv, const double* __restrict__ lu, double* X,
                                         int ld, int c, Sync sync) {
-  int e0 = nphase > 0 ? ptr[wv] : 0, e1 = nphase > 0 ? ptr[wv + 1] : 0;
+  // Software pipeline over phases with vector loads, which have a wait
+  // counter of their own, so the phase's LDS waits never wait for them:
+  // phase bounds three phases ahead (lanes 0 and 1), entries two phases
+  // ahead and factor values one phase ahead (lane u holds entry u).
+  const int lane = threadIdx.x & 63;
+  auto bounds = [&](int q) -> int {
+    return q < nphase && lane < 2 ? ptr[q * kS64 + wv + lane] : 0;
+  };
+  auto first = [](int bq) { return __builtin_amdgcn_readlane(bq, 0); };
+  auto count = [](int bq) { return __builtin_amdgcn_readlane(bq, 1) - __builtin_amdgcn_readlane(bq, 0); };
+  auto entries = [&](int bq) -> int4 {
+    const int b = first(bq), n = count(bq);
+    return lane < n ? ent[b + lane] : make_int4(-1, 0, 0, 0);
+  };
+  auto values = [&](int4 ev) -> double { return ev.x >= 0 ? lu[kTrans ? ev.w : ev.z] : 0.0; };
+  int bq0 = bounds(0), bq1 = bounds(1), bq2 = bounds(2);
+  int4 ev0 = entries(bq0), ev1 = entries(bq1);
+  double lv0 = values(ev0);
   for (int q = 0; q < nphase; ++q) {
-    const int n0 = q + 1 < nphase ? ptr[(q + 1) * kS64 + wv] : 0;
-    const int n1 = q + 1 < nphase ? ptr[(q + 1) * kS64 + wv + 1] : 0;
+    const double lv1 = values(ev1);
+    const int4 ev2 = entries(bq2);
+    const int bq3 = bounds(q + 3);
+    const int b0 = first(bq0), n = count(bq0);
     int cur = -1;
     double acc = 0.0;
-    int e = e0;
-    for (; e + 4 <= e1; e += 4) {
-      const int4 t0 = ent[e], t1 = ent[e + 1], t2 = ent[e + 2], t3 = ent[e + 3];
-      const double v0 = lu[kTrans ? t0.w : t0.z], v1 = lu[kTrans ? t1.w : t1.z];
-      const double v2 = lu[kTrans ? t2.w : t2.z], v3 = lu[kTrans ? t3.w : t3.z];
-      const double x0 = X[t0.y * ld + c], x1 = X[t1.y * ld + c];
-      const double x2 = X[t2.y * ld + c], x3 = X[t3.y * ld + c];
-      if (t0.x != cur) { if (cur >= 0) X[cur * ld + c] = acc; cur = t0.x; acc = X[cur * ld + c]; }
-      acc = fma(-v0, x0, acc);
-      if (t1.x != cur) { X[cur * ld + c] = acc; cur = t1.x; acc = X[cur * ld + c]; }
-      acc = fma(-v1, x1, acc);
-      if (t2.x != cur) { X[cur * ld + c] = acc; cur = t2.x; acc = X[cur * ld + c]; }
-      acc = fma(-v2, x2, acc);
-      if (t3.x != cur) { X[cur * ld + c] = acc; cur = t3.x; acc = X[cur * ld + c]; }
-      acc = fma(-v3, x3, acc);
-    }
-    for (; e < e1; ++e) {
-      const int4 t = ent[e];
-      const double v = lu[kTrans ? t.w : t.z];
-      const double x = X[t.y * ld + c];
-      if (t.x != cur) { if (cur >= 0) X[cur * ld + c] = acc; cur = t.x; acc = X[cur * ld + c]; }
+    const int m = min(n, 64);
+    for (int u = 0; u < m; ++u) {
+      const int dst = __builtin_amdgcn_readlane(ev0.x, u), src = __builtin_amdgcn_readlane(ev0.y, u);
+      const double v = readlane_d(lv0, u);
+      const double x = X[src * ld + c];
+      if (dst != cur) {
+        if (cur >= 0) X[cur * ld + c] = acc;
+        cur = dst;
+        acc = X[cur * ld + c];
+      }
       acc = fma(-v, x, acc);
+    }
+    // entries past the 64 held in lanes, one at a time
+    for (int e = b0 + 64; e < b0 + n; ++e) {
+      const int4 t = ent[e];
+      const double x = X[t.y * ld + c];
+      if (t.x != cur) {
+        if (cur >= 0) X[cur * ld + c] = acc;
+        cur = t.x;
+        acc = X[cur * ld + c];
+      }
+      acc = fma(-lu[kTrans ? t.w : t.z], x, acc);
     }
     if (cur >= 0) X[cur * ld + c] = acc;
     sync();
-    e0 = n0;
-    e1 = n1;
+    bq0 = bq1;
+    bq1 = bq2;
+    bq2 = bq3;
+    ev0 = ev1;
+    ev1 = ev2;
+    lv0 = lv1;
   }
 }
 
@@ -467,18 +639,30 @@ __global__ __launch_bounds__(kRT) void k_reduce64(DP d) {
   int ldT = kW64;
   double* zk = kVar == 2 ? d.Zst + (long long)k * nz * d.nu_pad : nullptr;
   double* kzk = kVar == 2 ? d.KZst + (long long)k * nz * d.nu_pad : nullptr;
-  const int* __restrict__ k_ptr = d.k_ptr;
-  const int* __restrict__ k_usplit = d.k_usplit;
-  const int* __restrict__ k_col = d.k_col;
+  const int* k_ptr = d.k_ptr;
+  const int* k_usplit = d.k_usplit;
+  const int* k_col = d.k_col;
+  double* cv = smem;  // chain block values (global mode: the only LDS use)
   if (kLDS) {
     double* p = smem;
     double* slu = p; p += d.nnz_f + nx;
     double* skv = p; p += d.nnz_k;
     double* sgu = p; p += d.nnz_gu;
     T = p; p += (long long)nx * kW64;
-    if (kVar == 1) Lx = p;
+    if (kVar == 1) { Lx = p; p += (long long)nx * kW64; }
+    int* ip = reinterpret_cast<int*>(p);
+    int* skp = ip; ip += nz + 1;
+    int* sku = ip; ip += nz;
+    int* skc = ip;
     stage_copy(slu, lu_of(d, k), d.nnz_f + nx, tid, kRT);
     stage_copy(skv, d.K + (long long)k * d.nnz_k, d.nnz_k, tid, kRT);
+    stage_copy(skp, d.k_ptr, nz + 1, tid, kRT);
+    stage_copy(sku, d.k_usplit, nz, tid, kRT);
+    stage_copy(skc, d.k_col, d.nnz_k, tid, kRT);
+    k_ptr = skp;
+    k_usplit = sku;
+    k_col = skc;
+    cv = smem + (reduce_lds_bytes(sizes_of(d)) / 8 - (long long)d.chain_t * d.chain_t);
     for (int j = tid; j < d.nnz_gu; j += kRT) sgu[j] = ev[d.off_gu + d.guc_pos[j]];
     lu = slu; invd = slu + d.nnz_f; kv = skv; guv = sgu;
   } else {
@@ -501,6 +685,7 @@ __global__ __launch_bounds__(kRT) void k_reduce64(DP d) {
   if (colok)
     for (int j = d.guc_ptr[col] + wv; j < d.guc_ptr[col + 1]; j += kS64)
       T[(long long)d.guc_row[j] * ldT + c] = -gu_val(j);
+  chain_gather(d, lu, cv);
   __syncthreads();
   // step 1: T = -G_x^-1 G_u V
   const int4* uent = static_cast<const int4*>(d.ru_ent);
@@ -508,42 +693,80 @@ __global__ __launch_bounds__(kRT) void k_reduce64(DP d) {
   // every lane sweeps (barriers stay uniform); lanes past n_u work on
   // padding columns inside the panel, which nothing reads
   sweep64<false>(d.ru_ptr, uent, d.nph_u, wv, lu, T, ldT, c, bsync);
+  if (d.chain_t > 0) {
+    if (wv == 0) chain_solveW<true, false>(d, cv, T, ldT, c);
+    __syncthreads();
+    if (wv == 0) chain_solveW<false, false>(d, cv, T, ldT, c);
+    __syncthreads();
+  }
   sweep64<false>(d.rd_ptr, dent, d.nph_d, wv, lu, T, ldT, c, bsync);
   if (colok)
     for (int i = wv; i < nx; i += kS64) T[(long long)i * ldT + c] *= invd[i];
   __syncthreads();
-  // step 2: rows of K, one row per wavefront at a time
-  auto k_row = [&](int r) -> double {
-    double acc = 0.0;
-    const int eu = k_usplit[r], e1 = k_ptr[r + 1];
-    for (int e = eu; e < e1; ++e)
-      if (k_col[e] == nx + col) acc = kv[e];
-    int e = k_ptr[r];
-    double acc2 = 0.0;
-    for (; e + 2 <= eu; e += 2) {
-      acc = fma(kv[e], T[(long long)k_col[e] * ldT + c], acc);
-      acc2 = fma(kv[e + 1], T[(long long)k_col[e + 1] * ldT + c], acc2);
+  // step 2: rows of K, four rows per wavefront at a time (independent chains)
+  constexpr int kRowsK = 4;
+  auto k_rows = [&](int r0, double out4[kRowsK]) {
+    int e[kRowsK], eu[kRowsK], e1[kRowsK];
+    int len = 0;
+#pragma unroll
+    for (int j = 0; j < kRowsK; ++j) {
+      const int r = r0 + j * kS64;
+      e[j] = r < nz ? k_ptr[r] : 0;
+      eu[j] = r < nz ? k_usplit[r] : 0;
+      e1[j] = r < nz ? k_ptr[r + 1] : 0;
+      len = max(len, eu[j] - e[j]);
     }
-    if (e < eu) acc = fma(kv[e], T[(long long)k_col[e] * ldT + c], acc);
-    return acc + acc2;
+    double acc[kRowsK];
+#pragma unroll
+    for (int j = 0; j < kRowsK; ++j) {
+      acc[j] = 0.0;
+      for (int q = eu[j]; q < e1[j]; ++q)
+        if (k_col[q] == nx + col) acc[j] = kv[q];
+    }
+    for (int m = 0; m < len; ++m) {
+#pragma unroll
+      for (int j = 0; j < kRowsK; ++j) {
+        const int q = e[j] + m;
+        if (q < eu[j]) acc[j] = fma(kv[q], T[(long long)k_col[q] * ldT + c], acc[j]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kRowsK; ++j) out4[j] = acc[j];
   };
   if (kVar == 2) {
     if (!colok) return;
     if (kLDS)
       for (int i = wv; i < nx; i += kS64) zk[(long long)i * d.nu_pad + col] = T[i * kW64 + c];
-    for (int r = wv; r < nz; r += kS64) kzk[(long long)r * d.nu_pad + col] = k_row(r);
+    for (int r0 = wv; r0 < nz; r0 += kRowsK * kS64) {
+      double v[kRowsK];
+      k_rows(r0, v);
+#pragma unroll
+      for (int j = 0; j < kRowsK; ++j)
+        if (r0 + j * kS64 < nz) kzk[(long long)(r0 + j * kS64) * d.nu_pad + col] = v[j];
+    }
     return;
   }
   // adjoint: L_x (prescaled by 1/u_ii for the U^T sweep), L_u into part
   double* out = d.part + (long long)k * nu * nu;
   if (colok)
-    for (int r = wv; r < nz; r += kS64) {
-      const double acc = k_row(r);
-      if (r < nx) Lx[(long long)r * kW64 + c] = acc * invd[r];
-      else out[(long long)(r - nx) * nu + col] = acc;
+    for (int r0 = wv; r0 < nz; r0 += kRowsK * kS64) {
+      double v[kRowsK];
+      k_rows(r0, v);
+#pragma unroll
+      for (int j = 0; j < kRowsK; ++j) {
+        const int r = r0 + j * kS64;
+        if (r < nx) Lx[(long long)r * kW64 + c] = v[j] * invd[r];
+        else if (r < nz) out[(long long)(r - nx) * nu + col] = v[j];
+      }
     }
   __syncthreads();
   sweep64<true>(d.ru_ptr, uent, d.nph_u, wv, lu, Lx, kW64, c, bsync);
+  if (d.chain_t > 0) {
+    if (wv == 0) chain_solveW<true, true>(d, cv, Lx, kW64, c);
+    __syncthreads();
+    if (wv == 0) chain_solveW<false, true>(d, cv, Lx, kW64, c);
+    __syncthreads();
+  }
   sweep64<true>(d.rd_ptr, dent, d.nph_d, wv, lu, Lx, kW64, c, bsync);
   if (colok)
     for (int ru = wv; ru < nu; ru += kS64) {
@@ -594,8 +817,8 @@ __device__ __forceinline__ StepView step_view(const DP& d, int k, double* smem, 
     w.v2 = p; p += nx;
     double* spu = p; p += d.nu;
     unsigned* ue = reinterpret_cast<unsigned*>(p);
-    unsigned* de = ue + 2 * d.nnz_l;
-    int* ip = reinterpret_cast<int*>(de + 2 * d.nnz_l);
+    unsigned* de = ue + 2 * d.n_sent;
+    int* ip = reinterpret_cast<int*>(de + 2 * d.n_sent);
     w.uptr = ip;
     w.dptr = ip + d.nph_u * kGroupLds + 1;
     w.uent = ue;
@@ -641,6 +864,12 @@ template <bool kLDS, typename Sync>
 __device__ __forceinline__ void solve_fwd(const DP& d, const StepView& w, double* X, int gl, Sync sync) {
   constexpr int G = kLDS ? kGroupLds : kRT;
   sweep<kLDS, false>(w.uptr, w.uent, d.nph_u, G, gl, true, w.lu, X, 1, 0, sync);
+  if (d.chain_t > 0) {
+    if (gl < 64) chain_solve1<true, false>(d, w.lu, X, gl);
+    sync();
+    if (gl < 64) chain_solve1<false, false>(d, w.lu, X, gl);
+    sync();
+  }
   sweep<kLDS, false>(w.dptr, w.dent, d.nph_d, G, gl, true, w.lu, X, 1, 0, sync);
   for (int i = gl; i < d.nx; i += G) X[i] *= w.invd[i];
   sync();
@@ -651,6 +880,12 @@ template <bool kLDS, typename Sync>
 __device__ __forceinline__ void solve_adj_scaled(const DP& d, const StepView& w, double* X, int gl, Sync sync) {
   constexpr int G = kLDS ? kGroupLds : kRT;
   sweep<kLDS, true>(w.uptr, w.uent, d.nph_u, G, gl, true, w.lu, X, 1, 0, sync);
+  if (d.chain_t > 0) {
+    if (gl < 64) chain_solve1<true, true>(d, w.lu, X, gl);
+    sync();
+    if (gl < 64) chain_solve1<false, true>(d, w.lu, X, gl);
+    sync();
+  }
   sweep<kLDS, true>(w.dptr, w.dent, d.nph_d, G, gl, true, w.lu, X, 1, 0, sync);
   sync();
 }
@@ -821,23 +1056,24 @@ void launch_refactor(const DP& d, hipStream_t s) {
 
 void launch_reduce(const DP& d, hipStream_t s) {
   dim3 grid(ntiles(d), d.N);
-  const size_t lds = d.lds_red ? reduce_lds_bytes(sizes_of(d)) : 0;
+  // LDS mode: the staged data; global mode: only the chain block's values
+  const size_t lds = d.lds_red ? reduce_lds_bytes(sizes_of(d)) : 8 * (size_t)d.chain_t * d.chain_t;
   if (d.col_tile == kW64) {
     if (d.variant == 2) {
       if (d.lds_red) k_reduce64<true, 2><<<grid, kRT, lds, s>>>(d);
-      else k_reduce64<false, 2><<<grid, kRT, 0, s>>>(d);
+      else k_reduce64<false, 2><<<grid, kRT, lds, s>>>(d);
     } else {
       if (d.lds_red) k_reduce64<true, 1><<<grid, kRT, lds, s>>>(d);
-      else k_reduce64<false, 1><<<grid, kRT, 0, s>>>(d);
+      else k_reduce64<false, 1><<<grid, kRT, lds, s>>>(d);
     }
     return;
   }
   if (d.variant == 2) {
     if (d.lds_red) k_reduce<true, 2><<<grid, kRT, lds, s>>>(d);
-    else k_reduce<false, 2><<<grid, kRT, 0, s>>>(d);
+    else k_reduce<false, 2><<<grid, kRT, lds, s>>>(d);
   } else {
     if (d.lds_red) k_reduce<true, 1><<<grid, kRT, lds, s>>>(d);
-    else k_reduce<false, 1><<<grid, kRT, 0, s>>>(d);
+    else k_reduce<false, 1><<<grid, kRT, lds, s>>>(d);
   }
 }
 

@@ -23,12 +23,16 @@ namespace rkkt {
 
 // Sizes that fix the LDS layouts of the level-scheduled kernels.
 struct LdsSizes {
-  int nx, nu, nz, nnz_f, nnz_k, nnz_gu, nnz_l, nlu, nph_u, nph_d, n_upd, w, variant, spw;
+  int nx, nu, nz, nnz_f, nnz_k, nnz_gu;
+  int nnz_l;  // entries of every level-sliced schedule (at most the strict lower count)
+  int nlu, nph_u, nph_d, n_upd, w, variant, spw;
   int upd_lds;  // refactorisation update targets staged in LDS (else read from global)
+  int chain_t;  // rows of the chain (its values occupy chain_t^2 doubles in the reduction)
   int nnz_h, m;
 };
 
 constexpr int kRedThreads = 1024;  // reduction workgroup
+constexpr int kChainMax = 32;      // longest chain of single-row levels solved in registers
 constexpr int kGroupLds = 64;      // threads per scenario in the LDS-mode refactor / step
 
 __host__ __device__ inline int red_slots(const LdsSizes& z) { return kRedThreads / z.w; }
@@ -46,11 +50,12 @@ __host__ __device__ inline long long reduce_lds_ints(const LdsSizes& z) {
   return 4LL * z.nnz_l + (z.nph_u * S + 1) + (z.nph_d * S + 1) + (z.nz + 1) + z.nz + z.nnz_k +
          (z.nu + 1) + z.nnz_gu + 2;  // + padding to whole 8-byte units
 }
-// With 64-column tiles the schedule and the K pattern are read from global
-// memory (scalar loads) and only the doubles are staged.
+// With 64-column tiles the schedule is read from global memory (scalar
+// loads); the doubles and the K pattern (k_ptr k_usplit k_col) are staged.
+// Both layouts end with the chain block's values (chain_t^2 doubles).
 __host__ __device__ inline long long reduce_lds_bytes(const LdsSizes& z) {
-  if (z.w == 64) return 8 * reduce_lds_doubles(z);
-  return 8 * reduce_lds_doubles(z) + 4 * reduce_lds_ints(z);
+  const long long ints = z.w == 64 ? (z.nz + 1) + z.nz + z.nnz_k : reduce_lds_ints(z);
+  return 8 * reduce_lds_doubles(z) + 8 * ((ints + 1) / 2) + 8LL * z.chain_t * z.chain_t;
 }
 // Refactorisation workgroup (spw scenarios, one wavefront each): per scenario
 // doubles lu[nnz_f] invd[nx] rmax[nx]; shared packed items (2 words each),

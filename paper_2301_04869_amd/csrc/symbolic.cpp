@@ -105,17 +105,62 @@ std::vector<std::vector<std::pair<int, int>>> dependents(const Sym& s, bool up) 
   return dep;
 }
 
-// Tasks of phase q: (dest, source, position) sorted by dest then source,
-// split into runs of one dest.
+// Source groups of the phases of one direction, for a chain of the last t
+// rows.  Up: the rows before the chain of every level (the chain's rows are
+// solved after the phases, in registers).  Down: the chain rows as one group
+// (final once the chain is solved first), then the rows before the chain of
+// every level.  Groups whose rows have no dependents outside the chain are
+// dropped.
+std::vector<std::vector<int>> phase_groups_t(const Sym& s, bool up, int t) {
+  const std::vector<int>& lv_ptr = up ? s.lvu_ptr : s.lvd_ptr;
+  const std::vector<int>& lv_rows = up ? s.lvu_rows : s.lvd_rows;
+  const int nlev = (int)lv_ptr.size() - 1, c0 = s.nx - t;
+  auto has_dep = [&](int j) {  // j has a dependent that is not a chain-internal pair
+    const bool jc = j >= c0;
+    if (up) {
+      // dependents of j: rows i > j with (i, j) in L, i.e. (j, i) in U
+      for (int e = s.f_diag[j] + 1; e < s.f_ptr[j + 1]; ++e)
+        if (!(jc && s.f_col[e] >= c0)) return true;
+    } else {
+      for (int e = s.f_ptr[j]; e < s.f_diag[j]; ++e)
+        if (!(jc && s.f_col[e] >= c0)) return true;
+    }
+    return false;
+  };
+  std::vector<std::vector<int>> g;
+  if (!up && t > 0) {
+    g.emplace_back();
+    for (int i = c0; i < s.nx; ++i) g.back().push_back(i);
+  }
+  for (int q = 0; q < nlev; ++q) {
+    std::vector<int> rows;
+    bool any = false;
+    for (int r = lv_ptr[q]; r < lv_ptr[q + 1]; ++r) {
+      const int i = lv_rows[r];
+      if (i < c0) {
+        rows.push_back(i);
+        any = any || has_dep(i);
+      }
+    }
+    if (any) g.push_back(rows);
+  }
+  return g;
+}
+
+std::vector<std::vector<int>> phase_groups(const Sym& s, bool up) { return phase_groups_t(s, up, s.chain_t); }
+
+// Tasks of one phase: (dest, source, position) sorted by dest then source,
+// split into runs of one dest.  Pairs inside the chain are left to the chain
+// solve.
 void phase_tasks(const Sym& s, const std::vector<std::vector<std::pair<int, int>>>& dep,
-                 const std::vector<int>& lv_ptr, const std::vector<int>& lv_rows, int q,
-                 std::vector<std::array<int, 3>>& items, std::vector<std::pair<int, int>>& tasks) {
+                 const std::vector<int>& sources, std::vector<std::array<int, 3>>& items,
+                 std::vector<std::pair<int, int>>& tasks) {
   items.clear();
   tasks.clear();
-  for (int r = lv_ptr[q]; r < lv_ptr[q + 1]; ++r) {
-    const int j = lv_rows[r];
-    for (auto& d : dep[j]) items.push_back({d.first, j, d.second});
-  }
+  const int c0 = s.nx - s.chain_t;
+  for (int j : sources)
+    for (auto& d : dep[j])
+      if (!(j >= c0 && d.first >= c0)) items.push_back({d.first, j, d.second});
   std::sort(items.begin(), items.end());
   for (size_t a = 0; a < items.size();) {
     size_t b = a;
@@ -123,23 +168,21 @@ void phase_tasks(const Sym& s, const std::vector<std::vector<std::pair<int, int>
     tasks.push_back({(int)a, (int)b});
     a = b;
   }
-  (void)s;
 }
 
 void build_solve_sched(const Sym& s, bool up, int S, Sched& out) {
-  const std::vector<int>& lv_ptr = up ? s.lvu_ptr : s.lvd_ptr;
-  const std::vector<int>& lv_rows = up ? s.lvu_rows : s.lvd_rows;
   const auto dep = dependents(s, up);
+  const auto groups = phase_groups(s, up);
   out = Sched();
   out.S = S;
-  out.nphase = std::max(0, (int)lv_ptr.size() - 2);
+  out.nphase = (int)groups.size();
   out.ptr.assign(1, 0);
   std::vector<std::array<int, 3>> items;
   std::vector<std::pair<int, int>> tasks;
   std::vector<std::vector<int>> slot_tasks(S);
   std::vector<long long> cost;
   for (int q = 0; q < out.nphase; ++q) {
-    phase_tasks(s, dep, lv_ptr, lv_rows, q, items, tasks);
+    phase_tasks(s, dep, groups[q], items, tasks);
     cost.resize(tasks.size());
     for (size_t t = 0; t < tasks.size(); ++t) cost[t] = tasks[t].second - tasks[t].first;
     assign_tasks(cost, S, slot_tasks);
@@ -157,12 +200,14 @@ void build_solve_sched(const Sym& s, bool up, int S, Sched& out) {
 // Refactorisation items: the entry l_ik of row i, taken when row k (level q)
 // is final, costs one multiply by 1/u_kk and one update of row i per entry of
 // the U part of row k.  upd receives, per item, the positions of (i, j) for
-// the U columns j of row k in order.
+// the U columns j of row k in order.  Items inside the chain are left to the
+// chain factorisation.
 std::string build_fac_sched(const Sym& s, int S, Sched& out, std::vector<int>& upd) {
   const auto dep = dependents(s, true);
+  const auto groups = phase_groups(s, true);
   out = Sched();
   out.S = S;
-  out.nphase = std::max(0, (int)s.lvu_ptr.size() - 2);
+  out.nphase = (int)groups.size();
   out.ptr.assign(1, 0);
   upd.clear();
   std::vector<std::array<int, 3>> items;
@@ -170,7 +215,7 @@ std::string build_fac_sched(const Sym& s, int S, Sched& out, std::vector<int>& u
   std::vector<std::vector<int>> slot_tasks(S);
   std::vector<long long> cost;
   for (int q = 0; q < out.nphase; ++q) {
-    phase_tasks(s, dep, s.lvu_ptr, s.lvu_rows, q, items, tasks);
+    phase_tasks(s, dep, groups[q], items, tasks);
     cost.assign(tasks.size(), 0);
     for (size_t t = 0; t < tasks.size(); ++t)
       for (int a = tasks[t].first; a < tasks[t].second; ++a) {
@@ -195,6 +240,30 @@ std::string build_fac_sched(const Sym& s, int S, Sched& out, std::vector<int>& u
   }
   return "";
 }
+
+// The chain: a suffix of the elimination order (at most kChainMax rows) that
+// the solves and the refactorisation take sequentially in registers.  No row
+// before it depends on it in the up direction and it depends on nothing
+// before it in the down direction, so any suffix is valid; its length is the
+// one with the fewest barrier-separated phases, counting a chain step as an
+// eighth of a phase.  chain_pos[a t + b] is the position of (c0 + a, c0 + b)
+// in the filled pattern, -1 where structurally zero.
+void find_chain(Sym& s) {
+  const int nx = s.nx;
+  int best_t = 0;
+  double best = 1e300;
+  for (int t = 0; t <= kChainMax && t <= nx; ++t) {
+    const double cost = (double)phase_groups_t(s, true, t).size() + (double)phase_groups_t(s, false, t).size() +
+                        t / 8.0;
+    if (cost < best - 1e-9) { best = cost; best_t = t; }
+  }
+  const int t = best_t < 2 ? 0 : best_t;
+  s.chain_t = t;
+  s.chain_pos.assign((size_t)t * t, -1);
+  const int c0 = nx - t;
+  for (int a = 0; a < t; ++a)
+    for (int b = 0; b < t; ++b) s.chain_pos[a * t + b] = find_pos(s.f_ptr, s.f_col, c0 + a, c0 + b);
+}
 }  // namespace
 
 LdsSizes lds_sizes(const Sym& s, int w, int variant, int spw) {
@@ -204,11 +273,12 @@ LdsSizes lds_sizes(const Sym& s, int w, int variant, int spw) {
   z.nnz_l = s.nnz_l;
   z.nlu = (int)s.lvu_ptr.size() - 1;
   z.nph_u = std::max(0, z.nlu - 1);
-  z.nph_d = std::max(0, (int)s.lvd_ptr.size() - 2);
+  z.nph_d = std::max(0, (int)s.lvd_ptr.size() - 1);  // the chain's merged phase may add one
   z.n_upd = (int)(s.lu_flops - s.nnz_l);
   z.w = w; z.variant = variant; z.spw = spw;
   z.upd_lds = s.upd_lds ? 1 : 0;
   z.nnz_h = (int)s.h_col.size(); z.m = s.m;
+  z.chain_t = s.chain_t;
   return z;
 }
 
@@ -616,6 +686,8 @@ std::string build_symbolic(const rkkt_network& net, int N, int col_tile_req, int
     }
   }
 
+  find_chain(s);  // depends on the level structure only
+
   // ---- launch shapes.  Packed 16-bit schedule entries need every index
   // below 2^16, which holds whenever the data they index fits in LDS.
   const long long lds_max = 160 * 1024;
@@ -680,6 +752,10 @@ std::string build_symbolic(const rkkt_network& net, int N, int col_tile_req, int
     std::string m = build_fac_sched(s, s.group, s.fac, s.upd_dst);
     if (!m.empty()) return m;
   }
+  // every schedule holds the pairs outside the chain exactly once (the
+  // kernels size their LDS images from one count)
+  for (const Sched* sc : {&s.red_dn, &s.stp_up, &s.stp_dn, &s.fac})
+    if (sc->ent.size() != s.red_up.ent.size()) return "internal: schedule sizes differ";
   return "";
 }
 

@@ -91,6 +91,10 @@ struct Sym {
   long long lu_flops = 0;
 
   int nnz_l = 0;  // strictly lower entries of the filled pattern (= strictly upper)
+  // chain: rows nx - chain_t .. nx - 1, each alone in its level in both
+  // directions; solved and factorised sequentially in registers
+  int chain_t = 0;
+  std::vector<int> chain_pos;  // [chain_t][chain_t] positions in the filled pattern, -1 absent
 
   // Level-sliced schedules (see Sched): the reduction's solves (S = 1024 /
   // col_tile slots), the single-column solves of the step and the

@@ -288,9 +288,14 @@ int rkkt_profile_begin(rkkt_problem* p, int max_records);
 int rkkt_profile_end(rkkt_problem* p, hipStream_t stream, double* ms, int* count);
 
 /*
- * One hot-path pass with fixed buffers: evaluate, condense, copy khat into
- * chol, factor chol in place, step (the calls above in that order, each
- * argument as documented there).
+ * One hot-path pass with fixed buffers: evaluate, condense, factor, step (the
+ * calls above, each argument as documented there), with the same results as
+ * those calls in that order, except that the factor of khat is written to
+ * chol (its lower triangle; khat is left as it is and the strict upper
+ * triangle of chol is not written).  The step's right-hand-side solves run on
+ * a second stream of the handle, concurrently with the reduction and the
+ * factorisation; the pass is ordered after earlier work on `stream`, and later
+ * work on `stream` is ordered after all of it.
  */
 typedef struct {
   const double *x, *u, *y, *z;

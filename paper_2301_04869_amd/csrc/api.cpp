@@ -338,6 +338,11 @@ int rkkt_create(const rkkt_network* net, int n_scen, const double* pd, const dou
     if ((e = dalloc(p, &d.status, 2)) != hipSuccess) goto hip_error;
     if ((e = rkkt::configure_lu_kernels(d)) != hipSuccess) goto hip_error;
     if ((e = rkkt::configure_dense_kernels(d)) != hipSuccess) goto hip_error;
+    if ((e = hipStreamCreateWithFlags(&p->side_stream, hipStreamNonBlocking)) != hipSuccess) goto hip_error;
+    for (int i = 0; i < 2; ++i) {
+      if ((e = hipEventCreateWithFlags(&p->fork_ev[i], hipEventDisableTiming)) != hipSuccess) goto hip_error;
+      if ((e = hipEventCreateWithFlags(&p->join_ev[i], hipEventDisableTiming)) != hipSuccess) goto hip_error;
+    }
     if ((e = hipMemset(d.status, 0, 2 * sizeof(int))) != hipSuccess) goto hip_error;
     // loads
     if (s.nload > 0) {
@@ -364,6 +369,9 @@ int rkkt_create(const rkkt_network* net, int n_scen, const double* pd, const dou
   return RKKT_OK;
 hip_error : {
   int rc = hip_fail(nullptr, e, "rkkt_create");
+  if (p->side_stream) (void)hipStreamDestroy(p->side_stream);
+  for (hipEvent_t ev : {p->fork_ev[0], p->fork_ev[1], p->join_ev[0], p->join_ev[1]})
+    if (ev) (void)hipEventDestroy(ev);
   for (void* q : p->allocs) (void)hipFree(q);
   delete p;
   return rc;
@@ -456,19 +464,81 @@ int rkkt_status(rkkt_problem* p, hipStream_t stream, int* code, int* scenario) {
   return RKKT_OK;
 }
 
-int rkkt_iterate(rkkt_problem* p, const rkkt_iteration* it, hipStream_t stream) {
+// The pass of rkkt_iterate.  With `fork`, two groups of kernels run on the
+// handle's side stream, concurrently with kernels of `stream` that leave
+// most compute units idle; every result is the same as with the pass on one
+// stream:
+//   A: g, h, f and gradients, W and K (after the line and Jacobian values,
+//      which are all the refactorisation reads) beside the refactorisation;
+//   B: the step's right-hand-side solves (LU factors and K only) beside the
+//      stacked product, the scenario sum and the dense factorisation.
+// Each group is a fork and a join of events; under graph capture they become
+// concurrent branches of the graph.  No return between a fork and its join,
+// so that the side stream never stays part of a capture of `stream`.
+static int iterate_impl(rkkt_problem* p, const rkkt_iteration* it, hipStream_t stream, bool fork) {
+  (void)hipGetLastError();  // do not report an earlier, unrelated error
   if (!p || !it) return fail(p, RKKT_ERR_ARG, "rkkt_iterate: null argument");
-  int rc = rkkt_evaluate(p, it->x, it->u, it->y, it->z, it->obj_weight, it->f, it->grad_x,
-                         it->grad_u, it->g, it->h, stream);
-  if (rc) return rc;
-  rc = rkkt_condense(p, it->sigma_x, it->sigma_u, it->sigma_s, it->delta_w, it->khat, stream);
-  if (rc) return rc;
-  if (!it->chol || !it->info) return fail(p, RKKT_ERR_ARG, "rkkt_iterate: null chol or info");
-  rkkt::launch_copy(it->khat, it->chol, (long long)p->d.nu * p->d.nu, stream);
-  rc = rkkt_factor(p, it->chol, it->info, stream);
-  if (rc) return rc;
-  return rkkt_step(p, it->r1x, it->r1u, it->r2, it->r3, it->r4, it->sigma_s, it->chol, it->px,
-                   it->pu, it->ps, it->py, it->pz, stream);
+  if (!it->x || !it->u || !it->y || !it->z || !it->f || !it->grad_x || !it->grad_u || !it->g ||
+      !it->h || !it->sigma_x || !it->sigma_u || !it->sigma_s || !it->khat || !it->chol ||
+      !it->info || !it->r1x || !it->r1u || !it->r2 || !it->r3 || !it->r4 || !it->px || !it->pu ||
+      !it->ps || !it->py || !it->pz)
+    return fail(p, RKKT_ERR_ARG, "rkkt_iterate: null array");
+  if (!std::isfinite(it->obj_weight)) return fail(p, RKKT_ERR_ARG, "rkkt_iterate: non-finite obj_weight");
+  if (!std::isfinite(it->delta_w)) return fail(p, RKKT_ERR_ARG, "rkkt_iterate: non-finite delta_w");
+  const rkkt::DP& d = p->d;
+  hipStream_t side = fork ? p->side_stream : stream;
+  auto fork_to_side = [&](int g) -> hipError_t {
+    if (!fork) return hipSuccess;
+    hipError_t e = hipEventRecord(p->fork_ev[g], stream);
+    return e == hipSuccess ? hipStreamWaitEvent(side, p->fork_ev[g], 0) : e;
+  };
+  auto join_record = [&](int g) -> hipError_t {
+    return fork ? hipEventRecord(p->join_ev[g], side) : hipSuccess;
+  };
+  auto join_wait = [&](int g, hipError_t recorded) -> hipError_t {
+    if (!fork || recorded != hipSuccess) return recorded;
+    return hipStreamWaitEvent(stream, p->join_ev[g], 0);
+  };
+  stage(p, RKKT_STAGE_EVALUATE, stream,
+        [&] { rkkt::launch_evaluate_values(d, it->x, it->u, stream); });
+  hipError_t e = fork_to_side(0);
+  if (e != hipSuccess) return hip_fail(p, e, "rkkt_iterate: fork");
+  stage(p, RKKT_STAGE_EVALUATE, side, [&] {
+    rkkt::launch_evaluate_rest(d, it->x, it->u, it->y, it->z, it->obj_weight, it->f, it->grad_x,
+                               it->grad_u, it->g, it->h, side);
+  });
+  stage(p, RKKT_STAGE_CONDENSE_VALUES, side,
+        [&] { rkkt::launch_condense_values(d, it->sigma_x, it->sigma_s, it->delta_w, side); });
+  hipError_t ej = join_record(0);
+  stage(p, RKKT_STAGE_REFACTOR, stream, [&] { rkkt::launch_refactor(d, stream); });
+  e = join_wait(0, ej);
+  if (e != hipSuccess) return hip_fail(p, e, "rkkt_iterate: join");
+  stage(p, RKKT_STAGE_REDUCE, stream, [&] { rkkt::launch_reduce(d, stream); });
+  e = fork_to_side(1);
+  if (e != hipSuccess) return hip_fail(p, e, "rkkt_iterate: fork");
+  stage(p, RKKT_STAGE_STEP_RHS, side, [&] {
+    rkkt::launch_step_rhs(d, it->r1x, it->r2, it->r3, it->r4, it->sigma_s, side);
+  });
+  ej = join_record(1);
+  if (d.variant == 2)
+    stage(p, RKKT_STAGE_STACKED_PRODUCT, stream, [&] { rkkt::launch_stacked_product(d, stream); });
+  stage(p, RKKT_STAGE_SCENARIO_SUM, stream,
+        [&] { rkkt::launch_scenario_sum(d, it->sigma_u, it->delta_w, it->khat, stream); });
+  stage(p, RKKT_STAGE_FACTOR, stream,
+        [&] { rkkt::launch_cholesky_from(d, it->khat, it->chol, it->info, stream); });
+  e = join_wait(1, ej);
+  if (e != hipSuccess) return hip_fail(p, e, "rkkt_iterate: join");
+  stage(p, RKKT_STAGE_REDUCED_SOLVE, stream,
+        [&] { rkkt::launch_reduced_solve(d, it->r1u, it->chol, it->pu, stream); });
+  stage(p, RKKT_STAGE_STEP_RECOVER, stream, [&] {
+    rkkt::launch_step_recover(d, it->r2, it->r3, it->r4, it->sigma_s, it->pu, it->px, it->ps,
+                              it->py, it->pz, stream);
+  });
+  return check_launch(p, "rkkt_iterate");
+}
+
+int rkkt_iterate(rkkt_problem* p, const rkkt_iteration* it, hipStream_t stream) {
+  return iterate_impl(p, it, stream, true);
 }
 
 static void release_graph(rkkt_problem* p) {
@@ -555,7 +625,9 @@ int rkkt_batch_create(rkkt_problem* const* problems, const rkkt_iteration* its, 
     if (e != hipSuccess) break;
     const bool prof = problems[i]->prof;
     problems[i]->prof = false;
-    rc = rkkt_iterate(problems[i], &its[i], b->streams[i]);
+    // the instances are concurrent branches already; each pass stays on its
+    // instance's stream (no second level of forked streams in the capture)
+    rc = iterate_impl(problems[i], &its[i], b->streams[i], false);
     problems[i]->prof = prof;
     if (rc != RKKT_OK) break;
     e = hipEventRecord(b->events[i], b->streams[i]);
@@ -719,6 +791,9 @@ int rkkt_destroy(rkkt_problem* p) {
   release_events(p);
   release_graph(p);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  if (p->side_stream) (void)hipStreamDestroy(p->side_stream);
+  for (hipEvent_t ev : {p->fork_ev[0], p->fork_ev[1], p->join_ev[0], p->join_ev[1]})
+    if (ev) (void)hipEventDestroy(ev);
   for (void* q : p->ipm_allocs) (void)hipFree(q);
   for (void* q : p->allocs) (void)hipFree(q);
   delete p;

@@ -149,6 +149,12 @@ void launch_evaluate(const DP& d, const double* x, const double* u, const double
                      double* g, double* h, hipStream_t s);
 void launch_condense_values(const DP& d, const double* sx, const double* ss, double dw,
                             hipStream_t s);
+// the two halves of launch_evaluate: line values and EV (all that the
+// refactorisation needs), then g, h, f, its gradients and W
+void launch_evaluate_values(const DP& d, const double* x, const double* u, hipStream_t s);
+void launch_evaluate_rest(const DP& d, const double* x, const double* u, const double* y,
+                          const double* z, double w, double* f, double* gx, double* gu, double* g,
+                          double* h, hipStream_t s);
 // (k_lu.hip)
 void launch_refactor(const DP& d, hipStream_t s);
 void launch_identity_rows(const DP& d, hipStream_t s);
@@ -162,6 +168,8 @@ void launch_step_recover(const DP& d, const double* r2, const double* r3, const 
 void launch_scenario_sum(const DP& d, const double* su, double dw, double* khat, hipStream_t s);
 void launch_stacked_product(const DP& d, hipStream_t s);
 void launch_cholesky(const DP& d, double* a, int* info, hipStream_t s);
+// factor of src into dst (src is left as it is)
+void launch_cholesky_from(const DP& d, const double* src, double* dst, int* info, hipStream_t s);
 void launch_reduced_solve(const DP& d, const double* r1u, const double* chol, double* pu,
                           hipStream_t s);
 

@@ -30,4 +30,7 @@ struct rkkt_problem {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
+  // second stream of rkkt_iterate and its two fork / join event pairs
+  hipStream_t side_stream = nullptr;
+  hipEvent_t fork_ev[2] = {nullptr, nullptr}, join_ev[2] = {nullptr, nullptr};
 };

@@ -250,11 +250,12 @@ __device__ int chol_blocked_lds(double* sa, int n, int ld, int* sflag) {
 constexpr int kCholSmallThreads = 512;
 
 template <int kR>
-__global__ __launch_bounds__(kCholSmallThreads) void k_chol_small(double* A, int n, int* info) {
+__global__ __launch_bounds__(kCholSmallThreads) void k_chol_small(const double* src, double* A,
+                                                                   int n, int* info) {
   extern __shared__ double sa[];
   __shared__ int sflag;
   const int ld = n + 1, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  copy2d_overlapped(sa, ld, A, n, n, n, threadIdx.x, kCholSmallThreads);
+  copy2d_overlapped(sa, ld, src, n, n, n, threadIdx.x, kCholSmallThreads);
   __syncthreads();
   const int r = chol_blocked_lds<kCholSmallThreads / 64, kR>(sa, n, ld, &sflag);
   for (int i = wv; i < n; i += kCholSmallThreads / 64)
@@ -522,15 +523,16 @@ void launch_stacked_product(const DP& d, hipStream_t s) {
   k_stacked_product<<<dim3(T * (T + 1) / 2, d.nchunk), 256, 0, s>>>(d);
 }
 
-void launch_cholesky(const DP& d, double* a, int* info, hipStream_t s) {
+void launch_cholesky_from(const DP& d, const double* src, double* a, int* info, hipStream_t s) {
   const int n = d.nu;
   if (n <= kSmallN) {
     size_t lds = 8 * (size_t)n * (n + 1);
-    if (n <= 64) k_chol_small<1><<<1, kCholSmallThreads, lds, s>>>(a, n, info);
-    else if (n <= 128) k_chol_small<2><<<1, kCholSmallThreads, lds, s>>>(a, n, info);
-    else k_chol_small<3><<<1, kCholSmallThreads, lds, s>>>(a, n, info);
+    if (n <= 64) k_chol_small<1><<<1, kCholSmallThreads, lds, s>>>(src, a, n, info);
+    else if (n <= 128) k_chol_small<2><<<1, kCholSmallThreads, lds, s>>>(src, a, n, info);
+    else k_chol_small<3><<<1, kCholSmallThreads, lds, s>>>(src, a, n, info);
     return;
   }
+  if (src != a) launch_copy(src, a, (long long)n * n, s);
   k_set_int<<<1, 1, 0, s>>>(info, 0);
   for (int jb = 0; jb < n; jb += kNB) {
     k_chol_diag<<<1, kThreads, 0, s>>>(a, n, jb, info);
@@ -542,6 +544,10 @@ void launch_cholesky(const DP& d, double* a, int* info, hipStream_t s) {
     const int nt = (rest + 63) / 64;
     k_chol_update<<<dim3(nt, nt), kThreads, 0, s>>>(a, n, jb, info);
   }
+}
+
+void launch_cholesky(const DP& d, double* a, int* info, hipStream_t s) {
+  launch_cholesky_from(d, a, a, info, s);
 }
 
 void launch_reduced_solve(const DP& d, const double* r1u, const double* chol, double* pu,

@@ -47,11 +47,10 @@ __global__ void k_bus_loads(DP d, const double* pd, const double* qd) {
   d.qdb[t] = j >= 0 ? qd[(long long)k * d.nload + j] : 0.0;
 }
 
-// a1: basis terms and first derivatives of the four line-end functions
-__global__ void k_line_eval(DP d, const double* x, const double* u) {
-  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long long)d.N * d.nl) return;
-  int k = (int)(t / d.nl), l = (int)(t % d.nl);
+// a1: basis terms and first derivatives of the four line-end functions of
+// line l; o = its 28 values
+__device__ inline void line_eval_one(const DP& d, int k, int l, const double* x, const double* u,
+                                     double* o) {
   const double* xk = x + (long long)k * d.nx;
   int bf = d.line_f[l], bt = d.line_t[l];
   double dth = bus_theta(d, xk, bf) - bus_theta(d, xk, bt);
@@ -70,7 +69,6 @@ __global__ void k_line_eval(DP d, const double* x, const double* u) {
     grad[q][2] = 2.0 * A[q] * vf + vt * T;
     grad[q][3] = 2.0 * B[q] * vt + vf * T;
   }
-  double* o = d.LV + t * kLVsize;
   for (int e = 0; e < 2; ++e) {
     double P = val[2 * e], Q = val[2 * e + 1];
     double* oe = o + 14 * e;
@@ -84,29 +82,19 @@ __global__ void k_line_eval(DP d, const double* x, const double* u) {
   }
 }
 
-// bus injections and Jacobian values on the fixed patterns
-__global__ void k_gather_ev(DP d) {
-  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long long)d.N * d.n_ev) return;
-  int k = (int)(t / d.n_ev), e = (int)(t % d.n_ev);
-  const double* lv = d.LV + (long long)k * d.nl * kLVsize;
+// one bus injection or Jacobian value on the fixed patterns; lv = the
+// scenario's line values
+__device__ inline double gather_ev_one(const DP& d, int e, const double* lv) {
   double acc = d.ev_const[e];
   for (int j = d.ev_ptr[e]; j < d.ev_ptr[e + 1]; ++j) acc += lv[d.ev_src[j]];
-  d.EV[t] = acc;
+  return acc;
 }
 
-__device__ inline double pg_ref(const DP& d, int k) {
-  return d.EV[(long long)k * d.n_ev + d.off_P + d.ref] + d.pdb[(long long)k * d.nb + d.ref];
-}
-
-// g, h, gradient of f and f itself
-__global__ void k_assemble(DP d, const double* u, double w, double* f, double* gx, double* gu,
-                           double* g, double* h) {
-  const int per = 2 * d.nx + d.m + d.nu + 1;
-  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long long)d.N * per) return;
-  int k = (int)(t / per), i = (int)(t % per);
-  const double* ev = d.EV + (long long)k * d.n_ev;
+// one entry of g, h, the gradient of f, or f itself (item i of
+// 2 nx + m + nu + 1); ev, lv = the scenario's values
+__device__ inline void assemble_one(const DP& d, int k, int i, const double* u, double w,
+                                    double* f, double* gx, double* gu, double* g, double* h,
+                                    const double* ev, const double* lv) {
   const double* pdb = d.pdb + (long long)k * d.nb;
   const double* qdb = d.qdb + (long long)k * d.nb;
   double pref = ev[d.off_P + d.ref] + pdb[d.ref];
@@ -135,8 +123,8 @@ __global__ void k_assemble(DP d, const double* u, double w, double* f, double* g
       int r = i - 1 - d.ng;
       int e = r >= d.nl ? 1 : 0;
       int l = r - e * d.nl;
-      const double* lv = d.LV + ((long long)k * d.nl + l) * kLVsize + 14 * e;
-      v = lv[0] * lv[0] + lv[1] * lv[1];
+      const double* le = lv + (long long)l * kLVsize + 14 * e;
+      v = le[0] * le[0] + le[1] * le[1];
     }
     h[(long long)k * d.m + i] = v;
     return;
@@ -169,12 +157,11 @@ __global__ void k_assemble(DP d, const double* u, double w, double* f, double* g
   f[k] = w * acc;
 }
 
-// a3: local 4x4 Hessian of every line's share of f + y^T g + z^T h
-__global__ void k_line_hess(DP d, const double* x, const double* u, const double* y,
-                            const double* z, double w) {
-  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long long)d.N * d.nl) return;
-  int k = (int)(t / d.nl), l = (int)(t % d.nl);
+// a3: local 4x4 Hessian of line l's share of f + y^T g + z^T h; le = the
+// line's 28 values, o = its 10 Hessian values
+__device__ inline void line_hess_one(const DP& d, int k, int l, const double* x, const double* u,
+                                     const double* y, const double* z, double w,
+                                     const double* ev, const double* le0, double* o) {
   const double* xk = x + (long long)k * d.nx;
   const double* yk = y + (long long)k * d.nx;
   const double* zk = z + (long long)k * d.m;
@@ -185,17 +172,17 @@ __global__ void k_line_hess(DP d, const double* x, const double* u, const double
   sincos(dth, &sn, &cs);
   double A[4], B[4], C[4], D[4];
   line_coeffs(d.gs[l], d.bs[l], d.bc[l], A, B, C, D);
-  const double* lv = d.LV + t * kLVsize;
+  const double pgref = ev[d.off_P + d.ref] + d.pdb[(long long)k * d.nb + d.ref];
   double H[kLHsize];
   for (int q = 0; q < kLHsize; ++q) H[q] = 0.0;
   for (int e = 0; e < 2; ++e) {
     int b = bus[e];
     double wP, wQ;
     if (d.prow[b] >= 0) wP = yk[d.prow[b]];
-    else wP = zk[0] + w * (2.0 * d.aref * pg_ref(d, k) + d.bref);
+    else wP = zk[0] + w * (2.0 * d.aref * pgref + d.bref);
     wQ = d.qrow[b] >= 0 ? yk[d.qrow[b]] : zk[1 + (-d.qrow[b] - 1)];
     double zs = zk[1 + d.ng + e * d.nl + l];
-    const double* le = lv + 14 * e;
+    const double* le = le0 + 14 * e;
     double mu[2] = {wP + 2.0 * zs * le[0], wQ + 2.0 * zs * le[1]};
     for (int f2 = 0; f2 < 2; ++f2) {
       int q = 2 * e + f2;
@@ -219,37 +206,78 @@ __global__ void k_line_hess(DP d, const double* x, const double* u, const double
         for (int bq = a; bq < 4; ++bq) H[lh_index(a, bq)] += c2 * gr[a] * gr[bq];
     }
   }
-  double* o = d.LH + t * kLHsize;
   for (int q = 0; q < kLHsize; ++q) o[q] = H[q];
 }
 
-// Hessian of the Lagrangian on the pattern of K
-__global__ void k_w_gather(DP d, double w) {
-  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long long)d.N * d.nnz_k) return;
-  int k = (int)(t / d.nnz_k), e = (int)(t % d.nnz_k);
-  const double* lh = d.LH + (long long)k * d.nl * kLHsize;
-  const double* hv = d.EV + (long long)k * d.n_ev + d.off_h;
+// Hessian of the Lagrangian at entry e of the pattern of K; lh = the
+// scenario's line Hessians, hv = its Jacobian values of h
+__device__ inline double w_gather_one(const DP& d, int e, double w, const double* lh,
+                                      const double* hv) {
   double acc = 0.0;
   for (int j = d.w_ptr[e]; j < d.w_ptr[e + 1]; ++j) acc += lh[d.w_src[j]];
   double prod = d.w_const[e];
   for (int j = d.wp_ptr[e]; j < d.wp_ptr[e + 1]; ++j) prod += d.wp_coef[j] * hv[d.wp_a[j]] * hv[d.wp_b[j]];
-  d.W[t] = acc + w * prod;
+  return acc + w * prod;
 }
 
-// a4: K = W + H^T Sigma_s H + diag(Sigma_x) + delta_w on the x block
-__global__ void k_condense_values(DP d, const double* sx, const double* ss, double dw) {
+__global__ void k_line_eval(DP d, const double* x, const double* u) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)d.N * d.nl) return;
+  line_eval_one(d, (int)(t / d.nl), (int)(t % d.nl), x, u, d.LV + t * kLVsize);
+}
+
+__global__ void k_gather_ev(DP d) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)d.N * d.n_ev) return;
+  int k = (int)(t / d.n_ev), e = (int)(t % d.n_ev);
+  d.EV[t] = gather_ev_one(d, e, d.LV + (long long)k * d.nl * kLVsize);
+}
+
+__global__ void k_assemble(DP d, const double* u, double w, double* f, double* gx, double* gu,
+                           double* g, double* h) {
+  const int per = 2 * d.nx + d.m + d.nu + 1;
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)d.N * per) return;
+  int k = (int)(t / per), i = (int)(t % per);
+  assemble_one(d, k, i, u, w, f, gx, gu, g, h, d.EV + (long long)k * d.n_ev,
+               d.LV + (long long)k * d.nl * kLVsize);
+}
+
+__global__ void k_line_hess(DP d, const double* x, const double* u, const double* y,
+                            const double* z, double w) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)d.N * d.nl) return;
+  int k = (int)(t / d.nl), l = (int)(t % d.nl);
+  line_hess_one(d, k, l, x, u, y, z, w, d.EV + (long long)k * d.n_ev, d.LV + t * kLVsize,
+                d.LH + t * kLHsize);
+}
+
+__global__ void k_w_gather(DP d, double w) {
   long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (long long)d.N * d.nnz_k) return;
   int k = (int)(t / d.nnz_k), e = (int)(t % d.nnz_k);
-  const double* hv = d.EV + (long long)k * d.n_ev + d.off_h;
+  d.W[t] = w_gather_one(d, e, w, d.LH + (long long)k * d.nl * kLHsize,
+                        d.EV + (long long)k * d.n_ev + d.off_h);
+}
+
+// a4: entry e of K = W + H^T Sigma_s H + diag(Sigma_x) + delta_w on the x
+// block; wv = W at e, hv = the scenario's Jacobian values of h
+__device__ inline double condense_value(const DP& d, int k, int e, double wv, const double* hv,
+                                        const double* sx, const double* ss, double dw) {
   const double* sk = ss + (long long)k * d.m;
-  double acc = d.W[t];
+  double acc = wv;
   for (int j = d.t_ptr[e]; j < d.t_ptr[e + 1]; ++j) acc += sk[d.t_row[j]] * hv[d.t_a[j]] * hv[d.t_b[j]];
   int r = d.k_row[e];
   if (r < d.nx && d.k_col[e] == r) acc += sx[(long long)k * d.nx + d.perm[r]] + dw;
   if (!isfinite(acc)) atomicCAS(d.status, 0, RKKT_ERR_NONFINITE);
-  d.K[t] = acc;
+  return acc;
+}
+
+__global__ void k_condense_values(DP d, const double* sx, const double* ss, double dw) {
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)d.N * d.nnz_k) return;
+  int k = (int)(t / d.nnz_k), e = (int)(t % d.nnz_k);
+  d.K[t] = condense_value(d, k, e, d.W[t], d.EV + (long long)k * d.n_ev + d.off_h, sx, ss, dw);
 }
 
 }  // namespace
@@ -259,18 +287,29 @@ void launch_bus_loads(const DP& d, const double* pd, const double* qd, hipStream
   k_bus_loads<<<grid_for(n), kBlock, 0, s>>>(d, pd, qd);
 }
 
-void launch_evaluate(const DP& d, const double* x, const double* u, const double* y,
-                     const double* z, double w, double* f, double* gx, double* gu, double* g,
-                     double* h, hipStream_t s) {
+void launch_evaluate_values(const DP& d, const double* x, const double* u, hipStream_t s) {
   long long nl = (long long)d.N * d.nl;
   k_line_eval<<<grid_for(nl), kBlock, 0, s>>>(d, x, u);
   long long ne = (long long)d.N * d.n_ev;
   k_gather_ev<<<grid_for(ne), kBlock, 0, s>>>(d);
+}
+
+void launch_evaluate_rest(const DP& d, const double* x, const double* u, const double* y,
+                          const double* z, double w, double* f, double* gx, double* gu, double* g,
+                          double* h, hipStream_t s) {
   long long na = (long long)d.N * (2 * d.nx + d.m + d.nu + 1);
   k_assemble<<<grid_for(na), kBlock, 0, s>>>(d, u, w, f, gx, gu, g, h);
+  long long nl = (long long)d.N * d.nl;
   k_line_hess<<<grid_for(nl), kBlock, 0, s>>>(d, x, u, y, z, w);
   long long nk = (long long)d.N * d.nnz_k;
   k_w_gather<<<grid_for(nk), kBlock, 0, s>>>(d, w);
+}
+
+void launch_evaluate(const DP& d, const double* x, const double* u, const double* y,
+                     const double* z, double w, double* f, double* gx, double* gu, double* g,
+                     double* h, hipStream_t s) {
+  launch_evaluate_values(d, x, u, s);
+  launch_evaluate_rest(d, x, u, y, z, w, f, gx, gu, g, h, s);
 }
 
 void launch_condense_values(const DP& d, const double* sx, const double* ss, double dw,

@@ -335,6 +335,7 @@ int rkkt_create(const rkkt_network* net, int n_scen, const double* pd, const dou
     if ((e = dalloc(p, &d.rhat1, N * s.nx)) != hipSuccess) goto hip_error;
     if ((e = dalloc(p, &d.wbuf, d.lds_stp ? 1 : N * (size_t)s.m)) != hipSuccess) goto hip_error;
     if ((e = dalloc(p, &d.rpart, N * s.nu)) != hipSuccess) goto hip_error;
+    if ((e = dalloc(p, &d.qbuf, N * s.nx)) != hipSuccess) goto hip_error;
     if ((e = dalloc(p, &d.status, 2)) != hipSuccess) goto hip_error;
     if ((e = rkkt::configure_lu_kernels(d)) != hipSuccess) goto hip_error;
     if ((e = rkkt::configure_dense_kernels(d)) != hipSuccess) goto hip_error;

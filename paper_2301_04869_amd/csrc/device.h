@@ -72,6 +72,7 @@ struct DP {
   double *rhat1;   // [N][nx] internal order
   double *wbuf;    // [N][m] step work vector (global-memory step kernels)
   double *rpart;   // [N][nu]
+  double *qbuf;    // [N][nx] internal order: G_x^-1 r3 of the last step right-hand side
   int *status;     // [2]: code, scenario
 };
 

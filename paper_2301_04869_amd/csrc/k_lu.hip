@@ -995,6 +995,201 @@ __global__ __launch_bounds__(kT) void k_step_recover(DP d, const double* r2, con
   }
 }
 
+// ------------------------------------- step of the stacked variant
+// The stacked reduction leaves Z = [T; I], T = -G_x^-1 G_u (internal row
+// order, row pitch nu_pad), in HBM.  With it G_u^T G_x^-T b = -T^T b and
+// G_x^-1 G_u p_u = -T p_u, so each step kernel keeps one sparse solve: the
+// right-hand side keeps q = G_x^-1 r3, the recovery keeps p_y.  Wavefront 0
+// runs that solve on LDS data while the other wavefronts compute the terms
+// that do not depend on it; the dense products with T read Z with
+// consecutive lanes on consecutive columns.
+
+// the sweep-group view of the staged factor and schedule blob
+__device__ __forceinline__ StepView sweep_view(const DP& d, double* lu, unsigned* ue) {
+  StepView w{};
+  w.lu = lu;
+  w.invd = lu + d.nnz_f;
+  unsigned* de = ue + 2 * d.n_sent;
+  int* ip = reinterpret_cast<int*>(de + 2 * d.n_sent);
+  w.uptr = ip;
+  w.dptr = ip + d.nph_u * kGroupLds + 1;
+  w.uent = ue;
+  w.dent = de;
+  return w;
+}
+
+// out[c] = sum_i Z[i][c] b[i] for c < nu; kT threads as row slices x columns,
+// partial sums through red[kT + nu] (LDS), one barrier inside
+template <int kT>
+__device__ __forceinline__ void dense_tt_times(const DP& d, const double* __restrict__ Zk,
+                                               const double* b, double* red) {
+  const int nu = d.nu, nx = d.nx, ld = d.nu_pad, tid = threadIdx.x;
+  const bool wide = nu >= kT;
+  const int ns = wide ? 1 : kT / nu;
+  const int s = wide ? 0 : tid / nu;
+  if (s < ns) {
+    for (int c = wide ? tid : tid - s * nu; c < nu; c += wide ? kT : nu) {
+      double a0 = 0.0, a1 = 0.0;
+      int i = s;
+      for (; i + ns < nx; i += 2 * ns) {
+        a0 = fma(Zk[(long long)i * ld + c], b[i], a0);
+        a1 = fma(Zk[(long long)(i + ns) * ld + c], b[i + ns], a1);
+      }
+      if (i < nx) a0 = fma(Zk[(long long)i * ld + c], b[i], a0);
+      red[s * nu + c] = a0 + a1;
+    }
+  }
+  __syncthreads();
+}
+
+template <int kT>
+__global__ __launch_bounds__(kT) void k_step_rhs2(DP d, const double* r1x, const double* r2,
+                                                  const double* r3, const double* r4,
+                                                  const double* ss) {
+  extern __shared__ double smem[];
+  const int k = blockIdx.x, tid = threadIdx.x;
+  const int nx = d.nx, nu = d.nu, m = d.m, nf = d.nnz_f;
+  double* lu = smem;
+  double* q = lu + nf + nx;
+  double* b = q + nx;
+  double* part = b + nx;
+  double* red = part + nu;
+  unsigned* ue = reinterpret_cast<unsigned*>(red + kT + nu);
+  stage_copy(lu, lu_of(d, k), nf + nx, tid, kT);
+  stage_words(ue, d.blob_stp, d.blob_stp_words, tid, kT);
+  const double* r3k = r3 + (long long)k * nx;
+  for (int i = tid; i < nx; i += kT) q[i] = r3k[d.perm[i]];
+  __syncthreads();
+  if (tid < 64) {
+    solve_fwd<true>(d, sweep_view(d, lu, ue), q, tid, [] { wave_sync(); });
+  } else {
+    // rhat1 = r1x + H_x^T w and H_u^T w, with w = Sigma_s r4 - r2 formed per use
+    const double* hv = d.EV + (long long)k * d.n_ev + d.off_h;
+    const double* ssk = ss + (long long)k * m;
+    const double* r2k = r2 + (long long)k * m;
+    const double* r4k = r4 + (long long)k * m;
+    const double* r1k = r1x + (long long)k * nx;
+    for (int v = tid - 64; v < nx + nu; v += kT - 64) {
+      double acc = v < nx ? r1k[d.perm[v]] : 0.0;
+      const int j1 = d.ht_ptr[v + 1];
+      for (int j = d.ht_ptr[v]; j < j1; ++j) {
+        const int r = d.ht_row[j];
+        acc = fma(hv[d.ht_pos[j]], ssk[r] * r4k[r] - r2k[r], acc);
+      }
+      if (v < nx) b[v] = acc;
+      else part[v - nx] = -acc;
+    }
+  }
+  __syncthreads();
+  // b = rhat1 - K_xx q; rhat1 and q are kept for the recovery
+  const double* Kk = d.K + (long long)k * d.nnz_k;
+  double* grh1 = d.rhat1 + (long long)k * nx;
+  double* gq = d.qbuf + (long long)k * nx;
+  for (int i = tid; i < nx; i += kT) {
+    const double rh = b[i];
+    grh1[i] = rh;
+    gq[i] = q[i];
+    double acc = rh;
+    const int e1 = d.k_usplit[i];
+    for (int e = d.k_ptr[i]; e < e1; ++e) acc = fma(-Kk[e], q[d.k_col[e]], acc);
+    b[i] = acc;
+  }
+  __syncthreads();
+  dense_tt_times<kT>(d, d.Zst + (long long)k * d.nz * d.nu_pad, b, red);
+  // rpart = -H_u^T w + K_ux q - T^T b
+  const int ns = nu >= kT ? 1 : kT / nu;
+  for (int c = tid; c < nu; c += kT) {
+    const int v = nx + c;
+    double acc = part[c];
+    const int e1 = d.k_usplit[v];
+    for (int e = d.k_ptr[v]; e < e1; ++e) acc = fma(Kk[e], q[d.k_col[e]], acc);
+    double tb = 0.0;
+    for (int s = 0; s < ns; ++s) tb += red[s * nu + c];
+    d.rpart[(long long)k * nu + c] = acc - tb;
+  }
+}
+
+template <int kT>
+__global__ __launch_bounds__(kT) void k_step_recover2(DP d, const double* r2, const double* r3,
+                                                      const double* r4, const double* ss,
+                                                      const double* pu, double* px, double* ps,
+                                                      double* py, double* pz) {
+  extern __shared__ double smem[];
+  const int k = blockIdx.x, tid = threadIdx.x;
+  const int nx = d.nx, nu = d.nu, m = d.m, nf = d.nnz_f;
+  double* lu = smem;
+  double* xv = lu + nf + nx;
+  double* yv = xv + nx;
+  double* spu = yv + nx;
+  unsigned* ue = reinterpret_cast<unsigned*>(spu + nu + kT + nu);
+  stage_copy(lu, lu_of(d, k), nf + nx, tid, kT);
+  stage_words(ue, d.blob_stp, d.blob_stp_words, tid, kT);
+  for (int c = tid; c < nu; c += kT) spu[c] = pu[c];
+  __syncthreads();
+  // p_x = -q + T p_u: 16-lane groups per row of T, columns across the group
+  {
+    const double* Zk = d.Zst + (long long)k * d.nz * d.nu_pad;
+    const double* gq = d.qbuf + (long long)k * nx;
+    const int g = tid >> 4, l = tid & 15;
+    for (int i = g; i < nx; i += kT / 16) {
+      const double* zr = Zk + (long long)i * d.nu_pad;
+      double a0 = 0.0, a1 = 0.0;
+      int c = l;
+      for (; c + 16 < nu; c += 32) {
+        a0 = fma(zr[c], spu[c], a0);
+        a1 = fma(zr[c + 16], spu[c + 16], a1);
+      }
+      if (c < nu) a0 = fma(zr[c], spu[c], a0);
+      double acc = a0 + a1;
+      acc += __shfl_xor(acc, 8, 16);
+      acc += __shfl_xor(acc, 4, 16);
+      acc += __shfl_xor(acc, 2, 16);
+      acc += __shfl_xor(acc, 1, 16);
+      if (l == 0) {
+        const double x = acc - gq[i];
+        xv[i] = x;
+        px[(long long)k * nx + d.perm[i]] = x;
+      }
+    }
+  }
+  __syncthreads();
+  // p_y = -G_x^-T (rhat1 + K_x. [p_x; p_u]), prescaled by 1/u_ii
+  const double* Kk = d.K + (long long)k * d.nnz_k;
+  const double* grh1 = d.rhat1 + (long long)k * nx;
+  const double* invd = lu + nf;
+  for (int i = tid; i < nx; i += kT) {
+    double acc = grh1[i];
+    const int e1 = d.k_ptr[i + 1];
+    for (int e = d.k_ptr[i]; e < e1; ++e) {
+      const int cc = d.k_col[e];
+      acc = fma(Kk[e], cc < nx ? xv[cc] : spu[cc - nx], acc);
+    }
+    yv[i] = -acc * invd[i];
+  }
+  __syncthreads();
+  if (tid < 64) {
+    solve_adj_scaled<true>(d, sweep_view(d, lu, ue), yv, tid, [] { wave_sync(); });
+  } else {
+    // p_s = -(r4 + H p_d), p_z = Sigma_s (H p_d + r4) - r2, beside the solve
+    const double* hv = d.EV + (long long)k * d.n_ev + d.off_h;
+    const double* ssk = ss + (long long)k * m;
+    const double* r2k = r2 + (long long)k * m;
+    const double* r4k = r4 + (long long)k * m;
+    for (int r = tid - 64; r < m; r += kT - 64) {
+      double hp = 0.0;
+      const int e1 = d.h_ptr[r + 1];
+      for (int e = d.h_ptr[r]; e < e1; ++e) {
+        const int cc = d.h_col[e];
+        hp = fma(hv[e], cc < nx ? xv[cc] : spu[cc - nx], hp);
+      }
+      ps[(long long)k * m + r] = -(r4k[r] + hp);
+      pz[(long long)k * m + r] = ssk[r] * (hp + r4k[r]) - r2k[r];
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < nx; i += kT) py[(long long)k * nx + d.perm[i]] = yv[i];
+}
+
 // rows nx .. nz of every scenario block of the stacked Z are the identity
 __global__ void k_identity_rows(DP d) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1025,6 +1220,11 @@ hipError_t configure_lu_kernels(const DP& d) {
   if (e == hipSuccess && d.lds_stp) {
     e = allow_lds((const void*)k_step_rhs<true, kGT>, &c3, step_lds_bytes(z));
     if (e == hipSuccess) e = allow_lds((const void*)k_step_recover<true, kGT>, &c4, step_lds_bytes(z));
+    if (e == hipSuccess && d.variant == 2) {
+      static int c9 = 0, c10 = 0;
+      e = allow_lds((const void*)k_step_rhs2<kGT>, &c9, step2_lds_bytes(z, kGT));
+      if (e == hipSuccess) e = allow_lds((const void*)k_step_recover2<kGT>, &c10, step2_lds_bytes(z, kGT));
+    }
   }
   if (e == hipSuccess && d.lds_red) {
     if (d.col_tile == kW64) {
@@ -1077,9 +1277,14 @@ void launch_reduce(const DP& d, hipStream_t s) {
   }
 }
 
+// the stacked variant's one-solve step kernels (LDS mode)
+static bool step2(const DP& d) { return d.variant == 2 && d.lds_stp; }
+
 void launch_step_rhs(const DP& d, const double* r1x, const double* r2, const double* r3,
                      const double* r4, const double* ss, hipStream_t s) {
-  if (d.lds_stp)
+  if (step2(d))
+    k_step_rhs2<kGT><<<d.N, kGT, step2_lds_bytes(sizes_of(d), kGT), s>>>(d, r1x, r2, r3, r4, ss);
+  else if (d.lds_stp)
     k_step_rhs<true, kGT><<<d.N, kGT, step_lds_bytes(sizes_of(d)), s>>>(d, r1x, r2, r3, r4, ss);
   else
     k_step_rhs<false, kRT><<<d.N, kRT, 0, s>>>(d, r1x, r2, r3, r4, ss);
@@ -1088,7 +1293,10 @@ void launch_step_rhs(const DP& d, const double* r1x, const double* r2, const dou
 void launch_step_recover(const DP& d, const double* r2, const double* r3, const double* r4,
                          const double* ss, const double* pu, double* px, double* ps, double* py,
                          double* pz, hipStream_t s) {
-  if (d.lds_stp)
+  if (step2(d))
+    k_step_recover2<kGT><<<d.N, kGT, step2_lds_bytes(sizes_of(d), kGT), s>>>(d, r2, r3, r4, ss, pu,
+                                                                            px, ps, py, pz);
+  else if (d.lds_stp)
     k_step_recover<true, kGT><<<d.N, kGT, step_lds_bytes(sizes_of(d)), s>>>(d, r2, r3, r4, ss, pu, px,
                                                                            ps, py, pz);
   else

@@ -75,4 +75,11 @@ __host__ __device__ inline long long step_lds_bytes(const LdsSizes& z) {
          4LL * (4LL * z.nnz_l + (z.nph_u * (long long)kGroupLds + 1) + (z.nph_d * (long long)kGroupLds + 1) + 2);
 }
 
+// step kernels of the stacked variant: lu[nnz_f] invd[nx] v0[nx] v1[nx]
+// vu[nu] red[threads + nu] (doubles), then the step schedule blob
+__host__ __device__ inline long long step2_lds_bytes(const LdsSizes& z, int threads) {
+  return 8LL * ((long long)z.nnz_f + 3LL * z.nx + 2LL * z.nu + threads) +
+         4LL * (4LL * z.nnz_l + (z.nph_u * (long long)kGroupLds + 1) + (z.nph_d * (long long)kGroupLds + 1) + 2);
+}
+
 }  // namespace rkkt

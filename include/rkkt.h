@@ -202,11 +202,16 @@ int rkkt_condense(rkkt_problem* p, const double* sigma_x, const double* sigma_u,
                   const double* sigma_s, double delta_w, double* khat, hipStream_t stream);
 
 /*
- * Dense Cholesky khat = L L^T in place (lower triangle, row-major; the strict
- * upper triangle is not referenced).  The reduced matrix is factorised
+ * Dense Cholesky khat = L L^T in place (lower triangle, row-major; the input's
+ * strict upper triangle is not referenced).  The reduced matrix is factorised
  * densely in the paper ("Lapack on the GPU").  info_dev (device int) gets 0
  * on success or the 1-based column of the first non-positive pivot, which
- * signals wrong inertia of the condensed KKT system.
+ * signals wrong inertia of the condensed KKT system.  For n_u <= 128, on
+ * success, the strict upper triangle of each 16 x 16 diagonal block (rows and
+ * columns 16 b .. 16 b + 15) receives the transpose of the strict lower
+ * triangle of that block's inverse (khat[j][i] = (L_bb^-1)[i][j], i > j),
+ * which rkkt_step applies as small dense products; the rest of the strict
+ * upper triangle is left as it was.
  */
 int rkkt_factor(rkkt_problem* p, double* khat, int* info_dev, hipStream_t stream);
 

@@ -138,6 +138,14 @@ __device__ __forceinline__ void copy2d_overlapped(T* dst, int ldd, const T* __re
   }
 }
 
+// orders the LDS accesses of one wavefront: what its lanes wrote before is
+// seen by its lanes after
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 // dynamic LDS limits of the kernels for this problem's sizes; called by rkkt_create
 hipError_t configure_lu_kernels(const DP& d);
 hipError_t configure_dense_kernels(const DP& d);

@@ -10,7 +10,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kNB = 64;          // panel width of the blocked factorisation
-constexpr int kSmallN = 140;     // whole matrix in LDS up to this order
+constexpr int kSmallN = 128;     // whole matrix (padded to a multiple of 16) in LDS up to this order
 constexpr int kWavesD = kThreads / 64;
 
 __global__ void k_set_int(int* p, int v) { *p = v; }
@@ -148,20 +148,33 @@ __device__ __forceinline__ double rcp_nr(double d) {
 }
 
 // Right-looking blocked Cholesky of the lower triangle of an n x n block held
-// in LDS (row-major, leading dimension ld), n <= 64 kR, by a workgroup of
-// 64 kWaves threads.  Panels of kPB columns: wavefront 0 factorises the panel
-// in registers (lane l holds rows jb + l + 64 t; the diagonal row jb + p is
-// in lane p, so its entries are broadcast with readlane and no
-// synchronisation is needed inside the panel).  Inside the panel the
-// elimination runs in the square-root-free form A = W D^-1 W^T (column p of W
-// is the updated column p of A, D its diagonal), so the dependency chain from
-// one column to the next holds one reciprocal; the panel's columns are then
-// scaled to L = W D^-1/2 together.  The trailing lower triangle is updated in
-// 16 x 16 tiles on the FP64 matrix cores (v_mfma_f64_16x16x4f64: A operand
-// lane holds row lane%16, k = lane/16; B operand k = lane/16, column lane%16;
-// result register r of a lane is row lane/16 + 4 r, column lane%16).
+// in LDS (row-major, leading dimension ld), n a multiple of kPB (callers pad
+// with identity rows and columns) and n <= 64 kR, by a workgroup of 64 kWaves
+// threads.  Panels of kPB columns: wavefront 0 factorises the panel in
+// registers (lane l holds rows jb + l + 64 t; the diagonal row jb + p is in
+// lane p).  Inside the panel the elimination runs in the square-root-free
+// form A = W D^-1 W^T (column p of W is the updated column p of A, D its
+// diagonal): for column p one vector multiply forms every multiplier
+// w_qp / d_p in lane q, and readlane broadcasts each to the rows, so the
+// chain from one column to the next holds one reciprocal.  The panel's
+// columns are then scaled to L = W D^-1/2 together, and its pivots checked
+// once.  The inverse of each 16 x 16 diagonal block of L is formed on the way
+// and left, transposed, in the block's strict upper triangle (its diagonal is
+// 1 / L_aa).  The trailing lower triangle is updated in 16 x 16 tiles on the FP64
+// matrix cores (v_mfma_f64_16x16x4f64: A operand lane holds row lane%16,
+// k = lane/16; B operand k = lane/16, column lane%16; result register r of a
+// lane is row lane/16 + 4 r, column lane%16).
 // Returns 0 or the 1-based first column whose pivot is not positive.
 constexpr int kPB = 16;
+
+// identity rows n .. np - 1 (columns 0 .. np - 1) below an n x n block in LDS
+__device__ __forceinline__ void pad_identity(double* sa, int ld, int n, int np, int t0, int ts) {
+  const int cnt = (np - n) * np;
+  for (int t = t0; t < cnt; t += ts) {
+    const int r = n + t / np, c = t % np;
+    sa[r * ld + c] = r == c ? 1.0 : 0.0;
+  }
+}
 
 template <int kWaves, int kR>
 __device__ int chol_blocked_lds(double* sa, int n, int ld, int* sflag) {
@@ -169,58 +182,64 @@ __device__ int chol_blocked_lds(double* sa, int n, int ld, int* sflag) {
   if (tid == 0) *sflag = 0;
   __syncthreads();
   for (int jb = 0; jb < n; jb += kPB) {
-    const int nb = min(kPB, n - jb);
     if (wv == 0) {
       double x[kR][kPB];
 #pragma unroll
       for (int t = 0; t < kR; ++t) {
         const int r = jb + lane + 64 * t;
 #pragma unroll
-        for (int p = 0; p < kPB; ++p) x[t][p] = (r < n && p < nb) ? sa[r * ld + jb + p] : 0.0;
+        for (int p = 0; p < kPB; ++p) x[t][p] = r < n ? sa[r * ld + jb + p] : 0.0;
       }
-      int bad = 0;
       double dpiv[kPB];
+      // lanes 0..15 also carry row `lane` of the identity through the same
+      // column operations, which leaves row r of W_bb^-T D_bb (the inverse
+      // of the diagonal block's unit factor, transposed) in lane r
+      double y[kPB];
+#pragma unroll
+      for (int q = 0; q < kPB; ++q) y[q] = q == lane ? 1.0 : 0.0;
+      double dv = readlane_d(x[0][0], 0);
 #pragma unroll
       for (int p = 0; p < kPB; ++p) {
-        dpiv[p] = 1.0;
-        if (p < nb && !bad) {
-          const double dv = readlane_d(x[0][p], p);
-          if (!(dv > 0.0) || !isfinite(dv)) {
-            bad = jb + p + 1;
-          } else {
-            dpiv[p] = dv;
-            const double inv = rcp_nr(dv);
+        dpiv[p] = dv;
+        const double m = x[0][p] * rcp_nr(dv);  // lane q: w_qp / d_p
+        // the next pivot from lane p + 1's own multiplier: the same operands
+        // as its update below, taken first to keep the column chain short
+        if (p + 1 < kPB) dv = readlane_d(fma(-x[0][p], m, x[0][p + 1]), p + 1);
 #pragma unroll
-            for (int q = p + 1; q < kPB; ++q) {
-              if (q < nb) {
-                const double lq = readlane_d(x[0][p], q) * inv;  // w_qp / d_p
+        for (int q = p + 1; q < kPB; ++q) {
+          const double mq = readlane_d(m, q);
 #pragma unroll
-                for (int t = 0; t < kR; ++t) x[t][q] = fma(-x[t][p], lq, x[t][q]);
-              }
-            }
-          }
+          for (int t = 0; t < kR; ++t) x[t][q] = fma(-x[t][p], mq, x[t][q]);
+          y[q] = fma(-y[p], mq, y[q]);
         }
       }
+      int bad = 0;
+#pragma unroll
+      for (int p = kPB - 1; p >= 0; --p)
+        if (!(dpiv[p] > 0.0) || !isfinite(dpiv[p])) bad = jb + p + 1;
       if (bad) {
         if (lane == 0) *sflag = bad;
       } else {
-        // L = W D^-1/2 for the whole panel (independent chains)
+        // L = W D^-1/2 for the whole panel (independent chains); the
+        // diagonal block's inverse, (L_bb^-1)[q][r] = y_q(lane r) / sqrt(d_q),
+        // goes transposed into the block's strict upper triangle
 #pragma unroll
         for (int p = 0; p < kPB; ++p) {
           const double rs = rsqrt_nr(dpiv[p]);
 #pragma unroll
           for (int t = 0; t < kR; ++t) {
             const int r = jb + lane + 64 * t;
-            if (r < n && p < nb && jb + p <= r) sa[r * ld + jb + p] = r == jb + p ? dpiv[p] * rs : x[t][p] * rs;
+            if (r < n && jb + p <= r) sa[r * ld + jb + p] = r == jb + p ? dpiv[p] * rs : x[t][p] * rs;
           }
+          if (lane < p) sa[(jb + lane) * ld + jb + p] = y[p] * rs;
         }
       }
     }
     __syncthreads();
     if (*sflag) return *sflag;
-    const int s0 = jb + nb, rest = n - s0;
+    const int s0 = jb + kPB, rest = n - s0;
     if (rest <= 0) break;
-    const int nt = (rest + 15) / 16;
+    const int nt = rest / 16;
     const int lm = lane & 15, lk = lane >> 4;
     int cnt = 0;
     for (int ti = 0; ti < nt; ++ti)
@@ -230,14 +249,14 @@ __device__ int chol_blocked_lds(double* sa, int n, int ld, int* sflag) {
         v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int k0 = 0; k0 < kPB; k0 += 4) {
-          const double a = i0 + lm < n ? sa[(i0 + lm) * ld + jb + k0 + lk] : 0.0;
-          const double b = l0 + lm < n ? sa[(l0 + lm) * ld + jb + k0 + lk] : 0.0;
+          const double a = sa[(i0 + lm) * ld + jb + k0 + lk];
+          const double b = sa[(l0 + lm) * ld + jb + k0 + lk];
           acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int i = i0 + lk + 4 * r, l = l0 + lm;
-          if (i < n && l <= i) sa[i * ld + l] -= acc[r];
+          if (l <= i) sa[i * ld + l] -= acc[r];
         }
       }
     __syncthreads();
@@ -248,18 +267,28 @@ __device__ int chol_blocked_lds(double* sa, int n, int ld, int* sflag) {
 // whole matrix in LDS (leading dimension n + 1); kR = rows per lane of the
 // panel factorisation (n <= 64 kR)
 constexpr int kCholSmallThreads = 512;
+constexpr int kCholSmallWaves = kCholSmallThreads / 64;
 
+// Factor of an n x n matrix (n <= kSmallN) in one workgroup, padded in LDS
+// to a multiple of 16 with identity rows.  A's lower triangle receives L and,
+// on success, the strict upper triangle of each 16 x 16 diagonal block the
+// transpose of that block's inverse (A[b][a] = (L_bb^-1)[a][b], a > b), which
+// the reduced solve applies as small dense products.
 template <int kR>
 __global__ __launch_bounds__(kCholSmallThreads) void k_chol_small(const double* src, double* A,
                                                                    int n, int* info) {
   extern __shared__ double sa[];
   __shared__ int sflag;
-  const int ld = n + 1, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int np = (n + kPB - 1) / kPB * kPB;
+  const int ld = np + 1, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   copy2d_overlapped(sa, ld, src, n, n, n, threadIdx.x, kCholSmallThreads);
+  pad_identity(sa, ld, n, np, threadIdx.x, kCholSmallThreads);
   __syncthreads();
-  const int r = chol_blocked_lds<kCholSmallThreads / 64, kR>(sa, n, ld, &sflag);
-  for (int i = wv; i < n; i += kCholSmallThreads / 64)
-    for (int l = lane; l <= i; l += 64) A[(long long)i * n + l] = sa[i * ld + l];
+  const int r = chol_blocked_lds<kCholSmallWaves, kR>(sa, np, ld, &sflag);
+  for (int i = wv; i < n; i += kCholSmallWaves) {
+    const int l1 = r == 0 ? min(n, (i / kPB + 1) * kPB) : i + 1;
+    for (int l = lane; l < l1; l += 64) A[(long long)i * n + l] = sa[i * ld + l];
+  }
   if (threadIdx.x == 0) *info = r;
 }
 
@@ -270,9 +299,11 @@ __global__ __launch_bounds__(kThreads) void k_chol_diag(double* A, int n, int jb
   __shared__ int sflag;
   const int nb = min(kNB, n - jb), ld = kNB + 1;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nbp = (nb + kPB - 1) / kPB * kPB;
   copy2d_overlapped(sa, ld, A + (long long)jb * n + jb, n, nb, nb, threadIdx.x, kThreads);
+  pad_identity(sa, ld, nb, nbp, threadIdx.x, kThreads);
   __syncthreads();
-  const int r = chol_blocked_lds<kWavesD, 1>(sa, nb, ld, &sflag);
+  const int r = chol_blocked_lds<kWavesD, 1>(sa, nbp, ld, &sflag);
   for (int i = wv; i < nb; i += kWavesD)
     for (int l = lane; l <= i; l += 64) A[(long long)(jb + i) * n + jb + l] = sa[i * ld + l];
   if (threadIdx.x == 0 && r) *info = jb + r;
@@ -398,8 +429,18 @@ __global__ __launch_bounds__(kRThreads) void k_reduced_solve(DP d, const double*
   for (int c0 = 0; c0 < n; c0 += 64) {
     const int c = c0 + lane;
     double acc = 0.0;
-    if (c < n)
-      for (int k = k0; k < k1; ++k) acc += d.rpart[(long long)k * n + c];
+    if (c < n) {
+      // loads in batches of 8 so that they are in flight together
+      int k = k0;
+      for (; k + 8 <= k1; k += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = d.rpart[(long long)(k + u) * n + c];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u];
+      }
+      for (; k < k1; ++k) acc += d.rpart[(long long)k * n + c];
+    }
     red[wv][lane] = acc;
     __syncthreads();
     if (wv == 0 && c < n) {
@@ -472,6 +513,113 @@ __global__ __launch_bounds__(kRThreads) void k_reduced_solve(DP d, const double*
   for (int c = tid; c < n; c += kRThreads) pu[c] = y[c];
 }
 
+// Reduced solve with the factor stored by k_chol_small.  Every wavefront
+// stages the factor into LDS while summing the scenario parts of the
+// right-hand side; then wavefront 0 alone runs block forward and backward
+// substitution over 16-row blocks without barriers: lane l takes row
+// l % 16 of the block and every fourth column of its off-diagonal part
+// (two shuffles combine the four), and the block's stored diagonal inverse
+// is applied with readlane broadcasts of the block's partial results.
+constexpr int kIThreads = 1024, kIWaves = kIThreads / 64;
+
+__host__ __device__ inline long long rsolve_blk_lds_bytes(int n) { return 8LL * ((long long)n * (n + 1) + 2LL * n); }
+
+__global__ __launch_bounds__(kIThreads) void k_reduced_solve_blk(DP d, const double* r1u,
+                                                                 const double* A, double* pu) {
+  extern __shared__ double sm[];
+  __shared__ double red[kIThreads];
+  const int n = d.nu, ld = n + 1, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  double* sa = sm;
+  double* y = sa + (long long)n * ld;
+  double* rd = y + n;
+  copy2d_overlapped(sa, ld, A, n, n, n, tid, kIThreads);
+  // right-hand side: sum of the scenario parts, scenario slices per wavefront
+  const int per = (d.N + kIWaves - 1) / kIWaves;
+  const int k0 = wv * per, k1 = min(d.N, k0 + per);
+  for (int c0 = 0; c0 < n; c0 += 64) {
+    const int c = c0 + lane;
+    double acc = 0.0;
+    if (c < n) {
+      int k = k0;
+      for (; k + 8 <= k1; k += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = d.rpart[(long long)(k + u) * n + c];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u];
+      }
+      for (; k < k1; ++k) acc += d.rpart[(long long)k * n + c];
+    }
+    red[wv * 64 + lane] = acc;
+    __syncthreads();
+    if (wv == 0 && c < n) {
+      double sum = -r1u[c];
+      for (int q = 0; q < kIWaves; ++q) sum += red[q * 64 + lane];
+      y[c] = sum;
+    }
+    __syncthreads();
+  }
+  for (int c = tid; c < n; c += kIThreads) rd[c] = rcp_nr(sa[c * ld + c]);
+  __syncthreads();
+  if (wv != 0) return;
+  const int r = lane & 15, g = lane >> 4;
+  // forward: L y = b, y overwriting b block by block
+  for (int jb = 0; jb < n; jb += 16) {
+    const int nb = min(16, n - jb);
+    const int row = jb + min(r, nb - 1);
+    double a0 = 0.0, a1 = 0.0;
+    int k = g;
+    for (; k + 4 < jb; k += 8) {
+      a0 = fma(sa[row * ld + k], y[k], a0);
+      a1 = fma(sa[row * ld + k + 4], y[k + 4], a1);
+    }
+    if (k < jb) a0 = fma(sa[row * ld + k], y[k], a0);
+    double acc = a0 + a1;
+    acc += __shfl_xor(acc, 16);
+    acc += __shfl_xor(acc, 32);
+    const double tr = y[row] - acc;  // lane r (and r + 16 g): t_r
+    // y_r = t_r / L_rr + sum_{p < r} (L_bb^-1)[r][p] t_p, stored at sa[jb + p][jb + r]
+    double v0 = rd[row] * tr, v1 = 0.0;
+#pragma unroll
+    for (int p = 0; p < 16; p += 2) {
+      const double t0 = readlane_d(tr, p), t1 = readlane_d(tr, p + 1);
+      if (p < r && p < nb) v0 = fma(sa[(jb + p) * ld + row], t0, v0);
+      if (p + 1 < r && p + 1 < nb) v1 = fma(sa[(jb + p + 1) * ld + row], t1, v1);
+    }
+    wave_sync();
+    if (g == 0 && r < nb) y[jb + r] = v0 + v1;
+    wave_sync();
+  }
+  // backward: L^T x = y, x overwriting y block by block
+  for (int jb = (n - 1) / 16 * 16; jb >= 0; jb -= 16) {
+    const int nb = min(16, n - jb);
+    const int col = jb + min(r, nb - 1);
+    double a0 = 0.0, a1 = 0.0;
+    int i = jb + 16 + g;
+    for (; i + 4 < n; i += 8) {
+      a0 = fma(sa[i * ld + col], y[i], a0);
+      a1 = fma(sa[(i + 4) * ld + col], y[i + 4], a1);
+    }
+    if (i < n) a0 = fma(sa[i * ld + col], y[i], a0);
+    double acc = a0 + a1;
+    acc += __shfl_xor(acc, 16);
+    acc += __shfl_xor(acc, 32);
+    const double tr = y[col] - acc;
+    // x_r = t_r / L_rr + sum_{p > r} (L_bb^-1)[p][r] t_p, stored at sa[jb + r][jb + p]
+    double v0 = rd[col] * tr, v1 = 0.0;
+#pragma unroll
+    for (int p = 0; p < 16; p += 2) {
+      const double t0 = readlane_d(tr, p), t1 = readlane_d(tr, p + 1);
+      if (p > r && p < nb) v0 = fma(sa[col * ld + jb + p], t0, v0);
+      if (p + 1 > r && p + 1 < nb) v1 = fma(sa[col * ld + jb + p + 1], t1, v1);
+    }
+    wave_sync();
+    if (g == 0 && r < nb) y[jb + r] = v0 + v1;
+    wave_sync();
+  }
+  for (int c = lane; c < n; c += 64) pu[c] = y[c];
+}
+
 }  // namespace
 
 // raise the dynamic LDS limit of a kernel to what this problem needs (never lowered)
@@ -486,12 +634,14 @@ hipError_t configure_dense_kernels(const DP& d) {
   static int c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0;
   hipError_t e = hipSuccess;
   if (d.nu <= kSmallN) {
-    const void* f = d.nu <= 64 ? (const void*)k_chol_small<1>
-                    : d.nu <= 128 ? (const void*)k_chol_small<2> : (const void*)k_chol_small<3>;
-    int* cur = d.nu <= 64 ? &c1 : d.nu <= 128 ? &c4 : &c5;
-    e = allow_lds(f, cur, 8 * d.nu * (d.nu + 1));
+    const void* f = d.nu <= 64 ? (const void*)k_chol_small<1> : (const void*)k_chol_small<2>;
+    int* cur = d.nu <= 64 ? &c1 : &c4;
+    const int np = (d.nu + kPB - 1) / kPB * kPB;
+    e = allow_lds(f, cur, 8 * np * (np + 1));
   }
-  if (e == hipSuccess) {
+  if (e == hipSuccess && d.nu <= kSmallN)
+    e = allow_lds((const void*)k_reduced_solve_blk, &c5, (int)rsolve_blk_lds_bytes(d.nu));
+  if (e == hipSuccess && d.nu > kSmallN) {
     if (rsolve_lds(d.nu))
       e = allow_lds((const void*)k_reduced_solve<true>, &c2, 8 * (d.nu * (d.nu + 1) + d.nu));
     else
@@ -526,10 +676,10 @@ void launch_stacked_product(const DP& d, hipStream_t s) {
 void launch_cholesky_from(const DP& d, const double* src, double* a, int* info, hipStream_t s) {
   const int n = d.nu;
   if (n <= kSmallN) {
-    size_t lds = 8 * (size_t)n * (n + 1);
+    const int np = (n + kPB - 1) / kPB * kPB;
+    const size_t lds = 8 * (size_t)np * (np + 1);
     if (n <= 64) k_chol_small<1><<<1, kCholSmallThreads, lds, s>>>(src, a, n, info);
-    else if (n <= 128) k_chol_small<2><<<1, kCholSmallThreads, lds, s>>>(src, a, n, info);
-    else k_chol_small<3><<<1, kCholSmallThreads, lds, s>>>(src, a, n, info);
+    else k_chol_small<2><<<1, kCholSmallThreads, lds, s>>>(src, a, n, info);
     return;
   }
   if (src != a) launch_copy(src, a, (long long)n * n, s);
@@ -552,7 +702,9 @@ void launch_cholesky(const DP& d, double* a, int* info, hipStream_t s) {
 
 void launch_reduced_solve(const DP& d, const double* r1u, const double* chol, double* pu,
                           hipStream_t s) {
-  if (rsolve_lds(d.nu))
+  if (d.nu <= kSmallN)
+    k_reduced_solve_blk<<<1, kIThreads, (size_t)rsolve_blk_lds_bytes(d.nu), s>>>(d, r1u, chol, pu);
+  else if (rsolve_lds(d.nu))
     k_reduced_solve<true><<<1, kRThreads, 8 * ((size_t)d.nu * (d.nu + 1) + d.nu), s>>>(d, r1u, chol, pu);
   else
     k_reduced_solve<false><<<1, kRThreads, 8 * (size_t)d.nu, s>>>(d, r1u, chol, pu);

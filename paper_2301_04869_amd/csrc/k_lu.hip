@@ -32,12 +32,6 @@ namespace {
 constexpr int kRT = kRedThreads;  // reduction workgroup and global-mode scenario group
 constexpr int kGT = 256;          // LDS-mode refactor / step workgroup (up to 4 scenarios)
 
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
 __device__ inline void raise_status(const DP& d, int code, int k) {
   if (atomicCAS(d.status, 0, code) == 0) d.status[1] = k;
 }

@@ -17,6 +17,7 @@ region) and the CPU oracle timed on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -128,9 +129,10 @@ def stage_work(d):
     w["refactor"] = (N * 2 * d["lu_update_flops"], 8 * N * (ngx + nlu + nx) + 4 * 3 * nlu)
     nz = nx + nu
     if d["variant"] == 2:
-        # forward solves and K products; Z and K Z written once
+        # forward solves and K products; the T rows of Z (its identity rows
+        # are written once at set-up) and K Z written once
         w["reduce"] = (N * nu * (2 * nlu + 2 * nkx),
-                       8 * N * (nlu + nx + nk + ngu + 2 * nz * nu) + 4 * (3 * nlu + 2 * nk))
+                       8 * N * (nlu + nx + nk + ngu + (nx + nz) * nu) + 4 * (3 * nlu + 2 * nk))
         # lower triangle of Z^T (K Z): Z and K Z read once, partials written
         w["stacked_product"] = (N * nz * nu * (nu + 1), 8 * 2 * N * nz * nu + 8 * nu * nu)
     else:
@@ -144,19 +146,39 @@ def stage_work(d):
     return w
 
 
-def roofline_entry(stage, ms, count, d):
+def measured_traffic(stage, workload):
+    """HBM bytes per launch of `stage` from the committed counter record
+    (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy), or None when there is
+    none for this stage and workload or the kernel's source changed since."""
+    root = os.path.dirname(os.path.abspath(__file__))
+    for name in sorted(os.listdir(os.path.join(root, "profiles"))):
+        if not (name.startswith("hbm_traffic_") and name.endswith(".json")):
+            continue
+        with open(os.path.join(root, "profiles", name)) as fh:
+            rec = json.load(fh)
+        if rec.get("stage") != stage or rec.get("workload") != workload:
+            continue
+        with open(os.path.join(root, rec["source"]), "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest() != rec["source_sha256"]:
+                return None
+        return rec["bytes_per_launch"]
+    return None
+
+
+def roofline_entry(stage, ms, count, d, workload):
     flops, nbytes = stage_work(d)[stage]
+    traffic = measured_traffic(stage, workload)
     t = ms / count * 1e-3
     t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
     t_alu = flops / (FP64_PEAK_TFS * 1e12)
     if t_hbm >= t_alu:
         ach = nbytes / t / 1e9
         return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel_stage": stage,
+                "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "kernel_stage": stage,
                 "avg_ms": ms / count, "algorithmic_bytes": nbytes, "algorithmic_flops": flops}
     ach = flops / t / 1e12
     return {"bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
-            "frac": ach / FP64_PEAK_TFS, "traffic": None, "kernel_stage": stage,
+            "frac": ach / FP64_PEAK_TFS, "traffic": traffic, "kernel_stage": stage,
             "avg_ms": ms / count, "algorithmic_bytes": nbytes, "algorithmic_flops": flops}
 
 
@@ -318,7 +340,7 @@ def main():
     cf_ms = sum(stages[s][0] for s in ("condense_values", "refactor", "reduce", "stacked_product",
                                        "scenario_sum", "factor")) / args.steps
     dom = max((s for s in stages if stages[s][1] > 0), key=lambda s: stages[s][0])
-    roof = roofline_entry(dom, stages[dom][0], stages[dom][1], d)
+    roof = roofline_entry(dom, stages[dom][0], stages[dom][1], d, args.config)
 
     out = {
         "metric": "scenario-IPM-iterations/sec (condense+factor) vs plain form; IPM iters w/ warm start",

@@ -151,6 +151,8 @@ def measured_traffic(stage, workload):
     (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy), or None when there is
     none for this stage and workload or the kernel's source changed since."""
     root = os.path.dirname(os.path.abspath(__file__))
+    if not os.path.isdir(os.path.join(root, "profiles")):
+        return None
     for name in sorted(os.listdir(os.path.join(root, "profiles"))):
         if not (name.startswith("hbm_traffic_") and name.endswith(".json")):
             continue

@@ -22,7 +22,7 @@ __global__ void k_set_int(int* p, int v) { *p = v; }
 // order); its 8 wavefronts each sum a contiguous eighth of the matrices in
 // index order and the eight partial sums are added in wavefront order, so the
 // result does not depend on scheduling.
-constexpr int kSumEntries = 64, kSumWaves = 8;
+constexpr int kSumEntries = 64, kSumWaves = 16;
 
 __global__ __launch_bounds__(kSumEntries * kSumWaves) void k_sym_sum(DP d, const double* src, int cnt,
                                                                       const double* su, double dw,
@@ -44,8 +44,19 @@ __global__ __launch_bounds__(kSumEntries * kSumWaves) void k_sym_sum(DP d, const
   const int per = (cnt + kSumWaves - 1) / kSumWaves;
   const int k0 = wv * per, k1 = min(cnt, k0 + per);
   double acc = 0.0;
-  if (t < ntri)
-    for (int k = k0; k < k1; ++k) acc += src[(long long)k * nn + off];
+  if (t < ntri) {
+    // loads in batches of 16 so that they are in flight together; the
+    // additions keep the chunk order
+    int k = k0;
+    for (; k + 16 <= k1; k += 16) {
+      double v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v[u] = src[(long long)(k + u) * nn + off];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc += v[u];
+    }
+    for (; k < k1; ++k) acc += src[(long long)k * nn + off];
+  }
   part[wv][lane] = acc;
   __syncthreads();
   if (wv == 0 && t < ntri) {
@@ -63,61 +74,148 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // Stacked product of the reduction's product variant: for chunk c of the
 // stacked rows rho (all scenarios, x rows then u rows of each),
 //   gpart_c[i][j] = sum_rho Z[rho][i] (K Z)[rho][j],   i >= j,
-// so that sum_c gpart_c = sum_k Z_k^T K_k Z_k.  One workgroup per (32 x 32
-// lower output tile, chunk); its 4 wavefronts take interleaved 4-row slices
-// of the chunk and each accumulates the whole tile as 2 x 2 blocks of
-// v_mfma_f64_16x16x4f64 (A operand: lane holds Z[rho + lane/16][i + lane%16];
-// B operand: (K Z)[rho + lane/16][j + lane%16]; result register r of a lane:
-// row lane/16 + 4 r, column lane%16); the four tiles are added in wavefront
-// order.
-__global__ __launch_bounds__(256) void k_stacked_product(DP d) {
-  int t = blockIdx.x, ti = 0;
-  while (t > ti) { t -= ti + 1; ++ti; }
-  const int tj = t, chunk = blockIdx.y;
+// so that sum_c gpart_c = sum_k Z_k^T K_k Z_k.  The output's lower triangle
+// is cut into 16 x 16 blocks, grouped into super-tiles of kSB x kSB blocks
+// (triangular on the diagonal).  One workgroup per (super-tile, chunk): it
+// streams the chunk's rows in slabs of 32 through LDS (the super-tile's 16 kSB
+// columns of Z and of K Z, double-buffered, each value read from HBM once per
+// super-tile) and its 4 wavefronts take the super-tile's blocks round robin,
+// each block one v_mfma_f64_16x16x4f64 accumulator (A operand: lane holds
+// Z[rho + lane/16][i + lane%16]; B operand: (K Z)[rho + lane/16][j + lane%16];
+// result register r of a lane: row lane/16 + 4 r, column lane%16).
+constexpr int kSB = 7;                        // blocks per super-tile side
+constexpr int kSBMax = (kSB * kSB + 3) / 4;   // blocks per wavefront, at most
+constexpr int kSlab = 32, kSW = 16 * kSB + 1; // slab rows, LDS row pitch
+
+__host__ __device__ inline int sp_nblk(int nu) { return (nu + 15) / 16; }
+__host__ __device__ inline int sp_nsuper(int nu) { return (sp_nblk(nu) + kSB - 1) / kSB; }
+__host__ inline long long sp_rows_per_chunk(long long rows, int nchunk) {
+  return ((rows + nchunk - 1) / nchunk + kSlab - 1) / kSlab * kSlab;
+}
+
+// kSlots: blocks per wavefront for this shape; every slot's product runs
+// (a slot past the wavefront's blocks reads block (0, 0) and is not stored),
+// so the accumulators stay in fixed registers with no branches around them
+template <int kSlots>
+__global__ __launch_bounds__(256) void k_stacked_product(DP d, long long per) {
+  __shared__ double zs[2][kSlab * kSW], ks[2][kSlab * kSW];
+  int t = blockIdx.x, SI = 0;
+  while (t > SI) { t -= SI + 1; ++SI; }
+  const int SJ = t, chunk = blockIdx.y;
+  const int nblk = sp_nblk(d.nu);
+  const int bi0 = SI * kSB, bj0 = SJ * kSB;
+  const int ni = min(kSB, nblk - bi0), nj = min(kSB, nblk - bj0);
+  const int ci = 16 * ni, cj = 16 * nj;        // columns staged of Z, of K Z
   const long long rows = (long long)d.N * d.nz;
-  const long long per = ((rows + d.nchunk - 1) / d.nchunk + 15) / 16 * 16;
   const long long r0 = (long long)chunk * per, r1 = min(rows, r0 + per);
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lm = lane & 15, lk = lane >> 4;
-  const int i0 = ti * 32, j0 = tj * 32;
   const long long ld = d.nu_pad;
-  const double* Z = d.Zst;
-  const double* KZ = d.KZst;
-  v4d acc[2][2];
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
-  // kU 4-row slices per wavefront in flight: all their operand loads are
-  // issued before the first of their matrix-core products
-  constexpr int kU = 4;
-  for (long long r = r0 + 4 * wv; r < r1; r += 16 * kU) {
-    double a0[kU], a1[kU], b0[kU], b1[kU];
+  const double* Z = d.Zst + 16LL * bi0;
+  const double* KZ = d.KZst + 16LL * bj0;
+  // this wavefront's blocks: numbers wv, wv + 4, ... of the super-tile's
+  // blocks (a, b) in row order (lower triangle on the diagonal), a over Z,
+  // b over K Z
+  const int nblocks = SI == SJ ? ni * (ni + 1) / 2 : ni * nj;
+  int ba[kSlots], bb[kSlots];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const long long rr = r + 16 * u + lk;
-      const bool ok = rr < r1;
-      a0[u] = ok ? Z[rr * ld + i0 + lm] : 0.0;
-      a1[u] = ok ? Z[rr * ld + i0 + 16 + lm] : 0.0;
-      b0[u] = ok ? KZ[rr * ld + j0 + lm] : 0.0;
-      b1[u] = ok ? KZ[rr * ld + j0 + 16 + lm] : 0.0;
+  for (int q = 0; q < kSlots; ++q) {
+    int idx = wv + 4 * q, a = 0;
+    if (idx >= nblocks) {
+      idx = 0;
+    } else if (SI == SJ) {
+      while (idx > a) { idx -= a + 1; ++a; }
+    } else {
+      a = idx / nj;
+      idx -= a * nj;
     }
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u], b0[u], acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[u], b1[u], acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], b0[u], acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[u], b1[u], acc[1][1], 0, 0, 0);
-    }
+    ba[q] = a;
+    bb[q] = idx;
   }
-  __shared__ double red[4][32][33];
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b)
-      for (int r = 0; r < 4; ++r) red[wv][16 * a + lk + 4 * r][16 * b + lm] = acc[a][b][r];
+  const int nmine = nblocks > wv ? (nblocks - wv + 3) / 4 : 0;
+  v4d acc[kSlots];
+#pragma unroll
+  for (int q = 0; q < kSlots; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+  // slab staging: each thread moves kPer values; element u of a thread has
+  // a fixed row, source (Z or K Z, at a fixed offset from the slab's first
+  // row) and LDS place, so only the row bound changes from slab to slab.
+  // Branch-free: an element outside the chunk or the super-tile is loaded
+  // from row 0 of the super-tile's columns of Z (a chunk may start past the
+  // last row) and stored as 0, and the zero is applied when the value goes
+  // to LDS, after the products, so that no wait on the loads precedes them.
+  constexpr int kPer = (kSlab * 2 * 16 * kSB + 255) / 256;
+  int goff[kPer], soff[kPer];
+  unsigned colok = 0, isk = 0;
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int e = tid + 256 * u;
+    const int row = e / (2 * 16 * kSB), col = e % (2 * 16 * kSB);
+    const bool isz = col < 16 * kSB;
+    const int cc = isz ? col : col - 16 * kSB;
+    goff[u] = row * (int)ld + cc;
+    soff[u] = row * kSW + cc;
+    colok |= (cc < (isz ? ci : cj) ? 1u : 0u) << u;
+    isk |= (isz ? 0u : 1u) << u;
+  }
+  auto load = [&](long long rs, double* v) -> unsigned {
+    unsigned ok = 0;
+    const double* zb = Z + rs * ld;
+    const double* kzb = KZ + rs * ld;
+    const long long left = r1 - rs;  // rows of this slab inside the chunk
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int row = (tid + 256 * u) / (2 * 16 * kSB);
+      const bool in = ((colok >> u) & 1u) && row < left;
+      ok |= (in ? 1u : 0u) << u;
+      v[u] = *(in ? ((isk >> u) & 1u ? kzb : zb) + goff[u] : Z);
+    }
+    return ok;
+  };
+  auto store = [&](int buf, const double* v, unsigned ok) {
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const double x = (ok >> u) & 1u ? v[u] : 0.0;
+      if ((isk >> u) & 1u) ks[buf][soff[u]] = x;
+      else zs[buf][soff[u]] = x;
+    }
+  };
+  static_assert(kPer * 256 == kSlab * 2 * 16 * kSB, "slab staging covers the slab exactly");
+  double v[kPer];
+  unsigned ok = load(r0, v);
+  store(0, v, ok);
   __syncthreads();
-  for (int e = threadIdx.x; e < 32 * 32; e += 256) {
-    const int i = e >> 5, j = e & 31;
-    const double s = ((red[0][i][j] + red[1][i][j]) + red[2][i][j]) + red[3][i][j];
-    const int gi = i0 + i, gj = j0 + j;
-    if (gi < d.nu && gj <= gi) d.gpart[((long long)chunk * d.nu + gi) * d.nu + gj] = s;
+  int buf = 0;
+  for (long long rs = r0; rs < r1; rs += kSlab) {
+    const bool more = rs + kSlab < r1;
+    if (more) ok = load(rs + kSlab, v);
+    const double* za = zs[buf];
+    const double* kb = ks[buf];
+#pragma unroll
+    for (int k0 = 0; k0 < kSlab; k0 += 4) {
+      double av[kSlots], bv[kSlots];
+#pragma unroll
+      for (int q = 0; q < kSlots; ++q) {
+        av[q] = za[(k0 + lk) * kSW + 16 * ba[q] + lm];
+        bv[q] = kb[(k0 + lk) * kSW + 16 * bb[q] + lm];
+      }
+#pragma unroll
+      for (int q = 0; q < kSlots; ++q)
+        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[q], acc[q], 0, 0, 0);
+    }
+    if (more) store(buf ^ 1, v, ok);
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int q = 0; q < kSlots; ++q) {
+    if (q < nmine) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gi = 16 * (bi0 + ba[q]) + lk + 4 * r, gj = 16 * (bj0 + bb[q]) + lm;
+        if (gi < d.nu && gj <= gi) d.gpart[((long long)chunk * d.nu + gi) * d.nu + gj] = acc[q][r];
+      }
+    }
   }
 }
 
@@ -669,8 +767,17 @@ void launch_scenario_sum(const DP& d, const double* su, double dw, double* khat,
 }
 
 void launch_stacked_product(const DP& d, hipStream_t s) {
-  const int T = d.nu_pad / 32;
-  k_stacked_product<<<dim3(T * (T + 1) / 2, d.nchunk), 256, 0, s>>>(d);
+  const int T = sp_nsuper(d.nu), nblk = sp_nblk(d.nu);
+  const long long per = sp_rows_per_chunk((long long)d.N * d.nz, d.nchunk);
+  // blocks per wavefront: the largest super-tile's count over 4 wavefronts
+  const int most = nblk > kSB ? kSB * kSB : nblk * (nblk + 1) / 2;
+  const int slots = (most + 3) / 4;
+  const dim3 grid(T * (T + 1) / 2, d.nchunk);
+  if (slots <= 1) k_stacked_product<1><<<grid, 256, 0, s>>>(d, per);
+  else if (slots <= 2) k_stacked_product<2><<<grid, 256, 0, s>>>(d, per);
+  else if (slots <= 4) k_stacked_product<4><<<grid, 256, 0, s>>>(d, per);
+  else if (slots <= 7) k_stacked_product<7><<<grid, 256, 0, s>>>(d, per);
+  else k_stacked_product<kSBMax><<<grid, 256, 0, s>>>(d, per);
 }
 
 void launch_cholesky_from(const DP& d, const double* src, double* a, int* info, hipStream_t s) {

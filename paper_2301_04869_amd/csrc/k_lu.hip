@@ -243,6 +243,49 @@ __device__ __forceinline__ void chain_solveW(const DP& d, const double* cv, doub
     if (a < t) X[(long long)(c0 + a) * ld + c] = x[a];
 }
 
+// Many columns, all wavefronts: wavefront w takes columns 4 w .. 4 w + 3 of
+// X, lanes 0..31 holding the chain rows of columns 4 w and 4 w + 2, lanes
+// 32..63 those of 4 w + 1 and 4 w + 3; x_b is broadcast with readlane.  The up solve
+// and then the down solve, each row subtracting its terms in the same order
+// as chain_solveW (so the results are the same).  64 columns = 16
+// wavefronts.
+template <bool kTrans>
+__device__ __forceinline__ void chain_solveR(const DP& d, const double* cv, double* X, int ld, int wv) {
+  const int t = d.chain_t, c0 = d.chain_c0;
+  const int lane = threadIdx.x & 63, a = lane & 31, half = lane >> 5;
+  const bool own = a < t;
+  // both column pairs of the wavefront at once (independent chains)
+  const int col0 = 4 * wv + half, col1 = col0 + 2;
+  double x = own ? X[(long long)(c0 + a) * ld + col0] : 0.0;
+  double y = own ? X[(long long)(c0 + a) * ld + col1] : 0.0;
+#pragma unroll
+  for (int b = 0; b < kChainMax; ++b)
+    if (b < t) {
+      const double cf = own ? (kTrans ? cv[b * t + a] : cv[a * t + b]) : 0.0;
+      const double x0 = readlane_d(x, b), x1 = readlane_d(x, 32 + b);
+      const double y0 = readlane_d(y, b), y1 = readlane_d(y, 32 + b);
+      if (a > b) {
+        x = fma(-cf, half ? x1 : x0, x);
+        y = fma(-cf, half ? y1 : y0, y);
+      }
+    }
+#pragma unroll
+  for (int b = kChainMax - 1; b >= 0; --b)
+    if (b < t) {
+      const double cf = own ? (kTrans ? cv[b * t + a] : cv[a * t + b]) : 0.0;
+      const double x0 = readlane_d(x, b), x1 = readlane_d(x, 32 + b);
+      const double y0 = readlane_d(y, b), y1 = readlane_d(y, 32 + b);
+      if (a < b) {
+        x = fma(-cf, half ? x1 : x0, x);
+        y = fma(-cf, half ? y1 : y0, y);
+      }
+    }
+  if (own) {
+    X[(long long)(c0 + a) * ld + col0] = x;
+    X[(long long)(c0 + a) * ld + col1] = y;
+  }
+}
+
 // chain block values of one scenario into cv (all threads of the workgroup)
 __device__ __forceinline__ void chain_gather(const DP& d, const double* lu, double* cv) {
   const int tt = d.chain_t * d.chain_t;
@@ -628,7 +671,8 @@ __global__ __launch_bounds__(kRT) void k_reduce64(DP d) {
   const bool colok = col < nu;
   extern __shared__ double smem[];
   const double* ev = d.EV + (long long)k * d.n_ev;
-  const double *lu, *invd, *kv, *guv = nullptr;
+  const double *lu, *invd, *guv = nullptr;
+  const double* kv;
   double *T, *Lx = nullptr;
   int ldT = kW64;
   double* zk = kVar == 2 ? d.Zst + (long long)k * nz * d.nu_pad : nullptr;
@@ -636,6 +680,7 @@ __global__ __launch_bounds__(kRT) void k_reduce64(DP d) {
   const int* k_ptr = d.k_ptr;
   const int* k_usplit = d.k_usplit;
   const int* k_col = d.k_col;
+  kv = d.K + (long long)k * d.nnz_k;
   double* cv = smem;  // chain block values (global mode: the only LDS use)
   if (kLDS) {
     double* p = smem;
@@ -656,13 +701,13 @@ __global__ __launch_bounds__(kRT) void k_reduce64(DP d) {
     k_ptr = skp;
     k_usplit = sku;
     k_col = skc;
+    kv = skv;
     cv = smem + (reduce_lds_bytes(sizes_of(d)) / 8 - (long long)d.chain_t * d.chain_t);
     for (int j = tid; j < d.nnz_gu; j += kRT) sgu[j] = ev[d.off_gu + d.guc_pos[j]];
-    lu = slu; invd = slu + d.nnz_f; kv = skv; guv = sgu;
+    lu = slu; invd = slu + d.nnz_f; guv = sgu;
   } else {
     lu = lu_of(d, k);
     invd = lu + d.nnz_f;
-    kv = d.K + (long long)k * d.nnz_k;
     if (kVar == 2) {
       T = zk + c0;  // solved in place in the stacked panel
       ldT = d.nu_pad;
@@ -688,9 +733,7 @@ __global__ __launch_bounds__(kRT) void k_reduce64(DP d) {
   // padding columns inside the panel, which nothing reads
   sweep64<false>(d.ru_ptr, uent, d.nph_u, wv, lu, T, ldT, c, bsync);
   if (d.chain_t > 0) {
-    if (wv == 0) chain_solveW<true, false>(d, cv, T, ldT, c);
-    __syncthreads();
-    if (wv == 0) chain_solveW<false, false>(d, cv, T, ldT, c);
+    chain_solveR<false>(d, cv, T, ldT, wv);
     __syncthreads();
   }
   sweep64<false>(d.rd_ptr, dent, d.nph_d, wv, lu, T, ldT, c, bsync);
@@ -756,9 +799,7 @@ __global__ __launch_bounds__(kRT) void k_reduce64(DP d) {
   __syncthreads();
   sweep64<true>(d.ru_ptr, uent, d.nph_u, wv, lu, Lx, kW64, c, bsync);
   if (d.chain_t > 0) {
-    if (wv == 0) chain_solveW<true, true>(d, cv, Lx, kW64, c);
-    __syncthreads();
-    if (wv == 0) chain_solveW<false, true>(d, cv, Lx, kW64, c);
+    chain_solveR<true>(d, cv, Lx, kW64, wv);
     __syncthreads();
   }
   sweep64<true>(d.rd_ptr, dent, d.nph_d, wv, lu, Lx, kW64, c, bsync);

@@ -736,11 +736,16 @@ std::string build_symbolic(const rkkt_network& net, int N, int col_tile_req, int
   // scenario, columns padded to a multiple of 64 (the reduction's widest tile)
   s.nu_pad = (nu + 63) / 64 * 64;
   {
+    // row chunks of the stacked product: about 256 workgroups over the
+    // super-tiles of 7 x 7 16-column blocks, at least 64 rows per chunk
     const long long rows = (long long)N * s.nz;
-    const int T = s.nu_pad / 32;
-    const long long tiles = (long long)T * (T + 1) / 2;
-    long long nc = std::max(1LL, 512 / tiles);
-    nc = std::min(nc, std::max(1LL, rows / 256));
+    const long long T = ((nu + 15) / 16 + 6) / 7;
+    const long long tiles = T * (T + 1) / 2;
+    long long nc = std::max(1LL, 256 / tiles);
+    nc = std::min(nc, std::max(1LL, rows / 64));
+    // chunks of whole 32-row slabs; no chunk starts past the last row
+    const long long per = ((rows + nc - 1) / nc + 31) / 32 * 32;
+    nc = (rows + per - 1) / per;
     s.nchunk = (int)nc;
   }
   // schedules

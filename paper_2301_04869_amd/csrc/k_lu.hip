@@ -740,9 +740,57 @@ __global__ __launch_bounds__(kRT) void k_reduce64(DP d) {
   if (colok)
     for (int i = wv; i < nx; i += kS64) T[(long long)i * ldT + c] *= invd[i];
   __syncthreads();
-  // step 2: rows of K, four rows per wavefront at a time (independent chains)
+  // step 2: rows of K, four rows per wavefront at a time (independent
+  // chains).  A row's entries are read lane-parallel (lane u holds entry u,
+  // one vector read per array) and broadcast with readlane, so the LDS pipe
+  // carries only the panel reads; rows longer than 64 entries take the
+  // entry-by-entry path.
   constexpr int kRowsK = 4;
   auto k_rows = [&](int r0, double out4[kRowsK]) {
+    int e[kRowsK], eu[kRowsK], e1[kRowsK];
+    int len = 0, longest = 0;
+#pragma unroll
+    for (int j = 0; j < kRowsK; ++j) {
+      const int r = r0 + j * kS64;
+      e[j] = r < nz ? k_ptr[r] : 0;
+      eu[j] = r < nz ? k_usplit[r] : 0;
+      e1[j] = r < nz ? k_ptr[r + 1] : 0;
+      len = max(len, eu[j] - e[j]);
+      longest = max(longest, e1[j] - e[j]);
+    }
+    if (longest > 64) return false;
+    const int lane = threadIdx.x & 63;
+    int colv[kRowsK];
+    double valv[kRowsK], acc[kRowsK];
+#pragma unroll
+    for (int j = 0; j < kRowsK; ++j) {
+      const bool in = lane < e1[j] - e[j];
+      colv[j] = in ? k_col[e[j] + lane] : -1;
+      valv[j] = in ? kv[e[j] + lane] : 0.0;
+      acc[j] = 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < kRowsK; ++j)
+      for (int m = eu[j] - e[j]; m < e1[j] - e[j]; ++m) {
+        const int cm = __builtin_amdgcn_readlane(colv[j], m);
+        const double vm = readlane_d(valv[j], m);
+        if (cm == nx + col) acc[j] = vm;
+      }
+    for (int m = 0; m < len; ++m) {
+#pragma unroll
+      for (int j = 0; j < kRowsK; ++j) {
+        if (m < eu[j] - e[j]) {
+          const int cm = __builtin_amdgcn_readlane(colv[j], m);
+          const double vm = readlane_d(valv[j], m);
+          acc[j] = fma(vm, T[(long long)cm * ldT + c], acc[j]);
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kRowsK; ++j) out4[j] = acc[j];
+    return true;
+  };
+  auto k_rows_slow = [&](int r0, double out4[kRowsK]) {
     int e[kRowsK], eu[kRowsK], e1[kRowsK];
     int len = 0;
 #pragma unroll
@@ -770,32 +818,33 @@ __global__ __launch_bounds__(kRT) void k_reduce64(DP d) {
 #pragma unroll
     for (int j = 0; j < kRowsK; ++j) out4[j] = acc[j];
   };
+  // k_rows reads a row's entries across all 64 lanes, so every lane runs it
+  // (padding columns of the panel are zero and match no u column) and only
+  // the stores are limited to columns < n_u
   if (kVar == 2) {
-    if (!colok) return;
-    if (kLDS)
+    if (kLDS && colok)
       for (int i = wv; i < nx; i += kS64) zk[(long long)i * d.nu_pad + col] = T[i * kW64 + c];
     for (int r0 = wv; r0 < nz; r0 += kRowsK * kS64) {
       double v[kRowsK];
-      k_rows(r0, v);
+      if (!k_rows(r0, v)) k_rows_slow(r0, v);
 #pragma unroll
       for (int j = 0; j < kRowsK; ++j)
-        if (r0 + j * kS64 < nz) kzk[(long long)(r0 + j * kS64) * d.nu_pad + col] = v[j];
+        if (colok && r0 + j * kS64 < nz) kzk[(long long)(r0 + j * kS64) * d.nu_pad + col] = v[j];
     }
     return;
   }
   // adjoint: L_x (prescaled by 1/u_ii for the U^T sweep), L_u into part
   double* out = d.part + (long long)k * nu * nu;
-  if (colok)
-    for (int r0 = wv; r0 < nz; r0 += kRowsK * kS64) {
-      double v[kRowsK];
-      k_rows(r0, v);
+  for (int r0 = wv; r0 < nz; r0 += kRowsK * kS64) {
+    double v[kRowsK];
+    if (!k_rows(r0, v)) k_rows_slow(r0, v);
 #pragma unroll
-      for (int j = 0; j < kRowsK; ++j) {
-        const int r = r0 + j * kS64;
-        if (r < nx) Lx[(long long)r * kW64 + c] = v[j] * invd[r];
-        else if (r < nz) out[(long long)(r - nx) * nu + col] = v[j];
-      }
+    for (int j = 0; j < kRowsK; ++j) {
+      const int r = r0 + j * kS64;
+      if (r < nx) Lx[(long long)r * kW64 + c] = colok ? v[j] * invd[r] : 0.0;
+      else if (r < nz && colok) out[(long long)(r - nx) * nu + col] = v[j];
     }
+  }
   __syncthreads();
   sweep64<true>(d.ru_ptr, uent, d.nph_u, wv, lu, Lx, kW64, c, bsync);
   if (d.chain_t > 0) {

@@ -127,3 +127,29 @@ def test_refactor_schedule_reproduces_dense_lu(case):
     mask[rows, fc] = True
     assert np.abs(np.tril(Lf, -1)[~mask]).max(initial=0.0) == 0.0
     assert np.abs(np.triu(U, 1)[~mask]).max(initial=0.0) < 1e-300
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("which", ["reduce_up", "reduce_down", "step_up", "step_down"])
+def test_sweep_phases_group_destinations(case, which):
+    """What the batched sweeps read ahead relies on: within a phase no row is
+    both a destination and a source, every destination belongs to one slot,
+    and a slot's entries for one destination are contiguous."""
+    name, n = case
+    inst = sg.preset(name)
+    n = n or inst.scen.n_scen
+    sc = R.rkkt_analyze_schedule(inst.net, n, which)
+    P, S, ptr, ent = sc["nphase"], sc["slots"], sc["ptr"], sc["ent"]
+    for q in range(P):
+        dsts, srcs, owner = set(), set(), {}
+        for sl in range(S):
+            runs = []
+            for e in range(ptr[q * S + sl], ptr[q * S + sl + 1]):
+                d, s = int(ent[e][0]), int(ent[e][1])
+                dsts.add(d)
+                srcs.add(s)
+                assert owner.setdefault(d, sl) == sl, (q, d)
+                if not runs or runs[-1] != d:
+                    assert d not in runs, (q, sl, d)
+                    runs.append(d)
+        assert not (dsts & srcs), q

@@ -628,36 +628,16 @@ __device__ __forceinline__ void sweep64(const int* __restrict__ ptr, const int4*
     int cur = -1;
     double acc = 0.0;
     const int m = min(n, 64);
-    // four entries at a time: their source values and their destinations'
-    // current values are read together, then applied in order (a slot's
-    // entries come grouped by destination, and a destination of this phase
-    // is no source of it, so the early reads see final values)
-    for (int u0 = 0; u0 < m; u0 += 4) {
-      int dd[4], ss[4];
-      double vv[4], xs[4], xd[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int u = min(u0 + k, 63);
-        const bool ok = u0 + k < m;
-        dd[k] = ok ? __builtin_amdgcn_readlane(ev0.x, u) : -1;
-        ss[k] = ok ? __builtin_amdgcn_readlane(ev0.y, u) : 0;
-        vv[k] = ok ? readlane_d(lv0, u) : 0.0;
+    for (int u = 0; u < m; ++u) {
+      const int dst = __builtin_amdgcn_readlane(ev0.x, u), src = __builtin_amdgcn_readlane(ev0.y, u);
+      const double v = readlane_d(lv0, u);
+      const double x = X[src * ld + c];
+      if (dst != cur) {
+        if (cur >= 0) X[cur * ld + c] = acc;
+        cur = dst;
+        acc = X[cur * ld + c];
       }
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        xs[k] = X[ss[k] * ld + c];
-        xd[k] = dd[k] >= 0 ? X[dd[k] * ld + c] : 0.0;
-      }
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        if (dd[k] < 0) continue;
-        if (dd[k] != cur) {
-          if (cur >= 0) X[cur * ld + c] = acc;
-          cur = dd[k];
-          acc = xd[k];
-        }
-        acc = fma(-vv[k], xs[k], acc);
-      }
+      acc = fma(-v, x, acc);
     }
     // entries past the 64 held in lanes, one at a time
     for (int e = b0 + 64; e < b0 + n; ++e) {

@@ -132,9 +132,10 @@ def test_refactor_schedule_reproduces_dense_lu(case):
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 @pytest.mark.parametrize("which", ["reduce_up", "reduce_down", "step_up", "step_down"])
 def test_sweep_phases_group_destinations(case, which):
-    """What the batched sweeps read ahead relies on: within a phase no row is
-    both a destination and a source, every destination belongs to one slot,
-    and a slot's entries for one destination are contiguous."""
+    """What the sweeps that read a phase's values ahead rely on: within a
+    phase no row is both a destination and a source, every destination
+    belongs to one slot, and a slot's entries for one destination are
+    contiguous."""
     name, n = case
     inst = sg.preset(name)
     n = n or inst.scen.n_scen

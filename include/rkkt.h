@@ -168,6 +168,19 @@ int rkkt_analyze_schedule(const rkkt_network* net, int n_scen, const rkkt_option
 /* Replace the scenario loads with device arrays [N][n_load]. */
 int rkkt_set_loads(rkkt_problem* p, const double* pd_dev, const double* qd_dev, hipStream_t stream);
 
+/*
+ * Line status per scenario (contingencies; the paper's scenarios may carry
+ * them next to the loads, case-study section): status_dev [N][n_line] device
+ * array, copied into the handle; 1 = in service, 0 = tripped (any factor
+ * scales the line's series and charging admittance).  A tripped line keeps
+ * its place in the shared patterns with zero admittance, so its flows and
+ * every derivative of them are zero and the reduction is the one of the grid
+ * without the line.  The caller keeps the grid connected (a tripped bridge
+ * makes G_x singular: RKKT_ERR_SINGULAR_GX from the next condense).  All ones
+ * after rkkt_create.  Stream-ordered; allocates nothing.
+ */
+int rkkt_set_line_status(rkkt_problem* p, const double* status_dev, hipStream_t stream);
+
 int rkkt_dims_get(const rkkt_problem* p, rkkt_dims* out);
 
 /*

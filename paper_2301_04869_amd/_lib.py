@@ -26,7 +26,7 @@ EXPORTS = ("rkkt_create", "rkkt_analyze", "rkkt_set_loads", "rkkt_dims_get", "rk
            "rkkt_last_error", "rkkt_profile_begin", "rkkt_profile_end", "rkkt_solve",
            "rkkt_iterate", "rkkt_graph_capture", "rkkt_graph_launch", "rkkt_batch_create",
            "rkkt_batch_launch", "rkkt_batch_destroy", "rkkt_autotune", "rkkt_analyze_lu",
-           "rkkt_analyze_schedule")
+           "rkkt_analyze_schedule", "rkkt_set_line_status")
 IPM_STATUS = {0: "converged", 1: "max_iter", 2: "line_search_failed",
               3: "inertia_correction_failed", 4: "device_error"}
 STAGES = ("evaluate", "condense_values", "refactor", "reduce", "scenario_sum", "factor",
@@ -112,6 +112,7 @@ def lib():
     L.rkkt_analyze.argtypes = [ctypes.POINTER(Network), ctypes.c_int, ctypes.POINTER(Options),
                                ctypes.POINTER(Dims)]
     L.rkkt_set_loads.argtypes = [vp, vp, vp, vp]
+    L.rkkt_set_line_status.argtypes = [vp, vp, vp]
     L.rkkt_dims_get.argtypes = [vp, ctypes.POINTER(Dims)]
     L.rkkt_evaluate.argtypes = [vp, vp, vp, vp, vp, ctypes.c_double, vp, vp, vp, vp, vp, vp]
     L.rkkt_condense.argtypes = [vp, vp, vp, vp, ctypes.c_double, vp, vp]
@@ -293,6 +294,14 @@ def rkkt_dims_get(p):
 def rkkt_set_loads(p, pd, qd, stream=None):
     """pd, qd: device [N][n_load] tensors."""
     _check(lib().rkkt_set_loads(p.ptr, _ptr(pd, "pd"), _ptr(qd, "qd"), _stream(stream)), p.ptr)
+
+
+def rkkt_set_line_status(p, status, stream=None):
+    """status: device [N][n_line] float64 tensor, 1 in service, 0 tripped."""
+    d = p.dims
+    if tuple(status.shape) != (d["n_scen"], d["n_line"]):
+        raise ValueError("status must be [N][n_line]")
+    _check(lib().rkkt_set_line_status(p.ptr, _ptr(status, "status"), _stream(stream)), p.ptr)
 
 
 def rkkt_evaluate(p, x, u, y, z, obj_weight, f, grad_x, grad_u, g, h, stream=None):

@@ -311,6 +311,7 @@ int rkkt_create(const rkkt_network* net, int n_scen, const double* pd, const dou
     if (!d.lds_red && d.variant == 1) panel = std::max(panel, N * ntile * 2 * (size_t)s.nx * s.col_tile);
     const size_t stacked = d.variant == 2 ? N * (size_t)s.nz * s.nu_pad : 1;
     if ((e = dalloc(p, &d.pdb, N * s.nb)) != hipSuccess) goto hip_error;
+    if ((e = dalloc(p, &d.lstat, N * s.nl)) != hipSuccess) goto hip_error;
     if ((e = dalloc(p, &d.qdb, N * s.nb)) != hipSuccess) goto hip_error;
     if ((e = dalloc(p, &d.LV, N * s.nl * rkkt::kLVsize)) != hipSuccess) goto hip_error;
     if ((e = dalloc(p, &d.LH, N * s.nl * rkkt::kLHsize)) != hipSuccess) goto hip_error;
@@ -345,6 +346,8 @@ int rkkt_create(const rkkt_network* net, int n_scen, const double* pd, const dou
       if ((e = hipEventCreateWithFlags(&p->join_ev[i], hipEventDisableTiming)) != hipSuccess) goto hip_error;
     }
     if ((e = hipMemset(d.status, 0, 2 * sizeof(int))) != hipSuccess) goto hip_error;
+    rkkt::launch_line_status(d, nullptr, nullptr);
+    if ((e = hipGetLastError()) != hipSuccess) goto hip_error;
     // loads
     if (s.nload > 0) {
       double *tpd = nullptr, *tqd = nullptr;
@@ -386,6 +389,14 @@ int rkkt_set_loads(rkkt_problem* p, const double* pd_dev, const double* qd_dev, 
   if (p->d.nload == 0) return RKKT_OK;
   rkkt::launch_bus_loads(p->d, pd_dev, qd_dev, stream);
   return check_launch(p, "rkkt_set_loads");
+}
+
+int rkkt_set_line_status(rkkt_problem* p, const double* status_dev, hipStream_t stream) {
+  (void)hipGetLastError();  // do not report an earlier, unrelated error
+  if (!p) return fail(nullptr, RKKT_ERR_ARG, "rkkt_set_line_status: null handle");
+  if (!status_dev) return fail(p, RKKT_ERR_ARG, "rkkt_set_line_status: null status");
+  rkkt::launch_line_status(p->d, status_dev, stream);
+  return check_launch(p, "rkkt_set_line_status");
 }
 
 int rkkt_dims_get(const rkkt_problem* p, rkkt_dims* out) {

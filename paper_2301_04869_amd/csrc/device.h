@@ -28,6 +28,7 @@ struct DP {
   const double *ca, *cb, *cc;                 // per generator cost a Pg^2 + b Pg + c (per unit)
   const int *load_of_bus, *grow_bus, *gen_u;  // load index per bus, bus of every g row, u index of every generator's output
   double *pdb, *qdb;                          // [N][nb] bus loads
+  double *lstat;                              // [N][nl] line admittance factor (1 in service, 0 tripped)
   // permutation
   const int *perm, *pinv;
   // gathers
@@ -153,6 +154,7 @@ void launch_copy(const double* a, double* b, long long n, hipStream_t s);
 
 // launchers (k_eval.hip)
 void launch_bus_loads(const DP& d, const double* pd, const double* qd, hipStream_t s);
+void launch_line_status(const DP& d, const double* status, hipStream_t s);
 void launch_evaluate(const DP& d, const double* x, const double* u, const double* y,
                      const double* z, double w, double* f, double* gx, double* gu,
                      double* g, double* h, hipStream_t s);

@@ -58,7 +58,8 @@ __device__ inline void line_eval_one(const DP& d, int k, int l, const double* x,
   double sn, cs;
   sincos(dth, &sn, &cs);
   double A[4], B[4], C[4], D[4];
-  line_coeffs(d.gs[l], d.bs[l], d.bc[l], A, B, C, D);
+  const double st = d.lstat[(long long)k * d.nl + l];  // 0 for a tripped line
+  line_coeffs(st * d.gs[l], st * d.bs[l], st * d.bc[l], A, B, C, D);
   double val[4], grad[4][4];
   for (int q = 0; q < 4; ++q) {
     double T = C[q] * cs + D[q] * sn;
@@ -171,7 +172,8 @@ __device__ inline void line_hess_one(const DP& d, int k, int l, const double* x,
   double sn, cs;
   sincos(dth, &sn, &cs);
   double A[4], B[4], C[4], D[4];
-  line_coeffs(d.gs[l], d.bs[l], d.bc[l], A, B, C, D);
+  const double st = d.lstat[(long long)k * d.nl + l];
+  line_coeffs(st * d.gs[l], st * d.bs[l], st * d.bc[l], A, B, C, D);
   const double pgref = ev[d.off_P + d.ref] + d.pdb[(long long)k * d.nb + d.ref];
   double H[kLHsize];
   for (int q = 0; q < kLHsize; ++q) H[q] = 0.0;
@@ -281,6 +283,17 @@ __global__ void k_condense_values(DP d, const double* sx, const double* ss, doub
 }
 
 }  // namespace
+
+__global__ void k_line_status(DP d, const double* st) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < (long long)d.N * d.nl) d.lstat[t] = st ? st[t] : 1.0;
+}
+
+// copies the status into the handle (st == nullptr: every line in service)
+void launch_line_status(const DP& d, const double* st, hipStream_t s) {
+  const long long n = (long long)d.N * d.nl;
+  k_line_status<<<grid_for(n), kBlock, 0, s>>>(d, st);
+}
 
 void launch_bus_loads(const DP& d, const double* pd, const double* qd, hipStream_t s) {
   long long n = (long long)d.N * d.nb;

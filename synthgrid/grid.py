@@ -346,3 +346,27 @@ def batch_instances(n: int = 64, seed: int = 2000, lo: int = 300, hi: int = 2000
                              seed * 1000 + i, loads="pq", sigma=sigma, name=f"batch{i}")
         out.append(inst)
     return out
+
+
+def line_outages(net: Network, n_scen: int, seed: int, frac: float = 0.5) -> np.ndarray:
+    """One tripped line or none per scenario (contingency scenarios): with
+    probability `frac` a scenario trips a line drawn uniformly from the lines
+    whose removal keeps the grid connected (so the state Jacobian stays
+    nonsingular); -1 = no outage.  Seeded; no model arithmetic."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components
+    rng = np.random.default_rng(seed)
+    nb, nl = net.n_bus, net.n_line
+    ok = []
+    for l in range(nl):
+        keep = np.arange(nl) != l
+        f, t = net.line_from[keep], net.line_to[keep]
+        adj = sp.coo_matrix((np.ones(len(f)), (f, t)), shape=(nb, nb))
+        ncomp, _ = connected_components(adj, directed=False)
+        if ncomp == 1:
+            ok.append(l)
+    ok = np.asarray(ok, dtype=np.int64)
+    out = np.full(n_scen, -1, dtype=np.int64)
+    trip = rng.uniform(size=n_scen) < frac
+    out[trip] = rng.choice(ok, size=int(trip.sum()))
+    return out

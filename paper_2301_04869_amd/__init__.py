@@ -6,7 +6,8 @@ from ._lib import (RkktError, lib, rkkt_analyze, rkkt_create, rkkt_set_loads, rk
                    rkkt_destroy, rkkt_last_error, rkkt_profile_begin, rkkt_profile_end,
                    rkkt_solve, rkkt_iterate, rkkt_graph_capture, rkkt_graph_launch,
                    rkkt_batch_create, rkkt_batch_launch, rkkt_batch_destroy, rkkt_autotune,
-                   rkkt_analyze_lu, rkkt_analyze_schedule, SCHEDULES, EXPORTS, STAGES, LIB_PATH)
+                   rkkt_analyze_lu, rkkt_analyze_schedule, SCHEDULES, EXPORTS, STAGES, LIB_PATH,
+                   Mlp, mlp_layout, MLP_EXPORTS)
 
 __all__ = ["RkktError", "lib", "rkkt_analyze", "rkkt_create", "rkkt_set_loads", "rkkt_set_line_status", "rkkt_dims_get",
            "rkkt_evaluate", "rkkt_condense", "rkkt_factor", "rkkt_step", "rkkt_status",
@@ -14,4 +15,4 @@ __all__ = ["RkktError", "lib", "rkkt_analyze", "rkkt_create", "rkkt_set_loads", 
            "rkkt_solve", "rkkt_iterate", "rkkt_graph_capture",
            "rkkt_graph_launch", "rkkt_batch_create", "rkkt_batch_launch", "rkkt_batch_destroy",
            "rkkt_autotune", "rkkt_analyze_lu", "rkkt_analyze_schedule", "SCHEDULES", "EXPORTS",
-           "STAGES", "LIB_PATH"]
+           "STAGES", "LIB_PATH", "Mlp", "mlp_layout", "MLP_EXPORTS"]

@@ -27,6 +27,9 @@ EXPORTS = ("rkkt_create", "rkkt_analyze", "rkkt_set_loads", "rkkt_dims_get", "rk
            "rkkt_iterate", "rkkt_graph_capture", "rkkt_graph_launch", "rkkt_batch_create",
            "rkkt_batch_launch", "rkkt_batch_destroy", "rkkt_autotune", "rkkt_analyze_lu",
            "rkkt_analyze_schedule", "rkkt_set_line_status")
+MLP_EXPORTS = ("rkkt_mlp_create", "rkkt_mlp_destroy", "rkkt_mlp_last_error", "rkkt_mlp_n_params",
+               "rkkt_mlp_set_params", "rkkt_mlp_get_params", "rkkt_mlp_forward", "rkkt_mlp_gradients",
+               "rkkt_mlp_train_step")
 IPM_STATUS = {0: "converged", 1: "max_iter", 2: "line_search_failed",
               3: "inertia_correction_failed", 4: "device_error"}
 STAGES = ("evaluate", "condense_values", "refactor", "reduce", "scenario_sum", "factor",
@@ -140,6 +143,20 @@ def lib():
                                         ctypes.c_int] + [c_int_p] * 9
     L.rkkt_last_error.argtypes = [vp]
     L.rkkt_last_error.restype = ctypes.c_char_p
+    L.rkkt_mlp_create.argtypes = [c_int_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)]
+    L.rkkt_mlp_destroy.argtypes = [vp]
+    L.rkkt_mlp_last_error.argtypes = [vp]
+    L.rkkt_mlp_last_error.restype = ctypes.c_char_p
+    L.rkkt_mlp_n_params.argtypes = [vp]
+    L.rkkt_mlp_n_params.restype = ctypes.c_longlong
+    L.rkkt_mlp_set_params.argtypes = [vp, vp, vp]
+    L.rkkt_mlp_get_params.argtypes = [vp, vp, vp]
+    L.rkkt_mlp_forward.argtypes = [vp, vp, ctypes.c_int, vp, vp]
+    L.rkkt_mlp_gradients.argtypes = [vp, vp, vp, ctypes.c_int, vp, vp, vp]
+    L.rkkt_mlp_train_step.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_float, vp, vp]
+    for name in ("rkkt_mlp_create", "rkkt_mlp_destroy", "rkkt_mlp_set_params", "rkkt_mlp_get_params",
+                 "rkkt_mlp_forward", "rkkt_mlp_gradients", "rkkt_mlp_train_step"):
+        getattr(L, name).restype = ctypes.c_int
     for name in EXPORTS:
         if name != "rkkt_last_error":
             getattr(L, name).restype = ctypes.c_int
@@ -453,3 +470,75 @@ def rkkt_destroy(p):
 
 def rkkt_last_error(p=None):
     return lib().rkkt_last_error(p.ptr if p is not None else None).decode()
+
+
+# ------------------------------------------------------------ warm-start MLP
+def _fptr(t, name, numel=None):
+    if t is None:
+        raise ValueError(f"{name} is None")
+    if not (t.is_cuda and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous device tensor")
+    if str(t.dtype) != "torch.float32":
+        raise ValueError(f"{name} must be float32")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Mlp:
+    """An rkkt_mlp* (rkkt_mlp.h); destroyed with the object."""
+
+    def __init__(self, sizes, batch_max):
+        sizes = np.ascontiguousarray(sizes, dtype=np.int32)
+        h = ctypes.c_void_p()
+        rc = lib().rkkt_mlp_create(sizes.ctypes.data_as(c_int_p), len(sizes) - 1, int(batch_max),
+                                   ctypes.byref(h))
+        if rc != RKKT_OK:
+            raise RkktError(rc, lib().rkkt_mlp_last_error(None).decode())
+        self.ptr = h
+        self.sizes = [int(v) for v in sizes]
+        self.batch_max = int(batch_max)
+        self.n_params = int(lib().rkkt_mlp_n_params(h))
+
+    def _check(self, rc):
+        if rc != RKKT_OK:
+            raise RkktError(rc, lib().rkkt_mlp_last_error(self.ptr).decode())
+
+    def set_params(self, params, stream=None):
+        self._check(lib().rkkt_mlp_set_params(self.ptr, _fptr(params, "params", self.n_params), _stream(stream)))
+
+    def get_params(self, params, stream=None):
+        self._check(lib().rkkt_mlp_get_params(self.ptr, _fptr(params, "params", self.n_params), _stream(stream)))
+
+    def forward(self, x, y, stream=None):
+        b = x.shape[0]
+        self._check(lib().rkkt_mlp_forward(self.ptr, _fptr(x, "x", b * self.sizes[0]), b,
+                                           _fptr(y, "y", b * self.sizes[-1]), _stream(stream)))
+
+    def gradients(self, x, t, grads, loss, stream=None):
+        b = x.shape[0]
+        g = _fptr(grads, "grads", self.n_params) if grads is not None else None
+        self._check(lib().rkkt_mlp_gradients(self.ptr, _fptr(x, "x", b * self.sizes[0]),
+                                             _fptr(t, "t", b * self.sizes[-1]), b, g,
+                                             _fptr(loss, "loss", 1), _stream(stream)))
+
+    def train_step(self, x, t, lr, loss, stream=None):
+        b = x.shape[0]
+        self._check(lib().rkkt_mlp_train_step(self.ptr, _fptr(x, "x", b * self.sizes[0]),
+                                              _fptr(t, "t", b * self.sizes[-1]), b, float(lr),
+                                              _fptr(loss, "loss", 1), _stream(stream)))
+
+    def __del__(self):
+        if getattr(self, "ptr", None) and _lib is not None:
+            _lib.rkkt_mlp_destroy(self.ptr)
+            self.ptr = None
+
+
+def mlp_layout(sizes):
+    """(offset of W_l, offset of b_l) per layer in the parameter vector."""
+    out, off = [], 0
+    for fi, fo in zip(sizes[:-1], sizes[1:]):
+        out.append((off, off + fi * fo))
+        off += fi * fo + fo
+    return out
+

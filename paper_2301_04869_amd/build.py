@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["symbolic.cpp", "api.cpp", "ipm.cpp", "k_eval.hip", "k_lu.hip", "k_dense.hip", "k_ipm.hip"]
+SOURCES = ["symbolic.cpp", "api.cpp", "ipm.cpp", "mlp.cpp", "k_eval.hip", "k_lu.hip", "k_dense.hip", "k_ipm.hip",
+           "k_mlp.hip"]
 LIB = os.path.join(HERE, "librkkt.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -35,7 +36,8 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
             _wait(procs)
     _wait(procs)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,
+           "-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocblas"]
     if verbose:
         print(" ".join(cmd))
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)

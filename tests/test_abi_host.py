@@ -1,5 +1,5 @@
-"""The C ABI library loads on the CPU, exports every symbol include/rkkt.h
-declares, and its host-only analysis gives the documented sizes.  No GPU."""
+"""The C ABI library loads on the CPU, exports every symbol include/*.h
+declare, and its host-only analysis gives the documented sizes.  No GPU."""
 import os
 import re
 
@@ -11,19 +11,21 @@ import synthgrid as sg
 ROOT = os.path.abspath(os.path.join(os.path.dirname(__file__), ".."))
 
 
-def _declared():
-    text = open(os.path.join(ROOT, "include", "rkkt.h")).read()
+def _declared(header):
+    text = open(os.path.join(ROOT, "include", header)).read()
     return sorted(set(re.findall(r"\b(rkkt_[a-z_]+)\s*\(", text)))
 
 
 def test_library_exports_every_declared_symbol():
     import paper_2301_04869_amd as R
     L = R.lib()
-    names = _declared()
-    assert len(names) >= 10
-    for n in names:
-        assert hasattr(L, n), n
-    assert set(names) == set(R.EXPORTS)
+    headers = sorted(h for h in os.listdir(os.path.join(ROOT, "include")) if h.endswith(".h"))
+    assert headers == ["rkkt.h", "rkkt_mlp.h"]
+    for h in headers:
+        for n in _declared(h):
+            assert hasattr(L, n), (h, n)
+    assert set(_declared("rkkt.h")) == set(R.EXPORTS)
+    assert set(_declared("rkkt_mlp.h")) == set(R.MLP_EXPORTS)
 
 
 @pytest.mark.parametrize("name", ["tiny5", "c0", "c1", "c4"])

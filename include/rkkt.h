@@ -281,6 +281,20 @@ int rkkt_solve(rkkt_problem* p, const rkkt_ipm_options* opt, double* x, double* 
                double* z, double* s, rkkt_ipm_result* res, hipStream_t stream);
 
 /*
+ * The same solve from a given start point (a learned warm start): x0
+ * [N][n_x], u0 [n_u] are pushed into their boxes by 1e-6 (relative), the
+ * slacks follow from h as in the cold start, y0 [N][n_x], z0 [N][m] are the
+ * multipliers for the objective weighted 1/N (the solver rescales them to its
+ * own objective scaling; a cold solve's multipliers convert with the factor
+ * 1 / (N res.obj_weight)), and every bound multiplier is set from
+ * complementarity at opt->mu0, which is also the starting barrier parameter.
+ * Device arrays; RKKT_ERR_ARG if any start array is null.
+ */
+int rkkt_solve_warm(rkkt_problem* p, const rkkt_ipm_options* opt, const double* x0, const double* u0,
+                    const double* y0, const double* z0, double* x, double* u, double* y, double* z,
+                    double* s, rkkt_ipm_result* res, hipStream_t stream);
+
+/*
  * Stage timing with HIP events recorded on the caller's stream around every
  * internal launch group (for benchmarks).  rkkt_profile_begin creates up to
  * max_records event pairs (this call allocates) and starts recording;

@@ -26,7 +26,7 @@ EXPORTS = ("rkkt_create", "rkkt_analyze", "rkkt_set_loads", "rkkt_dims_get", "rk
            "rkkt_last_error", "rkkt_profile_begin", "rkkt_profile_end", "rkkt_solve",
            "rkkt_iterate", "rkkt_graph_capture", "rkkt_graph_launch", "rkkt_batch_create",
            "rkkt_batch_launch", "rkkt_batch_destroy", "rkkt_autotune", "rkkt_analyze_lu",
-           "rkkt_analyze_schedule", "rkkt_set_line_status")
+           "rkkt_analyze_schedule", "rkkt_set_line_status", "rkkt_solve_warm")
 MLP_EXPORTS = ("rkkt_mlp_create", "rkkt_mlp_destroy", "rkkt_mlp_last_error", "rkkt_mlp_n_params",
                "rkkt_mlp_set_params", "rkkt_mlp_get_params", "rkkt_mlp_forward", "rkkt_mlp_gradients",
                "rkkt_mlp_train_step")
@@ -127,6 +127,8 @@ def lib():
     L.rkkt_profile_end.argtypes = [vp, vp, c_dbl_p, c_int_p]
     L.rkkt_solve.argtypes = [vp, ctypes.POINTER(IpmOptions), vp, vp, vp, vp, vp,
                              ctypes.POINTER(IpmResult), vp]
+    L.rkkt_solve_warm.argtypes = [vp, ctypes.POINTER(IpmOptions), vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                                  ctypes.POINTER(IpmResult), vp]
     L.rkkt_iterate.argtypes = [vp, ctypes.POINTER(Iteration), vp]
     L.rkkt_graph_capture.argtypes = [vp, ctypes.POINTER(Iteration)]
     L.rkkt_graph_launch.argtypes = [vp, vp]
@@ -389,6 +391,27 @@ def rkkt_solve(p, x=None, u=None, y=None, z=None, s=None, tol=0.0, max_iter=-1, 
                             opt(x, "x", N * nx), opt(u, "u", nu), opt(y, "y", N * nx),
                             opt(z, "z", N * m), opt(s, "s", N * m), ctypes.byref(r),
                             _stream(stream)), p.ptr)
+    out = {k: getattr(r, k) for k, _ in r._fields_}
+    out["status"] = IPM_STATUS.get(out["status"], out["status"])
+    return out
+
+
+def rkkt_solve_warm(p, x0, u0, y0, z0, x=None, u=None, y=None, z=None, s=None, tol=0.0, max_iter=-1,
+                    mu0=0.0, verbose=False, stream=None):
+    """Device interior-point solve from a start point (device float64 x0
+    [N][n_x], u0 [n_u], y0 [N][n_x], z0 [N][m]; multipliers for the objective
+    weighted 1/N).  Returns the result fields as a dict."""
+    d = p.dims
+    N, nx, nu, m = d["n_scen"], d["n_x"], d["n_u"], d["m"]
+
+    def opt(t, name, n):
+        return ctypes.c_void_p(None) if t is None else _ptr(t, name, n)
+    r = IpmResult()
+    _check(lib().rkkt_solve_warm(p.ptr, ctypes.byref(IpmOptions(tol, max_iter, mu0, int(verbose))),
+                                 _ptr(x0, "x0", N * nx), _ptr(u0, "u0", nu), _ptr(y0, "y0", N * nx),
+                                 _ptr(z0, "z0", N * m), opt(x, "x", N * nx), opt(u, "u", nu),
+                                 opt(y, "y", N * nx), opt(z, "z", N * m), opt(s, "s", N * m),
+                                 ctypes.byref(r), _stream(stream)), p.ptr)
     out = {k: getattr(r, k) for k, _ in r._fields_}
     out["status"] = IPM_STATUS.get(out["status"], out["status"])
     return out

@@ -28,6 +28,7 @@ struct Opt {
   double gamma_theta = 1e-5, gamma_phi = 1e-8, s_theta = 1.1, s_phi = 2.3, delta_sw = 1.0;
   double eta_phi = 1e-8, gamma_alpha = 0.05, kappa_sigma = 1e10, obj_grad_max = 100.0;
   int max_iter = 200;
+  double kappa_warm = 1e-6;  // interior push of a warm start point
 };
 
 template <typename T>
@@ -81,10 +82,12 @@ hipError_t ipm_workspace(rkkt_problem* p) {
 
 }  // namespace
 
-extern "C" int rkkt_solve(rkkt_problem* p, const rkkt_ipm_options* uopt, double* x_out,
-                          double* u_out, double* y_out, double* z_out, double* s_out,
-                          rkkt_ipm_result* res, hipStream_t st) {
+// warm: x0, u0, y0, z0 (device) or all null for the cold start
+static int solve_impl(rkkt_problem* p, const rkkt_ipm_options* uopt, const double* x0, const double* u0,
+                      const double* y0, const double* z0, double* x_out, double* u_out, double* y_out,
+                      double* z_out, double* s_out, rkkt_ipm_result* res, hipStream_t st) {
   if (!p || !res) return RKKT_ERR_ARG;
+  const bool warm = x0 != nullptr;
   Opt o;
   int verbose = 0;
   if (uopt) {
@@ -146,13 +149,16 @@ extern "C" int rkkt_solve(rkkt_problem* p, const rkkt_ipm_options* uopt, double*
 
   // ---- start point and objective scaling
   rkkt::ipm_init_primal(d, s, o.kappa1, o.kappa2, st);
+  if (warm) rkkt::ipm_warm_primal(d, s, x0, u0, o.kappa_warm, o.kappa_warm, st);
   CK(hipGetLastError());
   CR(eval(false, 1.0 / N));
-  rkkt::ipm_init_slack(d, s, o.kappa1, o.kappa2, st);
+  rkkt::ipm_init_slack(d, s, warm ? o.kappa_warm : o.kappa1, warm ? o.kappa_warm : o.kappa2, st);
   rkkt::ipm_grad_max(d, s, s.scal, st);
   CK(fetch(1));
   const double scale = hs[0] > 0 ? std::min(1.0, o.obj_grad_max / hs[0]) : 1.0;
   const double w = scale / N;
+  // warm multipliers are given for objective weight 1 / N: scale them by w N
+  if (warm) rkkt::ipm_warm_duals(d, s, y0, z0, w * N, o.mu0, st);
   double mu = o.mu0;
   double tau = std::max(o.tau_min, 1.0 - mu);
   CR(eval(false, w));
@@ -278,3 +284,19 @@ extern "C" int rkkt_solve(rkkt_problem* p, const rkkt_ipm_options* uopt, double*
 #undef CR
   return RKKT_OK;
 }
+
+extern "C" int rkkt_solve(rkkt_problem* p, const rkkt_ipm_options* opt, double* x, double* u, double* y,
+                          double* z, double* s, rkkt_ipm_result* res, hipStream_t stream) {
+  return solve_impl(p, opt, nullptr, nullptr, nullptr, nullptr, x, u, y, z, s, res, stream);
+}
+
+extern "C" int rkkt_solve_warm(rkkt_problem* p, const rkkt_ipm_options* opt, const double* x0,
+                               const double* u0, const double* y0, const double* z0, double* x, double* u,
+                               double* y, double* z, double* s, rkkt_ipm_result* res, hipStream_t stream) {
+  if (!x0 || !u0 || !y0 || !z0) {
+    if (p) p->err = "rkkt_solve_warm: null start point";
+    return RKKT_ERR_ARG;
+  }
+  return solve_impl(p, opt, x0, u0, y0, z0, x, u, y, z, s, res, stream);
+}
+

@@ -35,5 +35,9 @@ void ipm_accept(const DP& d, const IpmDev& s, double alpha, double alpha_z, doub
 void ipm_init_primal(const DP& d, const IpmDev& s, double k1, double k2, hipStream_t st);
 void ipm_init_slack(const DP& d, const IpmDev& s, double k1, double k2, hipStream_t st);
 void ipm_grad_max(const DP& d, const IpmDev& s, double* out, hipStream_t st);
+void ipm_warm_primal(const DP& d, const IpmDev& s, const double* x0, const double* u0, double k1, double k2,
+                     hipStream_t st);
+void ipm_warm_duals(const DP& d, const IpmDev& s, const double* y0, const double* z0, double mult, double mu0,
+                    hipStream_t st);
 
 }  // namespace rkkt

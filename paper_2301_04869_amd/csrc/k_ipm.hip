@@ -391,6 +391,47 @@ __global__ void k_init_slack(DP d, IpmDev s, double k1, double k2) {
   s.s[t] = push(-s.h[t], s.sl[i], s.su[i], k1, k2);
 }
 
+// warm start, primal part: x0, u0 pushed into the boxes
+__global__ void k_warm_primal(DP d, IpmDev s, const double* x0, const double* u0, double k1, double k2) {
+  const long long nxN = (long long)d.N * d.nx;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < nxN) {
+    const int i = (int)(t % d.nx);
+    s.x[t] = push(x0[t], s.xl[i], s.xu[i], k1, k2);
+  } else if (t - nxN < d.nu) {
+    const int c = (int)(t - nxN);
+    s.u[c] = push(u0[c], s.ul[c], s.uu[c], k1, k2);
+  }
+}
+
+// warm start, dual part: y = mult y0, z = mult z0, and every bound
+// multiplier from complementarity at mu0 (mu0 / gap), after the slacks
+__global__ void k_warm_duals(DP d, IpmDev s, const double* y0, const double* z0, double mult, double mu0) {
+  const long long nxN = (long long)d.N * d.nx, nmN = (long long)d.N * d.m;
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < nxN) {
+    const int i = (int)(t % d.nx);
+    s.y[t] = mult * y0[t];
+    s.zlx[t] = fin(s.xl[i]) ? mu0 / (s.x[t] - s.xl[i]) : 0.0;
+    s.zux[t] = fin(s.xu[i]) ? mu0 / (s.xu[i] - s.x[t]) : 0.0;
+    return;
+  }
+  t -= nxN;
+  if (t < nmN) {
+    const int i = (int)(t % d.m);
+    s.z[t] = mult * z0[t];
+    s.zls[t] = fin(s.sl[i]) ? mu0 / (s.s[t] - s.sl[i]) : 0.0;
+    s.zus[t] = fin(s.su[i]) ? mu0 / (s.su[i] - s.s[t]) : 0.0;
+    return;
+  }
+  t -= nmN;
+  if (t < d.nu) {
+    const int c = (int)t;
+    s.zlu[c] = fin(s.ul[c]) ? mu0 / (s.u[c] - s.ul[c]) : 0.0;
+    s.zuu[c] = fin(s.uu[c]) ? mu0 / (s.uu[c] - s.u[c]) : 0.0;
+  }
+}
+
 // out[0] = max(max |grad_x f_i|, max |sum_i grad_u f_i|)
 __global__ __launch_bounds__(kRed) void k_grad_max(DP d, IpmDev s, double* out) {
   __shared__ double sh[kRed];
@@ -449,6 +490,18 @@ void ipm_init_primal(const DP& d, const IpmDev& s, double k1, double k2, hipStre
 void ipm_init_slack(const DP& d, const IpmDev& s, double k1, double k2, hipStream_t st) {
   const long long n = (long long)d.N * d.m;
   k_init_slack<<<grid_for(n), kBlock, 0, st>>>(d, s, k1, k2);
+}
+
+void ipm_warm_primal(const DP& d, const IpmDev& s, const double* x0, const double* u0, double k1, double k2,
+                     hipStream_t st) {
+  const long long n = (long long)d.N * d.nx + d.nu;
+  k_warm_primal<<<grid_for(n), kBlock, 0, st>>>(d, s, x0, u0, k1, k2);
+}
+
+void ipm_warm_duals(const DP& d, const IpmDev& s, const double* y0, const double* z0, double mult, double mu0,
+                    hipStream_t st) {
+  const long long n = (long long)d.N * (d.nx + d.m) + d.nu;
+  k_warm_duals<<<grid_for(n), kBlock, 0, st>>>(d, s, y0, z0, mult, mu0);
 }
 
 void ipm_grad_max(const DP& d, const IpmDev& s, double* out, hipStream_t st) {

@@ -32,6 +32,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP64_PEAK_TFS = 78.6           # MI355X FP64 vector (and FP64 matrix) TFLOP/s
 
 WORKLOADS = {
+    "warm": "learned warm start on the 118-bus grid (load draws sigma 0.15)",
     "c1": "118-bus / 186-line / 54-generator synthetic grid (the sizes of the paper's case118), "
           "N = 128 load scenarios (sigma 0.1), n_x = 181, n_u = 107; full hot path per step",
     "c4": "9241-bus / 16049-line / 1445-generator synthetic grid (the sizes of the paper's "
@@ -40,6 +41,60 @@ WORKLOADS = {
           "0.15 n_bus generators; autotuned column tiles; all 64 passes in one graph launch vs 64 "
           "sequential plain launches",
 }
+
+
+def warm_main(args):
+    """Learned warm start on the 118-bus grid: cold device IPM solves of
+    seeded load draws (sigma 0.15), the perceptron 198 -> 512 -> 512 -> 512
+    -> 896 trained on the first n_train, warm solves of the rest."""
+    import torch
+    import synthgrid as sg
+    from paper_2301_04869_amd import warmstart as ws
+    n_tr, n_va, n_te = args.n_train, args.n_val, args.n_test
+    inst = sg.preset("c3", n_scen=n_tr + n_va + n_te)
+    res = ws.experiment(torch, inst.net, inst.scen.pd, inst.scen.qd, n_train=n_tr, n_val=n_va,
+                        mu0s=(1e-2, 1e-3, 1e-4, 1e-5, 1e-6), steps=args.train_steps,
+                        log=lambda m: print(m, file=sys.stderr, flush=True))
+    # training-step rate of the perceptron alone (batch 256), HIP events
+    dd = sg.dims(inst.net.n_bus, inst.net.n_line, inst.net.n_gen)
+    sizes = [2 * len(inst.net.load_bus), 512, 512, 512, 2 * dd["n_x"] + dd["n_u"] + dd["m"]]
+    import paper_2301_04869_amd as R
+    m = R.Mlp(sizes, 256)
+    m.set_params(torch.tensor(ws.init_params(sizes, 0), device="cuda"))
+    x = torch.randn(256, sizes[0], device="cuda")
+    t = torch.randn(256, sizes[-1], device="cuda")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    for _ in range(20):
+        m.train_step(x, t, 1e-4, loss)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(200):
+        m.train_step(x, t, 1e-4, loss)
+    e1.record()
+    torch.cuda.synchronize()
+    step_ms = e0.elapsed_time(e1) / 200
+    n_par = m.n_params
+    flops = 6.0 * 256 * sum(a * b for a, b in zip(sizes[:-1], sizes[1:]))
+    out = {"metric": "mean IPM iterations per solve, cold vs learned warm start (fallbacks counted)",
+           "value": res["warm_mean_iters"], "unit": "IPM iterations", "n_gpus": 1,
+           "steps": res["n_test"], "warmup": 0, "ms_per_step": None, "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64 solves, bf16 products in the MLP",
+           "data": "synthetic",
+           "config": {"workload": "118-bus grid, load draws sigma 0.15 (the warm-start set); MLP "
+                      f"{sizes}, {n_par} parameters; {n_tr} training / {n_va} validation / {n_te} "
+                      "test draws; warm-start mu0 chosen on the validation draws",
+                      "train_steps": args.train_steps, "mu0_warm": res["mu0_warm"],
+                      "validation_mean_iters": res["validation_mean_iters"]},
+           "cold_mean_iters": res["cold_mean_iters"], "fallback_rate": res["fallback_rate"],
+           "max_rel_obj_diff": res["max_rel_obj_diff"], "cold_solve_seconds": res["cold_solve_seconds"],
+           "train_seconds": res["train_seconds"],
+           "mlp_train_step_ms": step_ms, "mlp_samples_per_s": 256 / (step_ms * 1e-3),
+           "mlp_roofline": {"bound": "mfma", "achieved": flops / (step_ms * 1e-3) / 1e12, "peak": 2500.0,
+                            "unit": "TFLOP/s", "frac": flops / (step_ms * 1e-3) / 1e12 / 2500.0,
+                            "traffic": None}}
+    print(json.dumps(out), flush=True)
 
 
 def batch_main(args):
@@ -248,6 +303,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--seed", type=int, default=2024)
+    ap.add_argument("--n-train", type=int, default=2000, help="warm: training draws")
+    ap.add_argument("--n-val", type=int, default=100, help="warm: validation draws (choice of mu0)")
+    ap.add_argument("--n-test", type=int, default=200, help="warm: held-out draws")
+    ap.add_argument("--train-steps", type=int, default=10000, help="warm: Adam steps")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device copies of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -274,6 +333,9 @@ def main():
     R.lib()
     if args.config == "c2":
         batch_main(args)
+        return
+    if args.config == "warm":
+        warm_main(args)
         return
     inst = sg.preset(args.config)
     net, N = inst.net, inst.scen.n_scen

@@ -123,29 +123,11 @@ def predict(torch, m, X):
     return out.cpu().numpy().astype(np.float64)
 
 
-def experiment(torch, net, pd, qd, n_train, mu0=1e-4, tol=1e-8, steps=2000, seed=0, log=print):
-    """Cold solves of every draw, training on the first n_train, warm solves
-    of the rest; returns a dict of the comparison (iterations counted with
-    fallbacks: a warm solve that fails or whose objective differs from the
-    cold one by more than 1e-6 relative adds the cold iterations)."""
-    solver = Solver(net, torch)
-    t0 = time.time()
-    sols, its, objs, ok = solve_draws(solver, pd, qd, tol)
-    t_solve = time.time() - t0
-    log(f"cold solves: {len(its)} in {t_solve:.1f} s, mean {its.mean():.2f} iterations, "
-        f"{(~ok).sum()} not converged")
-    X = np.concatenate([pd.T, qd.T], axis=1)
-    tr = np.arange(n_train)[ok[:n_train]]
-    te = np.arange(n_train, len(its))[ok[n_train:]]
-    sx, sy = Standardizer(X[tr]), Standardizer(sols[tr])
-    sizes = [X.shape[1], 512, 512, 512, sols.shape[1]]
-    t0 = time.time()
-    mlp, hist = fit(torch, sx.fwd(X[tr]), sy.fwd(sols[tr]), sizes, steps=steps, seed=seed)
-    t_train = time.time() - t0
-    log(f"training: {steps} steps in {t_train:.1f} s, loss {hist[0]:.3e} -> {hist[-1]:.3e}")
-    pred = sy.inv(predict(torch, mlp, sx.fwd(X[te])))
+def warm_solves(solver, torch, pd, qd, idx, pred, objs, its, mu0, tol):
+    """Warm solves of the draws idx from the predictions; (iterations with
+    fallbacks counted, number of fallbacks, relative objective differences)."""
     warm_its, fallbacks, obj_err = [], 0, []
-    for j, k in enumerate(te):
+    for j, k in enumerate(idx):
         solver.set_loads(pd[:, k], qd[:, k])
         r, _ = solver.solve(tol, warm=solver.split(pred[j]), mu0=mu0)
         rel = abs(r["obj"] - objs[k]) / max(abs(objs[k]), 1e-300)
@@ -155,11 +137,49 @@ def experiment(torch, net, pd, qd, n_train, mu0=1e-4, tol=1e-8, steps=2000, seed
             fallbacks += 1
             n += its[k]
         warm_its.append(n)
-    warm_its = np.array(warm_its)
-    out = {"n_train": int(len(tr)), "n_test": int(len(te)), "cold_mean_iters": float(its[te].mean()),
-           "warm_mean_iters": float(warm_its.mean()), "fallback_rate": fallbacks / max(len(te), 1),
-           "max_rel_obj_diff": float(np.max(obj_err)) if obj_err else 0.0, "train_loss": hist,
-           "cold_solve_seconds": t_solve, "train_seconds": t_train, "mu0_warm": mu0}
-    log(f"test: cold {out['cold_mean_iters']:.2f} vs warm {out['warm_mean_iters']:.2f} mean iterations, "
-        f"fallback rate {out['fallback_rate']:.3f}")
+    return np.array(warm_its), fallbacks, np.array(obj_err)
+
+
+def experiment(torch, net, pd, qd, n_train, n_val=0, mu0s=(1e-4,), tol=1e-8, steps=2000, seed=0, log=print):
+    """Cold solves of every draw; training on the first n_train, the warm
+    start's barrier parameter chosen among mu0s on the next n_val draws (the
+    first of mu0s without validation draws), warm solves of the rest.
+    Iterations are counted with fallbacks: a warm solve that fails or whose
+    objective differs from the cold one by more than 1e-6 relative adds the
+    cold iterations."""
+    solver = Solver(net, torch)
+    t0 = time.time()
+    sols, its, objs, ok = solve_draws(solver, pd, qd, tol)
+    t_solve = time.time() - t0
+    log(f"cold solves: {len(its)} in {t_solve:.1f} s, mean {its.mean():.2f} iterations, "
+        f"{(~ok).sum()} not converged")
+    X = np.concatenate([pd.T, qd.T], axis=1)
+    tr = np.arange(n_train)[ok[:n_train]]
+    va = np.arange(n_train, n_train + n_val)[ok[n_train:n_train + n_val]]
+    te = np.arange(n_train + n_val, len(its))[ok[n_train + n_val:]]
+    sx, sy = Standardizer(X[tr]), Standardizer(sols[tr])
+    sizes = [X.shape[1], 512, 512, 512, sols.shape[1]]
+    t0 = time.time()
+    mlp, hist = fit(torch, sx.fwd(X[tr]), sy.fwd(sols[tr]), sizes, steps=steps, seed=seed)
+    t_train = time.time() - t0
+    log(f"training: {steps} steps in {t_train:.1f} s, loss {hist[0]:.3e} -> {hist[-1]:.3e}")
+    mu0 = mu0s[0]
+    val = {}
+    if len(va):
+        pv = sy.inv(predict(torch, mlp, sx.fwd(X[va])))
+        for m0 in mu0s:
+            wi, fb, _ = warm_solves(solver, torch, pd, qd, va, pv, objs, its, m0, tol)
+            val[m0] = float(wi.mean())
+            log(f"validation: mu0 {m0:g}: warm {wi.mean():.2f} vs cold {its[va].mean():.2f}, {fb} fallbacks")
+        mu0 = min(val, key=val.get)
+    pred = sy.inv(predict(torch, mlp, sx.fwd(X[te])))
+    warm_its, fallbacks, obj_err = warm_solves(solver, torch, pd, qd, te, pred, objs, its, mu0, tol)
+    out = {"n_train": int(len(tr)), "n_val": int(len(va)), "n_test": int(len(te)),
+           "cold_mean_iters": float(its[te].mean()), "warm_mean_iters": float(warm_its.mean()),
+           "fallback_rate": fallbacks / max(len(te), 1),
+           "max_rel_obj_diff": float(np.max(obj_err)) if len(obj_err) else 0.0, "train_loss": hist,
+           "cold_solve_seconds": t_solve, "train_seconds": t_train, "mu0_warm": mu0,
+           "validation_mean_iters": {f"{k:g}": v for k, v in val.items()}}
+    log(f"test: cold {out['cold_mean_iters']:.2f} vs warm {out['warm_mean_iters']:.2f} mean iterations "
+        f"(mu0 {mu0:g}), fallback rate {out['fallback_rate']:.3f}")
     return out

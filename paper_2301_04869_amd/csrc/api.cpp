@@ -340,6 +340,7 @@ int rkkt_create(const rkkt_network* net, int n_scen, const double* pd, const dou
     if ((e = dalloc(p, &d.status, 2)) != hipSuccess) goto hip_error;
     if ((e = rkkt::configure_lu_kernels(d)) != hipSuccess) goto hip_error;
     if ((e = rkkt::configure_dense_kernels(d)) != hipSuccess) goto hip_error;
+    if ((e = rkkt::configure_eval_kernels(d)) != hipSuccess) goto hip_error;
     if ((e = hipStreamCreateWithFlags(&p->side_stream, hipStreamNonBlocking)) != hipSuccess) goto hip_error;
     for (int i = 0; i < 2; ++i) {
       if ((e = hipEventCreateWithFlags(&p->fork_ev[i], hipEventDisableTiming)) != hipSuccess) goto hip_error;

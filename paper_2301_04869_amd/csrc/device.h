@@ -160,6 +160,8 @@ void launch_evaluate(const DP& d, const double* x, const double* u, const double
                      double* g, double* h, hipStream_t s);
 void launch_condense_values(const DP& d, const double* sx, const double* ss, double dw,
                             hipStream_t s);
+// dynamic LDS limit of the fused line / gather kernel (never lowered)
+hipError_t configure_eval_kernels(const DP& d);
 // the two halves of launch_evaluate: line values and EV (all that the
 // refactorisation needs), then g, h, f, its gradients and W
 void launch_evaluate_values(const DP& d, const double* x, const double* u, hipStream_t s);

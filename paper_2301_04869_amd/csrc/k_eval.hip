@@ -222,6 +222,26 @@ __device__ inline double w_gather_one(const DP& d, int e, double w, const double
   return acc + w * prod;
 }
 
+// line values and the bus / Jacobian values of one scenario in one
+// workgroup, the line values in LDS (they feed only the gathers and, from
+// HBM, the kernels after; both copies are written)
+constexpr int kLvT = 512;
+
+__global__ __launch_bounds__(kLvT) void k_line_eval_gather(DP d, const double* x, const double* u) {
+  extern __shared__ double lv[];
+  const int k = blockIdx.x, tid = threadIdx.x;
+  double* glv = d.LV + (long long)k * d.nl * kLVsize;
+  for (int l = tid; l < d.nl; l += kLvT) {
+    double* o = lv + (long long)l * kLVsize;
+    line_eval_one(d, k, l, x, u, o);
+#pragma unroll
+    for (int q = 0; q < kLVsize; ++q) glv[(long long)l * kLVsize + q] = o[q];
+  }
+  __syncthreads();
+  double* gev = d.EV + (long long)k * d.n_ev;
+  for (int e = tid; e < d.n_ev; e += kLvT) gev[e] = gather_ev_one(d, e, lv);
+}
+
 __global__ void k_line_eval(DP d, const double* x, const double* u) {
   long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (long long)d.N * d.nl) return;
@@ -300,7 +320,24 @@ void launch_bus_loads(const DP& d, const double* pd, const double* qd, hipStream
   k_bus_loads<<<grid_for(n), kBlock, 0, s>>>(d, pd, qd);
 }
 
+// the fused line / gather kernel where a scenario's line values fit in LDS
+static long long line_lds_bytes(const DP& d) { return 8LL * d.nl * kLVsize; }
+static bool line_fused(const DP& d) { return line_lds_bytes(d) <= 96 * 1024; }
+
+hipError_t configure_eval_kernels(const DP& d) {
+  static int cur = 0;
+  if (!line_fused(d) || line_lds_bytes(d) <= cur) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute((const void*)k_line_eval_gather, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)line_lds_bytes(d));
+  if (e == hipSuccess) cur = (int)line_lds_bytes(d);
+  return e;
+}
+
 void launch_evaluate_values(const DP& d, const double* x, const double* u, hipStream_t s) {
+  if (line_fused(d)) {
+    k_line_eval_gather<<<d.N, kLvT, (size_t)line_lds_bytes(d), s>>>(d, x, u);
+    return;
+  }
   long long nl = (long long)d.N * d.nl;
   k_line_eval<<<grid_for(nl), kBlock, 0, s>>>(d, x, u);
   long long ne = (long long)d.N * d.n_ev;

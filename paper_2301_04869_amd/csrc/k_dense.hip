@@ -362,32 +362,195 @@ __device__ int chol_blocked_lds(double* sa, int n, int ld, int* sflag) {
   return 0;
 }
 
-// whole matrix in LDS (leading dimension n + 1); kR = rows per lane of the
-// panel factorisation (n <= 64 kR)
+// Factor of an n x n matrix (n <= kSmallN) in one workgroup of 8 wavefronts,
+// the matrix padded in LDS to a multiple of 16 with identity rows and its
+// lower triangle of 16 x 16 tiles kept there.  Right-looking by 16-column
+// panels with look-ahead:
+//  - wavefront 0 factorises the panel's diagonal tile in registers
+//    (chol_tile16), which also yields the tile's inverse L_kk^-1;
+//  - the owner of each block row i below forms L_ik = A_ik L_kk^-T as the
+//    product L_kk^-1 A_ik^T on the matrix cores, and after a barrier updates
+//    its tiles A_il -= L_ik L_lk^T (l <= i) with the L_ik still in its
+//    registers (the accumulator layout of v_mfma_f64_16x16x4f64 is the
+//    transpose of its A operand layout, so L_kk^-1 A_ik^T comes out as L_ik
+//    in A operand form);
+//  - wavefront 0 owns the next block row, so it updates the next diagonal
+//    tile first and factorises it while the other wavefronts finish the
+//    trailing update: the chain of pivots, the only sequential part, runs
+//    behind the matrix-core work.  Two barriers per panel.
+// Every entry of L goes to A from registers as it is formed; the diagonal
+// tile's inverse goes, transposed, into its strict upper triangle.  MFMA
+// operands: A operand lane holds row lane%16, k = lane/16; B operand k =
+// lane/16, column lane%16; result register r row lane/16 + 4 r, column
+// lane%16.
 constexpr int kCholSmallThreads = 512;
-constexpr int kCholSmallWaves = kCholSmallThreads / 64;
+constexpr int kInvLd = kPB + 1;   // row pitch of the diagonal-tile inverse in LDS
 
-// Factor of an n x n matrix (n <= kSmallN) in one workgroup, padded in LDS
-// to a multiple of 16 with identity rows.  A's lower triangle receives L and,
-// on success, the strict upper triangle of each 16 x 16 diagonal block the
-// transpose of that block's inverse (A[b][a] = (L_bb^-1)[a][b], a > b), which
-// the reduced solve applies as small dense products.
-template <int kR>
-__global__ __launch_bounds__(kCholSmallThreads) void k_chol_small(const double* src, double* A,
-                                                                   int n, int* info) {
+// LDS of k_chol_small: the padded matrix and two diagonal-tile inverses
+__host__ __device__ inline int chol_small_lds_bytes(int n) {
+  const int np = (n + kPB - 1) / kPB * kPB;
+  return 8 * (np * (np + 1) + 2 * kPB * kInvLd);
+}
+
+// LDL^T of one 16 x 16 symmetric tile by one wavefront, in the square-root-free
+// column form A = W D^-1 W^T: lanes 0..15 hold the tile's rows (x[q] =
+// A[lane][q]), lanes 16..31 rows of the identity, and each column p is
+// eliminated from the later ones in every row, x[q] -= x[p] w_qp / d_p, the
+// multiplier w_qp / d_p formed in lane q and broadcast by readlane.  At the
+// end lane r < 16 holds row r of W and lane 16 + r row r of W^-T D (the same
+// column operations applied to the identity).  The pivot chain holds only
+// what the next pivot needs: d_p+1 = a_p+1,p+1 - w_p+1,p^2 / d_p from the
+// reciprocal estimate r0 of d_p and its error e = 1 - d_p r0, 1/d_p =
+// r0 (1 + e + e^2 + e^3 + ...) (the estimate is good to about 2^-23, so
+// three terms leave less than 2^-60).  Lane p of dpv receives d_p, rs[p]
+// d_p^-1/2 (every lane).
+__device__ __forceinline__ void chol_tile16(double (&x)[kPB], double& dpv, double (&rs)[kPB], int lane) {
+  double d = readlane_d(x[0], 0);
+#pragma unroll
+  for (int p = 0; p < kPB; ++p) {
+    dpv = lane == p ? d : dpv;
+    const double r0 = __builtin_amdgcn_rcp(d);
+    const double e = fma(-d, r0, 1.0);
+    const double t = fma(e, fma(e, e, e), e);
+    rs[p] = rsqrt_nr(d);
+    const double m = x[p] * fma(r0, t, r0);
+    if (p + 1 < kPB) {
+      const double a = x[p] * x[p] * r0;
+      d = readlane_d(fma(-a, t, x[p + 1] - a), p + 1);
+    }
+#pragma unroll
+    for (int q = p + 1; q < kPB; ++q) x[q] = fma(-x[p], readlane_d(m, q), x[q]);
+  }
+}
+
+// Pivot test, outputs of a factorised diagonal tile at jb: lane r < 16 writes
+// L[jb + r][jb + p] = W[r][p] d_p^-1/2 (p <= r), lane 16 + r the inverse's
+// transpose A[jb + r][jb + p] = (L^-1)[p][r] = d_p^-1/2 (W^-T D)[r][p]
+// (p > r) and column r of L^-1 into inv.  Returns the 1-based first column
+// whose pivot is not positive (then nothing is written), else 0.
+__device__ __forceinline__ int chol_tile16_out(const double (&x)[kPB], double dpv, const double (&rs)[kPB],
+                                               double* A, int n, int jb, double* inv, int lane) {
+  const unsigned long long badl = __ballot(lane < kPB && !(dpv > 0.0 && isfinite(dpv)));
+  if (badl) return jb + __ffsll((long long)badl);
+  const int r = lane & 15, row = jb + r;
+  if (lane < 2 * kPB && row < n) {
+    const double diag = dpv * rsqrt_nr(dpv);
+    double* a = A + (long long)row * n + jb;
+#pragma unroll
+    for (int p = 0; p < kPB; ++p) {
+      const double v = p == r ? diag : x[p] * rs[p];
+      if (jb + p < n && (lane < kPB ? p <= r : p > r)) a[p] = v;
+    }
+  }
+  if (lane >= kPB && lane < 2 * kPB) {
+#pragma unroll
+    for (int p = 0; p < kPB; ++p) inv[p * kInvLd + r] = x[p] * rs[p];
+  }
+  return 0;
+}
+
+__global__ __launch_bounds__(kCholSmallThreads) void k_chol_small(const double* src, double* A, int n,
+                                                                   int* info) {
   extern __shared__ double sa[];
   __shared__ int sflag;
-  const int np = (n + kPB - 1) / kPB * kPB;
-  const int ld = np + 1, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  copy2d_overlapped(sa, ld, src, n, n, n, threadIdx.x, kCholSmallThreads);
-  pad_identity(sa, ld, n, np, threadIdx.x, kCholSmallThreads);
-  __syncthreads();
-  const int r = chol_blocked_lds<kCholSmallWaves, kR>(sa, np, ld, &sflag);
-  for (int i = wv; i < n; i += kCholSmallWaves) {
-    const int l1 = r == 0 ? min(n, (i / kPB + 1) * kPB) : i + 1;
-    for (int l = lane; l < l1; l += 64) A[(long long)i * n + l] = sa[i * ld + l];
+  const int np = (n + kPB - 1) / kPB * kPB, nb = np / kPB;
+  const int ld = np + 1, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int lm = lane & 15, lk = lane >> 4;
+  double* inv = sa + np * ld;   // [2][kPB][kInvLd], by panel parity
+  double x[kPB], dpv = 0.0, rs[kPB];
+  if (tid == 0) sflag = 0;
+  if (wv == 0) {
+    // panel 0's diagonal tile straight from global memory
+#pragma unroll
+    for (int q = 0; q < kPB; ++q) {
+      const bool real = lane < n && q < n;
+      x[q] = lane < kPB && real ? src[(long long)lane * n + q] : (lane == q || lane == q + kPB ? 1.0 : 0.0);
+    }
+  } else {
+    // the other wavefronts stage the lower block triangle below tile row 0:
+    // tile tau of block row bi >= 1, block column bl <= bi, in row-major order
+    const int ntile = (nb - 1) * (nb + 2) / 2, total = ntile * kPB * kPB;
+    const int start = tid - 64, stride = kCholSmallThreads - 64;
+    for (int t0 = start; t0 < total; t0 += kStageBatch * stride) {
+      double v[kStageBatch];
+      int o[kStageBatch];
+#pragma unroll
+      for (int u = 0; u < kStageBatch; ++u) {
+        const int t = t0 + u * stride;
+        o[u] = -1;
+        if (t < total) {
+          int tau = t / (kPB * kPB), bi = 1;
+          while (tau >= bi + 1) tau -= ++bi;
+          const int e = t % (kPB * kPB);
+          const int i = kPB * bi + e / kPB, c = kPB * tau + e % kPB;
+          v[u] = i < n && c < n ? src[(long long)i * n + c] : (i == c ? 1.0 : 0.0);
+          o[u] = i * ld + c;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kStageBatch; ++u)
+        if (o[u] >= 0) sa[o[u]] = v[u];
+    }
   }
-  if (threadIdx.x == 0) *info = r;
+  if (wv == 0) {
+    chol_tile16(x, dpv, rs, lane);
+    const int bad = chol_tile16_out(x, dpv, rs, A, n, 0, inv, lane);
+    if (bad && lane == 0) sflag = bad;
+  }
+  __syncthreads();
+  for (int k = 0; k + 1 < nb && sflag == 0; ++k) {
+    const int jb = kPB * k;
+    const double* iv = inv + (k & 1) * kPB * kInvLd;
+    // block row owned by this wavefront: k + 1 for wavefront 0, k + 1 + wv
+    // for the others (nb <= 8 leaves the last wavefront idle)
+    const int i = k + 1 + wv;
+    const bool own = i < nb;
+    v4d li = {0.0, 0.0, 0.0, 0.0};
+    if (own) {
+      const int i0 = kPB * i;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const double m1 = iv[lm * kInvLd + 4 * j + lk];
+        const double b = sa[(i0 + lm) * ld + jb + 4 * j + lk];
+        li = __builtin_amdgcn_mfma_f64_16x16x4f64(m1, b, li, 0, 0, 0);
+      }
+      // register r: L[i0 + lm][jb + lk + 4 r]
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        sa[(i0 + lm) * ld + jb + lk + 4 * r] = li[r];
+        if (i0 + lm < n && jb + lk + 4 * r < n) A[(long long)(i0 + lm) * n + jb + lk + 4 * r] = li[r];
+      }
+    }
+    __syncthreads();
+    if (own) {
+      const int i0 = kPB * i;
+      // wavefront 0 has only the diagonal tile (k+1, k+1); the others go
+      // from their diagonal tile leftwards
+      for (int l = i; l > k; --l) {
+        const int l0 = kPB * l;
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const double b = sa[(l0 + lm) * ld + jb + 4 * j + lk];
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(li[j], b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sa[(i0 + lk + 4 * r) * ld + l0 + lm] -= acc[r];
+      }
+    }
+    if (wv == 0) {
+      wave_sync();
+      const int j1 = jb + kPB;
+#pragma unroll
+      for (int q = 0; q < kPB; ++q)
+        x[q] = lane < kPB ? sa[(j1 + lane) * ld + j1 + q] : (lane == q + kPB ? 1.0 : 0.0);
+      chol_tile16(x, dpv, rs, lane);
+      const int bad = chol_tile16_out(x, dpv, rs, A, n, j1, inv + ((k + 1) & 1) * kPB * kInvLd, lane);
+      if (bad && lane == 0) sflag = bad;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) *info = sflag;
 }
 
 // blocked: factor the 64 x 64 diagonal block at jb
@@ -729,14 +892,9 @@ static hipError_t allow_lds(const void* fn, int* cur, int need) {
 }
 
 hipError_t configure_dense_kernels(const DP& d) {
-  static int c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0;
+  static int c1 = 0, c2 = 0, c3 = 0, c5 = 0;
   hipError_t e = hipSuccess;
-  if (d.nu <= kSmallN) {
-    const void* f = d.nu <= 64 ? (const void*)k_chol_small<1> : (const void*)k_chol_small<2>;
-    int* cur = d.nu <= 64 ? &c1 : &c4;
-    const int np = (d.nu + kPB - 1) / kPB * kPB;
-    e = allow_lds(f, cur, 8 * np * (np + 1));
-  }
+  if (d.nu <= kSmallN) e = allow_lds((const void*)k_chol_small, &c1, chol_small_lds_bytes(d.nu));
   if (e == hipSuccess && d.nu <= kSmallN)
     e = allow_lds((const void*)k_reduced_solve_blk, &c5, (int)rsolve_blk_lds_bytes(d.nu));
   if (e == hipSuccess && d.nu > kSmallN) {
@@ -783,10 +941,7 @@ void launch_stacked_product(const DP& d, hipStream_t s) {
 void launch_cholesky_from(const DP& d, const double* src, double* a, int* info, hipStream_t s) {
   const int n = d.nu;
   if (n <= kSmallN) {
-    const int np = (n + kPB - 1) / kPB * kPB;
-    const size_t lds = 8 * (size_t)np * (np + 1);
-    if (n <= 64) k_chol_small<1><<<1, kCholSmallThreads, lds, s>>>(src, a, n, info);
-    else k_chol_small<2><<<1, kCholSmallThreads, lds, s>>>(src, a, n, info);
+    k_chol_small<<<1, kCholSmallThreads, (size_t)chol_small_lds_bytes(n), s>>>(src, a, n, info);
     return;
   }
   if (src != a) launch_copy(src, a, (long long)n * n, s);

@@ -2,6 +2,8 @@
 // paper's MPI all-reduce of K_hat, here a fixed-order on-device sum), the
 // Cholesky factorisation of K_hat (the paper factorises it densely with
 // LAPACK on the GPU) and the two triangular solves for p_u.
+#include <utility>
+
 #include "device.h"
 
 namespace rkkt {
@@ -378,75 +380,122 @@ __device__ int chol_blocked_lds(double* sa, int n, int ld, int* sflag) {
 //    tile first and factorises it while the other wavefronts finish the
 //    trailing update: the chain of pivots, the only sequential part, runs
 //    behind the matrix-core work.  Two barriers per panel.
-// Every entry of L goes to A from registers as it is formed; the diagonal
-// tile's inverse goes, transposed, into its strict upper triangle.  MFMA
+// The factorised diagonal tile is staged raw in LDS (rows of W and of
+// W^-T D, d_p^-1/2); the block-row owners scale what they read, and the idle
+// last wavefront writes the tile's part of A (L and, transposed in its strict
+// upper triangle, L_kk^-1) while the others go on.  L_ik goes to A from
+// registers as it is formed.  MFMA
 // operands: A operand lane holds row lane%16, k = lane/16; B operand k =
 // lane/16, column lane%16; result register r row lane/16 + 4 r, column
 // lane%16.
 constexpr int kCholSmallThreads = 512;
-constexpr int kInvLd = kPB + 1;   // row pitch of the diagonal-tile inverse in LDS
+constexpr int kOutWave = kCholSmallThreads / 64 - 1;   // writes the diagonal tiles
+// a factorised diagonal tile in LDS: W rows, W^-T D rows (pitch kTileLd),
+// d_p^-1/2, d_p; two of them, by panel parity
+constexpr int kTileLd = kPB + 1;
+constexpr int kRawW = 0, kRawE = kPB * kTileLd, kRawRs = 2 * kPB * kTileLd, kRawD = kRawRs + kPB;
+constexpr int kRawSize = kRawD + kPB;
 
-// LDS of k_chol_small: the padded matrix and two diagonal-tile inverses
+// LDS of k_chol_small: the padded matrix and two staged diagonal tiles
 __host__ __device__ inline int chol_small_lds_bytes(int n) {
   const int np = (n + kPB - 1) / kPB * kPB;
-  return 8 * (np * (np + 1) + 2 * kPB * kInvLd);
+  return 8 * (np * (np + 1) + 2 * kRawSize);
 }
 
-// LDL^T of one 16 x 16 symmetric tile by one wavefront, in the square-root-free
-// column form A = W D^-1 W^T: lanes 0..15 hold the tile's rows (x[q] =
-// A[lane][q]), lanes 16..31 rows of the identity, and each column p is
-// eliminated from the later ones in every row, x[q] -= x[p] w_qp / d_p, the
-// multiplier w_qp / d_p formed in lane q and broadcast by readlane.  At the
-// end lane r < 16 holds row r of W and lane 16 + r row r of W^-T D (the same
-// column operations applied to the identity).  The pivot chain holds only
-// what the next pivot needs: d_p+1 = a_p+1,p+1 - w_p+1,p^2 / d_p from the
-// reciprocal estimate r0 of d_p and its error e = 1 - d_p r0, 1/d_p =
-// r0 (1 + e + e^2 + e^3 + ...) (the estimate is good to about 2^-23, so
-// three terms leave less than 2^-60).  Lane p of dpv receives d_p, rs[p]
-// d_p^-1/2 (every lane).
-__device__ __forceinline__ void chol_tile16(double (&x)[kPB], double& dpv, double (&rs)[kPB], int lane) {
-  double d = readlane_d(x[0], 0);
-#pragma unroll
-  for (int p = 0; p < kPB; ++p) {
-    dpv = lane == p ? d : dpv;
-    const double r0 = __builtin_amdgcn_rcp(d);
-    const double e = fma(-d, r0, 1.0);
-    const double t = fma(e, fma(e, e, e), e);
-    rs[p] = rsqrt_nr(d);
-    const double m = x[p] * fma(r0, t, r0);
-    if (p + 1 < kPB) {
-      const double a = x[p] * x[p] * r0;
-      d = readlane_d(fma(-a, t, x[p + 1] - a), p + 1);
+// value of v in lane Q of the caller's row of 16 lanes (DPP row_newbcast)
+template <int Q>
+__device__ __forceinline__ double row_bcast(double v) {
+  return __builtin_amdgcn_mov_dpp(v, 0x150 + Q, 0xf, 0xf, false);
+}
+
+// LDL^T of one 16 x 16 symmetric tile by lanes 0..15 of one wavefront, in the
+// square-root-free column form A = W D^-1 W^T: lane r holds row r of the tile
+// (x[q] = A[r][q]) and row r of the identity (y), and each column p is
+// eliminated from the later ones, x[q] -= x[p] w_qp / d_p (y alike), the
+// multiplier w_qp / d_p formed in lane q and broadcast along the row of lanes.
+// At the end lane r holds row r of W in x and row r of W^-T D in y.  The
+// pivot chain holds only what the next pivot needs: d_p+1 = a_p+1,p+1 -
+// w_p+1,p^2 / d_p from the reciprocal estimate r0 of d_p and its error
+// e = 1 - d_p r0, 1/d_p = r0 (1 + e + e^2 + e^3 + ...) (the estimate is good
+// to about 2^-24, so three terms leave less than 2^-90).  Lane p of dpv
+// receives d_p.
+// updates x[q], y[q] for kLo <= q < kHi by column P with multipliers m
+template <int P, int kLo, int kHi, int... Q>
+__device__ __forceinline__ void tile_eliminate(double (&x)[kPB], double (&y)[kPB], double m,
+                                               std::integer_sequence<int, Q...>) {
+  const double nx = -x[P], ny = -y[P];
+  auto one = [&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    if constexpr (q > P && q >= kLo && q < kHi) {
+      const double mq = row_bcast<q>(m);
+      x[q] = fma(mq, nx, x[q]);
+      y[q] = fma(mq, ny, y[q]);
+      // y is read only at the end: pin its update here so that it is not
+      // sunk there, which would keep every broadcast multiplier alive
+      asm volatile("" : "+v"(y[q]));
     }
-#pragma unroll
-    for (int q = p + 1; q < kPB; ++q) x[q] = fma(-x[p], readlane_d(m, q), x[q]);
-  }
+  };
+  (one(std::integral_constant<int, Q>{}), ...);
 }
 
-// Pivot test, outputs of a factorised diagonal tile at jb: lane r < 16 writes
-// L[jb + r][jb + p] = W[r][p] d_p^-1/2 (p <= r), lane 16 + r the inverse's
-// transpose A[jb + r][jb + p] = (L^-1)[p][r] = d_p^-1/2 (W^-T D)[r][p]
-// (p > r) and column r of L^-1 into inv.  Returns the 1-based first column
-// whose pivot is not positive (then nothing is written), else 0.
-__device__ __forceinline__ int chol_tile16_out(const double (&x)[kPB], double dpv, const double (&rs)[kPB],
-                                               double* A, int n, int jb, double* inv, int lane) {
+// Step P in one scheduling region with the rest of step P - 1: its pivot
+// chain first, then the rest (the tail) of step P - 1, then its own first two
+// columns (the head, all the next step's chain needs); no instruction moves
+// across regions, which keeps the broadcasts from being hoisted into a
+// register pile-up.
+template <int P>
+__device__ __forceinline__ void tile_chain(double (&x)[kPB], double (&y)[kPB], double d, double mprev,
+                                           double& dpv, int lane) {
+  constexpr auto all = std::make_integer_sequence<int, kPB>{};
+  dpv = lane == P ? d : dpv;
+  const double r0 = __builtin_amdgcn_rcp(d);
+  const double e = fma(-d, r0, 1.0);
+  const double t = fma(e, fma(e, e, e), e);
+  const double m = x[P] * fma(r0, t, r0);
+  double dn = 0.0;
+  if constexpr (P + 1 < kPB) {
+    const double a = x[P] * x[P] * r0;
+    dn = row_bcast<P + 1>(fma(-a, t, x[P + 1] - a));
+  }
+  if constexpr (P > 0) tile_eliminate<P - 1, P + 2, kPB>(x, y, mprev, all);
+  tile_eliminate<P, P + 1, P + 3>(x, y, m, all);
+  __builtin_amdgcn_sched_barrier(0);
+  if constexpr (P + 1 < kPB) tile_chain<P + 1>(x, y, dn, m, dpv, lane);
+}
+
+// Pivot test of a factorised diagonal tile at jb, then lane r < 16 stages row
+// r of W and of W^-T D, d_r^-1/2 and d_r in raw.  Returns the 1-based first
+// column whose pivot is not positive (then nothing is staged), else 0.
+__device__ __forceinline__ int chol_tile16_stage(const double (&x)[kPB], const double (&y)[kPB], double dpv,
+                                                 int jb, double* raw, int lane) {
   const unsigned long long badl = __ballot(lane < kPB && !(dpv > 0.0 && isfinite(dpv)));
   if (badl) return jb + __ffsll((long long)badl);
-  const int r = lane & 15, row = jb + r;
-  if (lane < 2 * kPB && row < n) {
-    const double diag = dpv * rsqrt_nr(dpv);
-    double* a = A + (long long)row * n + jb;
+  if (lane < kPB) {
 #pragma unroll
-    for (int p = 0; p < kPB; ++p) {
-      const double v = p == r ? diag : x[p] * rs[p];
-      if (jb + p < n && (lane < kPB ? p <= r : p > r)) a[p] = v;
+    for (int q = 0; q < kPB; ++q) {
+      raw[kRawW + lane * kTileLd + q] = x[q];
+      raw[kRawE + lane * kTileLd + q] = y[q];
     }
-  }
-  if (lane >= kPB && lane < 2 * kPB) {
-#pragma unroll
-    for (int p = 0; p < kPB; ++p) inv[p * kInvLd + r] = x[p] * rs[p];
+    raw[kRawRs + lane] = rsqrt_nr(dpv);
+    raw[kRawD + lane] = dpv;
   }
   return 0;
+}
+
+// A's part of the staged diagonal tile at jb, by one wavefront: row jb + r,
+// L[jb + r][jb + p] = W[r][p] d_p^-1/2 (p <= r) and, in the strict upper
+// part, the inverse's transpose (L^-1)[p][r] = d_p^-1/2 (W^-T D)[r][p].
+__device__ __forceinline__ void chol_tile16_write(const double* raw, double* A, int n, int jb, int lane) {
+#pragma unroll
+  for (int u = 0; u < kPB * kPB / 64; ++u) {
+    const int t = lane + 64 * u, r = t / kPB, p = t % kPB;
+    if (jb + r < n && jb + p < n) {
+      const double rs = raw[kRawRs + p];
+      const double v = p < r ? raw[kRawW + r * kTileLd + p] * rs
+                             : (p == r ? raw[kRawD + p] * rs : raw[kRawE + r * kTileLd + p] * rs);
+      A[(long long)(jb + r) * n + jb + p] = v;
+    }
+  }
 }
 
 __global__ __launch_bounds__(kCholSmallThreads) void k_chol_small(const double* src, double* A, int n,
@@ -456,15 +505,15 @@ __global__ __launch_bounds__(kCholSmallThreads) void k_chol_small(const double* 
   const int np = (n + kPB - 1) / kPB * kPB, nb = np / kPB;
   const int ld = np + 1, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int lm = lane & 15, lk = lane >> 4;
-  double* inv = sa + np * ld;   // [2][kPB][kInvLd], by panel parity
-  double x[kPB], dpv = 0.0, rs[kPB];
+  double* raw = sa + np * ld;   // two staged diagonal tiles, by panel parity
+  double x[kPB], y[kPB], dpv = 0.0;
   if (tid == 0) sflag = 0;
   if (wv == 0) {
     // panel 0's diagonal tile straight from global memory
 #pragma unroll
     for (int q = 0; q < kPB; ++q) {
-      const bool real = lane < n && q < n;
-      x[q] = lane < kPB && real ? src[(long long)lane * n + q] : (lane == q || lane == q + kPB ? 1.0 : 0.0);
+      x[q] = lane < n && q < n ? src[(long long)lane * n + q] : (lane == q ? 1.0 : 0.0);
+      y[q] = lane == q ? 1.0 : 0.0;
     }
   } else {
     // the other wavefronts stage the lower block triangle below tile row 0:
@@ -493,14 +542,15 @@ __global__ __launch_bounds__(kCholSmallThreads) void k_chol_small(const double* 
     }
   }
   if (wv == 0) {
-    chol_tile16(x, dpv, rs, lane);
-    const int bad = chol_tile16_out(x, dpv, rs, A, n, 0, inv, lane);
+    tile_chain<0>(x, y, row_bcast<0>(x[0]), 0.0, dpv, lane);
+    const int bad = chol_tile16_stage(x, y, dpv, 0, raw, lane);
     if (bad && lane == 0) sflag = bad;
   }
   __syncthreads();
   for (int k = 0; k + 1 < nb && sflag == 0; ++k) {
     const int jb = kPB * k;
-    const double* iv = inv + (k & 1) * kPB * kInvLd;
+    const double* rk = raw + (k & 1) * kRawSize;
+    if (wv == kOutWave) chol_tile16_write(rk, A, n, jb, lane);
     // block row owned by this wavefront: k + 1 for wavefront 0, k + 1 + wv
     // for the others (nb <= 8 leaves the last wavefront idle)
     const int i = k + 1 + wv;
@@ -508,9 +558,11 @@ __global__ __launch_bounds__(kCholSmallThreads) void k_chol_small(const double* 
     v4d li = {0.0, 0.0, 0.0, 0.0};
     if (own) {
       const int i0 = kPB * i;
+      // (L_kk^-1)[lm][c] = d_lm^-1/2 (W^-T D)[c][lm]
+      const double rsl = rk[kRawRs + lm];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const double m1 = iv[lm * kInvLd + 4 * j + lk];
+        const double m1 = rsl * rk[kRawE + (4 * j + lk) * kTileLd + lm];
         const double b = sa[(i0 + lm) * ld + jb + 4 * j + lk];
         li = __builtin_amdgcn_mfma_f64_16x16x4f64(m1, b, li, 0, 0, 0);
       }
@@ -542,14 +594,17 @@ __global__ __launch_bounds__(kCholSmallThreads) void k_chol_small(const double* 
       wave_sync();
       const int j1 = jb + kPB;
 #pragma unroll
-      for (int q = 0; q < kPB; ++q)
-        x[q] = lane < kPB ? sa[(j1 + lane) * ld + j1 + q] : (lane == q + kPB ? 1.0 : 0.0);
-      chol_tile16(x, dpv, rs, lane);
-      const int bad = chol_tile16_out(x, dpv, rs, A, n, j1, inv + ((k + 1) & 1) * kPB * kInvLd, lane);
+      for (int q = 0; q < kPB; ++q) {
+        x[q] = lane < kPB ? sa[(j1 + lane) * ld + j1 + q] : 0.0;
+        y[q] = lane == q ? 1.0 : 0.0;
+      }
+      tile_chain<0>(x, y, row_bcast<0>(x[0]), 0.0, dpv, lane);
+      const int bad = chol_tile16_stage(x, y, dpv, j1, raw + ((k + 1) & 1) * kRawSize, lane);
       if (bad && lane == 0) sflag = bad;
     }
     __syncthreads();
   }
+  if (sflag == 0 && wv == kOutWave) chol_tile16_write(raw + ((nb - 1) & 1) * kRawSize, A, n, kPB * (nb - 1), lane);
   if (tid == 0) *info = sflag;
 }
 

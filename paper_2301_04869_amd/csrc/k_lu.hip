@@ -176,21 +176,36 @@ __device__ __forceinline__ void sweep(const int* __restrict__ ptr, const void* e
 // phase per row.  Coefficient of (chain row a, chain row b): lu[pos(a, b)];
 // the transposed solves read lu[pos(b, a)].
 
+// Positions of the chain coefficients of row a = lane: pos(a, b), or pos(b, a)
+// for the transposed solves; -1 where there is none and past the chain.
+// Loaded ahead of the solve, so their global round trip overlaps other work.
+struct ChainPos {
+  int p[kChainMax];
+};
+
+template <bool kTrans>
+__device__ __forceinline__ ChainPos chain_positions(const DP& d, int lane) {
+  ChainPos c;
+  const int t = d.chain_t;
+  const int* __restrict__ P = d.chain_pos;
+  const bool own = lane < t;
+#pragma unroll
+  for (int b = 0; b < kChainMax; ++b) c.p[b] = own && b < t ? (kTrans ? P[b * t + lane] : P[lane * t + b]) : -1;
+  return c;
+}
+
 // One column, lanes 0 .. t-1 of the calling wavefront hold chain rows a;
 // x_b is broadcast with readlane.  Up: b increasing, rows a > b update;
 // down: b decreasing, rows a < b update.
-template <bool kUp, bool kTrans>
-__device__ __forceinline__ void chain_solve1(const DP& d, const double* lu, double* X, int lane) {
+template <bool kUp>
+__device__ __forceinline__ void chain_solve1(const DP& d, const double* lu, const ChainPos& cp, double* X,
+                                             int lane) {
   const int t = d.chain_t, c0 = d.chain_c0;
-  const int* __restrict__ P = d.chain_pos;
   const bool own = lane < t;
   double x = own ? X[c0 + lane] : 0.0;
   double coef[kChainMax];
 #pragma unroll
-  for (int b = 0; b < kChainMax; ++b) {
-    const int pp = own && b < t ? (kTrans ? P[b * t + lane] : P[lane * t + b]) : -1;
-    coef[b] = pp >= 0 ? lu[pp] : 0.0;
-  }
+  for (int b = 0; b < kChainMax; ++b) coef[b] = cp.p[b] >= 0 ? lu[cp.p[b]] : 0.0;
   if (kUp) {
 #pragma unroll
     for (int b = 0; b < kChainMax; ++b)
@@ -943,15 +958,17 @@ __device__ __forceinline__ StepView step_view(const DP& d, int k, double* smem, 
   return w;
 }
 
-// X <- G_x^-1 X (internal order) by the sweep group (G threads, slot gl)
+// X <- G_x^-1 X (internal order) by the sweep group (G threads, slot gl);
+// cp: chain_positions<false> of slot gl
 template <bool kLDS, typename Sync>
-__device__ __forceinline__ void solve_fwd(const DP& d, const StepView& w, double* X, int gl, Sync sync) {
+__device__ __forceinline__ void solve_fwd(const DP& d, const StepView& w, double* X, int gl, Sync sync,
+                                          const ChainPos& cp) {
   constexpr int G = kLDS ? kGroupLds : kRT;
   sweep<kLDS, false>(w.uptr, w.uent, d.nph_u, G, gl, true, w.lu, X, 1, 0, sync);
   if (d.chain_t > 0) {
-    if (gl < 64) chain_solve1<true, false>(d, w.lu, X, gl);
+    if (gl < 64) chain_solve1<true>(d, w.lu, cp, X, gl);
     sync();
-    if (gl < 64) chain_solve1<false, false>(d, w.lu, X, gl);
+    if (gl < 64) chain_solve1<false>(d, w.lu, cp, X, gl);
     sync();
   }
   sweep<kLDS, false>(w.dptr, w.dent, d.nph_d, G, gl, true, w.lu, X, 1, 0, sync);
@@ -959,19 +976,30 @@ __device__ __forceinline__ void solve_fwd(const DP& d, const StepView& w, double
   sync();
 }
 
-// X <- G_x^-T X for X already scaled by 1/u_ii
 template <bool kLDS, typename Sync>
-__device__ __forceinline__ void solve_adj_scaled(const DP& d, const StepView& w, double* X, int gl, Sync sync) {
+__device__ __forceinline__ void solve_fwd(const DP& d, const StepView& w, double* X, int gl, Sync sync) {
+  solve_fwd<kLDS>(d, w, X, gl, sync, chain_positions<false>(d, gl));
+}
+
+// X <- G_x^-T X for X already scaled by 1/u_ii; cp: chain_positions<true>
+template <bool kLDS, typename Sync>
+__device__ __forceinline__ void solve_adj_scaled(const DP& d, const StepView& w, double* X, int gl, Sync sync,
+                                                 const ChainPos& cp) {
   constexpr int G = kLDS ? kGroupLds : kRT;
   sweep<kLDS, true>(w.uptr, w.uent, d.nph_u, G, gl, true, w.lu, X, 1, 0, sync);
   if (d.chain_t > 0) {
-    if (gl < 64) chain_solve1<true, true>(d, w.lu, X, gl);
+    if (gl < 64) chain_solve1<true>(d, w.lu, cp, X, gl);
     sync();
-    if (gl < 64) chain_solve1<false, true>(d, w.lu, X, gl);
+    if (gl < 64) chain_solve1<false>(d, w.lu, cp, X, gl);
     sync();
   }
   sweep<kLDS, true>(w.dptr, w.dent, d.nph_d, G, gl, true, w.lu, X, 1, 0, sync);
   sync();
+}
+
+template <bool kLDS, typename Sync>
+__device__ __forceinline__ void solve_adj_scaled(const DP& d, const StepView& w, double* X, int gl, Sync sync) {
+  solve_adj_scaled<kLDS>(d, w, X, gl, sync, chain_positions<true>(d, gl));
 }
 
 // runs a sweep-group solve: wavefront 0 in LDS mode, every thread otherwise
@@ -1103,7 +1131,10 @@ __device__ __forceinline__ StepView sweep_view(const DP& d, double* lu, unsigned
 }
 
 // out[c] = sum_i Z[i][c] b[i] for c < nu; kT threads as row slices x columns,
-// partial sums through red[kT + nu] (LDS), one barrier inside
+// partial sums through red[kT + nu] (LDS), one barrier inside.  Each thread
+// keeps kTtRows loads of its column in flight.
+constexpr int kTtRows = 8;
+
 template <int kT>
 __device__ __forceinline__ void dense_tt_times(const DP& d, const double* __restrict__ Zk,
                                                const double* b, double* red) {
@@ -1113,14 +1144,26 @@ __device__ __forceinline__ void dense_tt_times(const DP& d, const double* __rest
   const int s = wide ? 0 : tid / nu;
   if (s < ns) {
     for (int c = wide ? tid : tid - s * nu; c < nu; c += wide ? kT : nu) {
-      double a0 = 0.0, a1 = 0.0;
-      int i = s;
-      for (; i + ns < nx; i += 2 * ns) {
-        a0 = fma(Zk[(long long)i * ld + c], b[i], a0);
-        a1 = fma(Zk[(long long)(i + ns) * ld + c], b[i + ns], a1);
+      double a[kTtRows];
+#pragma unroll
+      for (int u = 0; u < kTtRows; ++u) a[u] = 0.0;
+      for (int i0 = s; i0 < nx; i0 += kTtRows * ns) {
+        double z[kTtRows];
+#pragma unroll
+        for (int u = 0; u < kTtRows; ++u) {
+          const int i = i0 + u * ns;
+          z[u] = i < nx ? Zk[(long long)i * ld + c] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kTtRows; ++u) {
+          const int i = i0 + u * ns;
+          if (i < nx) a[u] = fma(z[u], b[i], a[u]);
+        }
       }
-      if (i < nx) a0 = fma(Zk[(long long)i * ld + c], b[i], a0);
-      red[s * nu + c] = a0 + a1;
+      double acc = 0.0;
+#pragma unroll
+      for (int u = 0; u < kTtRows; ++u) acc += a[u];
+      red[s * nu + c] = acc;
     }
   }
   __syncthreads();
@@ -1139,13 +1182,14 @@ __global__ __launch_bounds__(kT) void k_step_rhs2(DP d, const double* r1x, const
   double* part = b + nx;
   double* red = part + nu;
   unsigned* ue = reinterpret_cast<unsigned*>(red + kT + nu);
+  const ChainPos cp = chain_positions<false>(d, tid);
   stage_copy(lu, lu_of(d, k), nf + nx, tid, kT);
   stage_words(ue, d.blob_stp, d.blob_stp_words, tid, kT);
   const double* r3k = r3 + (long long)k * nx;
   for (int i = tid; i < nx; i += kT) q[i] = r3k[d.perm[i]];
   __syncthreads();
   if (tid < 64) {
-    solve_fwd<true>(d, sweep_view(d, lu, ue), q, tid, [] { wave_sync(); });
+    solve_fwd<true>(d, sweep_view(d, lu, ue), q, tid, [] { wave_sync(); }, cp);
   } else {
     // rhat1 = r1x + H_x^T w and H_u^T w, with w = Sigma_s r4 - r2 formed per use
     const double* hv = d.EV + (long long)k * d.n_ev + d.off_h;
@@ -1193,6 +1237,10 @@ __global__ __launch_bounds__(kT) void k_step_rhs2(DP d, const double* r1x, const
   }
 }
 
+constexpr int kPxRows = 4;     // rows of T per 16-lane group in flight
+constexpr int kPxChunks = 8;   // 16-column chunks of a row per pass
+constexpr int kKxPre = 16;     // entries of a K_x row loaded ahead
+
 template <int kT>
 __global__ __launch_bounds__(kT) void k_step_recover2(DP d, const double* r2, const double* r3,
                                                       const double* r4, const double* ss,
@@ -1206,45 +1254,94 @@ __global__ __launch_bounds__(kT) void k_step_recover2(DP d, const double* r2, co
   double* yv = xv + nx;
   double* spu = yv + nx;
   unsigned* ue = reinterpret_cast<unsigned*>(spu + nu + kT + nu);
+  const double* Kk = d.K + (long long)k * d.nnz_k;
+  // loaded ahead: the chain positions of the adjoint solve and the extent of
+  // this thread's first K_x row
+  const ChainPos cp = chain_positions<true>(d, tid);
+  const int ke0 = tid < nx ? d.k_ptr[tid] : 0, ke1 = tid < nx ? d.k_ptr[tid + 1] : 0;
+  const double* grh1 = d.rhat1 + (long long)k * nx;
+  const double rh = tid < nx ? grh1[tid] : 0.0;
   stage_copy(lu, lu_of(d, k), nf + nx, tid, kT);
   stage_words(ue, d.blob_stp, d.blob_stp_words, tid, kT);
   for (int c = tid; c < nu; c += kT) spu[c] = pu[c];
   __syncthreads();
-  // p_x = -q + T p_u: 16-lane groups per row of T, columns across the group
+  // the first K_x row's columns and values, in flight during p_x
+  int kc[kKxPre];
+  double kv[kKxPre];
+#pragma unroll
+  for (int u = 0; u < kKxPre; ++u) {
+    const bool in = ke0 + u < ke1;
+    kc[u] = in ? d.k_col[ke0 + u] : 0;
+    kv[u] = in ? Kk[ke0 + u] : 0.0;
+  }
+  // p_x = -q + T p_u: 16-lane groups, kPxRows rows each (rows g + 16 r of the
+  // batch), columns across the group, all of a batch's loads issued first
   {
     const double* Zk = d.Zst + (long long)k * d.nz * d.nu_pad;
     const double* gq = d.qbuf + (long long)k * nx;
+    constexpr int kG = kT / 16;
     const int g = tid >> 4, l = tid & 15;
-    for (int i = g; i < nx; i += kT / 16) {
-      const double* zr = Zk + (long long)i * d.nu_pad;
-      double a0 = 0.0, a1 = 0.0;
-      int c = l;
-      for (; c + 16 < nu; c += 32) {
-        a0 = fma(zr[c], spu[c], a0);
-        a1 = fma(zr[c + 16], spu[c + 16], a1);
+    for (int i0 = g; i0 < nx; i0 += kPxRows * kG) {
+      double acc[kPxRows], qv[kPxRows];
+#pragma unroll
+      for (int r = 0; r < kPxRows; ++r) {
+        acc[r] = 0.0;
+        qv[r] = i0 + r * kG < nx ? gq[i0 + r * kG] : 0.0;
       }
-      if (c < nu) a0 = fma(zr[c], spu[c], a0);
-      double acc = a0 + a1;
-      acc += __shfl_xor(acc, 8, 16);
-      acc += __shfl_xor(acc, 4, 16);
-      acc += __shfl_xor(acc, 2, 16);
-      acc += __shfl_xor(acc, 1, 16);
-      if (l == 0) {
-        const double x = acc - gq[i];
-        xv[i] = x;
-        px[(long long)k * nx + d.perm[i]] = x;
+      for (int c0 = 0; c0 < nu; c0 += 16 * kPxChunks) {
+        double z[kPxRows][kPxChunks];
+#pragma unroll
+        for (int r = 0; r < kPxRows; ++r) {
+          const int i = i0 + r * kG;
+#pragma unroll
+          for (int t = 0; t < kPxChunks; ++t) {
+            const int c = c0 + l + 16 * t;
+            z[r][t] = i < nx && c < nu ? Zk[(long long)i * d.nu_pad + c] : 0.0;
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < kPxChunks; ++t) {
+          const int c = c0 + l + 16 * t;
+          const double p = c < nu ? spu[c] : 0.0;
+#pragma unroll
+          for (int r = 0; r < kPxRows; ++r) acc[r] = fma(z[r][t], p, acc[r]);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kPxRows; ++r) {
+        double a = acc[r];
+        a += __shfl_xor(a, 8, 16);
+        a += __shfl_xor(a, 4, 16);
+        a += __shfl_xor(a, 2, 16);
+        a += __shfl_xor(a, 1, 16);
+        const int i = i0 + r * kG;
+        if (l == 0 && i < nx) {
+          const double x = a - qv[r];
+          xv[i] = x;
+          px[(long long)k * nx + d.perm[i]] = x;
+        }
       }
     }
   }
   __syncthreads();
   // p_y = -G_x^-T (rhat1 + K_x. [p_x; p_u]), prescaled by 1/u_ii
-  const double* Kk = d.K + (long long)k * d.nnz_k;
-  const double* grh1 = d.rhat1 + (long long)k * nx;
   const double* invd = lu + nf;
   for (int i = tid; i < nx; i += kT) {
-    double acc = grh1[i];
-    const int e1 = d.k_ptr[i + 1];
-    for (int e = d.k_ptr[i]; e < e1; ++e) {
+    double acc;
+    int e, e1;
+    if (i == tid) {
+      acc = rh;
+#pragma unroll
+      for (int u = 0; u < kKxPre; ++u)
+        if (u < ke1 - ke0) acc = fma(kv[u], kc[u] < nx ? xv[kc[u]] : spu[kc[u] - nx], acc);
+      e = ke0 + kKxPre;
+      e1 = ke1;
+    } else {
+      acc = grh1[i];
+      e = d.k_ptr[i];
+      e1 = d.k_ptr[i + 1];
+    }
+    for (; e < e1; ++e) {
       const int cc = d.k_col[e];
       acc = fma(Kk[e], cc < nx ? xv[cc] : spu[cc - nx], acc);
     }
@@ -1252,7 +1349,7 @@ __global__ __launch_bounds__(kT) void k_step_recover2(DP d, const double* r2, co
   }
   __syncthreads();
   if (tid < 64) {
-    solve_adj_scaled<true>(d, sweep_view(d, lu, ue), yv, tid, [] { wave_sync(); });
+    solve_adj_scaled<true>(d, sweep_view(d, lu, ue), yv, tid, [] { wave_sync(); }, cp);
   } else {
     // p_s = -(r4 + H p_d), p_z = Sigma_s (H p_d + r4) - r2, beside the solve
     const double* hv = d.EV + (long long)k * d.n_ev + d.off_h;

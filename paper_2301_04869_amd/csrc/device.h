@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 #include "layout.h"
 #include "rkkt.h"
 
@@ -114,6 +116,12 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
+// value of v in lane Q of the caller's row of 16 lanes (DPP row_newbcast)
+template <int Q>
+__device__ __forceinline__ double row_bcast(double v) {
+  return __builtin_amdgcn_mov_dpp(v, 0x150 + Q, 0xf, 0xf, false);
+}
+
 // dst[i * ldd + j] = src[i * lds + j] for i < rows, j < cols, kStageBatch
 // loads in flight per thread (dst in LDS)
 template <typename T>
@@ -140,11 +148,13 @@ __device__ __forceinline__ void copy2d_overlapped(T* dst, int ldd, const T* __re
 }
 
 // orders the LDS accesses of one wavefront: what its lanes wrote before is
-// seen by its lanes after
+// seen by its lanes after.  A wavefront's LDS operations execute in issue
+// order, so this is a compiler barrier only (wavefront-scope fences emit no
+// wait): loads issued earlier for later use stay in flight across it.
 __device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // dynamic LDS limits of the kernels for this problem's sizes; called by rkkt_create

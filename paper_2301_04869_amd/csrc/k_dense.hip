@@ -221,11 +221,6 @@ __global__ __launch_bounds__(256) void k_stacked_product(DP d, long long per) {
   }
 }
 
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 
 // 1/sqrt(d) for d > 0: the hardware reciprocal square root estimate refined by
@@ -400,12 +395,6 @@ constexpr int kRawSize = kRawD + kPB;
 __host__ __device__ inline int chol_small_lds_bytes(int n) {
   const int np = (n + kPB - 1) / kPB * kPB;
   return 8 * (np * (np + 1) + 2 * kRawSize);
-}
-
-// value of v in lane Q of the caller's row of 16 lanes (DPP row_newbcast)
-template <int Q>
-__device__ __forceinline__ double row_bcast(double v) {
-  return __builtin_amdgcn_mov_dpp(v, 0x150 + Q, 0xf, 0xf, false);
 }
 
 // LDL^T of one 16 x 16 symmetric tile by lanes 0..15 of one wavefront, in the

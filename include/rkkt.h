@@ -224,7 +224,8 @@ int rkkt_condense(rkkt_problem* p, const double* sigma_x, const double* sigma_u,
  * columns 16 b .. 16 b + 15) receives the transpose of the strict lower
  * triangle of that block's inverse (khat[j][i] = (L_bb^-1)[i][j], i > j),
  * which rkkt_step applies as small dense products; the rest of the strict
- * upper triangle is left as it was.
+ * upper triangle is left as it was.  When info_dev is not 0 the contents of
+ * khat are unspecified.
  */
 int rkkt_factor(rkkt_problem* p, double* khat, int* info_dev, hipStream_t stream);
 

@@ -819,29 +819,93 @@ __global__ __launch_bounds__(kRThreads) void k_reduced_solve(DP d, const double*
 }
 
 // Reduced solve with the factor stored by k_chol_small.  Every wavefront
-// stages the factor into LDS while summing the scenario parts of the
-// right-hand side; then wavefront 0 alone runs block forward and backward
-// substitution over 16-row blocks without barriers: lane l takes row
-// l % 16 of the block and every fourth column of its off-diagonal part
-// (two shuffles combine the four), and the block's stored diagonal inverse
-// is applied with readlane broadcasts of the block's partial results.
-constexpr int kIThreads = 1024, kIWaves = kIThreads / 64;
+// stages the lower block triangle of the factor (16 x 16 tiles, zeros past
+// n) into LDS while summing the scenario parts of the right-hand side.  Then
+// block substitution, right-looking with look-ahead, one barrier per block:
+// after block j is solved, the owner of each later block i subtracts
+// L_ij y_j (lane = row, four column quarters combined by two shuffles);
+// wavefront 0 owns block j + 1, so it updates it first and solves it at once
+// with the block's stored inverse (y_r = t_r / L_rr + sum_{p<r}
+// (L^-1)[r][p] t_p, t broadcast along the row of 16 lanes with DPP).  The
+// backward pass runs the same way on the transposed tiles.
+constexpr int kIThreads = 512, kIWaves = kIThreads / 64;
 
-__host__ __device__ inline long long rsolve_blk_lds_bytes(int n) { return 8LL * ((long long)n * (n + 1) + 2LL * n); }
+__host__ __device__ inline long long rsolve_blk_lds_bytes(int n) {
+  const long long np = (n + 15) / 16 * 16;
+  return 8LL * (np * (np + 1) + 2 * np);
+}
+
+// y[b0 + r] <- the block's inverse (kFwd: L_bb^-1, else L_bb^-T) applied to
+// y[b0 .. b0 + 15], by one wavefront (lanes 0..15 write)
+template <bool kFwd, int... P>
+__device__ __forceinline__ void rsolve_diag(const double* sa, int ld, const double* rd, double* y, int b0,
+                                            int lane, std::integer_sequence<int, P...>) {
+  const int r = lane & 15;
+  double c[kPB];
+  // (L^-1)[r][p] (p < r) is stored at [b0 + p][b0 + r], (L^-1)[p][r] (p > r)
+  // at [b0 + r][b0 + p]
+  ((c[P] = kFwd ? (P < r ? sa[(b0 + P) * ld + b0 + r] : 0.0) : (P > r ? sa[(b0 + r) * ld + b0 + P] : 0.0)), ...);
+  const double t = y[b0 + r];
+  double a0 = rd[b0 + r] * t, a1 = 0.0;
+  ((P % 2 == 0 ? (a0 = fma(c[P], row_bcast<P>(t), a0)) : (a1 = fma(c[P], row_bcast<P>(t), a1))), ...);
+  wave_sync();
+  if (lane < kPB) y[b0 + r] = a0 + a1;
+}
+
+// y_i -= L_ij y_j (kFwd) or L_ji^T y_j, 16 x 16, by one wavefront
+template <bool kFwd>
+__device__ __forceinline__ void rsolve_update(const double* sa, int ld, double* y, int i0, int j0, int lane) {
+  const int r = lane & 15, g = lane >> 4;
+  double acc = 0.0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int c = g + 4 * u;
+    const double l = kFwd ? sa[(i0 + r) * ld + j0 + c] : sa[(j0 + c) * ld + i0 + r];
+    acc = fma(l, y[j0 + c], acc);
+  }
+  acc += __shfl_xor(acc, 16);
+  acc += __shfl_xor(acc, 32);
+  if (g == 0) y[i0 + r] -= acc;
+}
 
 __global__ __launch_bounds__(kIThreads) void k_reduced_solve_blk(DP d, const double* r1u,
                                                                  const double* A, double* pu) {
   extern __shared__ double sm[];
   __shared__ double red[kIThreads];
-  const int n = d.nu, ld = n + 1, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int n = d.nu, np = (n + kPB - 1) / kPB * kPB, nb = np / kPB, ld = np + 1;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   double* sa = sm;
-  double* y = sa + (long long)n * ld;
-  double* rd = y + n;
-  copy2d_overlapped(sa, ld, A, n, n, n, tid, kIThreads);
+  double* y = sa + (long long)np * ld;
+  double* rd = y + np;
+  {
+    // lower block triangle: tile tau of block row bi, block column bl <= bi,
+    // in row-major order
+    const int total = nb * (nb + 1) / 2 * kPB * kPB;
+    for (int t0 = tid; t0 < total; t0 += kStageBatch * kIThreads) {
+      double v[kStageBatch];
+      int o[kStageBatch];
+#pragma unroll
+      for (int u = 0; u < kStageBatch; ++u) {
+        const int t = t0 + u * kIThreads;
+        o[u] = -1;
+        if (t < total) {
+          int tau = t / (kPB * kPB), bi = 0;
+          while (tau >= bi + 1) tau -= ++bi;
+          const int e = t % (kPB * kPB);
+          const int i = kPB * bi + e / kPB, c = kPB * tau + e % kPB;
+          v[u] = i < n && c < n ? A[(long long)i * n + c] : 0.0;
+          o[u] = i * ld + c;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kStageBatch; ++u)
+        if (o[u] >= 0) sa[o[u]] = v[u];
+    }
+  }
   // right-hand side: sum of the scenario parts, scenario slices per wavefront
   const int per = (d.N + kIWaves - 1) / kIWaves;
   const int k0 = wv * per, k1 = min(d.N, k0 + per);
-  for (int c0 = 0; c0 < n; c0 += 64) {
+  for (int c0 = 0; c0 < np; c0 += 64) {
     const int c = c0 + lane;
     double acc = 0.0;
     if (c < n) {
@@ -857,72 +921,41 @@ __global__ __launch_bounds__(kIThreads) void k_reduced_solve_blk(DP d, const dou
     }
     red[wv * 64 + lane] = acc;
     __syncthreads();
-    if (wv == 0 && c < n) {
-      double sum = -r1u[c];
+    if (wv == 0 && c < np) {
+      double sum = c < n ? -r1u[c] : 0.0;
       for (int q = 0; q < kIWaves; ++q) sum += red[q * 64 + lane];
       y[c] = sum;
     }
     __syncthreads();
   }
-  for (int c = tid; c < n; c += kIThreads) rd[c] = rcp_nr(sa[c * ld + c]);
+  for (int c = tid; c < np; c += kIThreads) rd[c] = c < n ? rcp_nr(sa[c * ld + c]) : 0.0;
   __syncthreads();
-  if (wv != 0) return;
-  const int r = lane & 15, g = lane >> 4;
-  // forward: L y = b, y overwriting b block by block
-  for (int jb = 0; jb < n; jb += 16) {
-    const int nb = min(16, n - jb);
-    const int row = jb + min(r, nb - 1);
-    double a0 = 0.0, a1 = 0.0;
-    int k = g;
-    for (; k + 4 < jb; k += 8) {
-      a0 = fma(sa[row * ld + k], y[k], a0);
-      a1 = fma(sa[row * ld + k + 4], y[k + 4], a1);
+  constexpr auto all = std::make_integer_sequence<int, kPB>{};
+  // forward: L y = b
+  if (wv == 0) rsolve_diag<true>(sa, ld, rd, y, 0, lane, all);
+  __syncthreads();
+  for (int j = 0; j + 1 < nb; ++j) {
+    const int i = j + 1 + wv;
+    if (i < nb) rsolve_update<true>(sa, ld, y, kPB * i, kPB * j, lane);
+    if (wv == 0) {
+      wave_sync();
+      rsolve_diag<true>(sa, ld, rd, y, kPB * (j + 1), lane, all);
     }
-    if (k < jb) a0 = fma(sa[row * ld + k], y[k], a0);
-    double acc = a0 + a1;
-    acc += __shfl_xor(acc, 16);
-    acc += __shfl_xor(acc, 32);
-    const double tr = y[row] - acc;  // lane r (and r + 16 g): t_r
-    // y_r = t_r / L_rr + sum_{p < r} (L_bb^-1)[r][p] t_p, stored at sa[jb + p][jb + r]
-    double v0 = rd[row] * tr, v1 = 0.0;
-#pragma unroll
-    for (int p = 0; p < 16; p += 2) {
-      const double t0 = readlane_d(tr, p), t1 = readlane_d(tr, p + 1);
-      if (p < r && p < nb) v0 = fma(sa[(jb + p) * ld + row], t0, v0);
-      if (p + 1 < r && p + 1 < nb) v1 = fma(sa[(jb + p + 1) * ld + row], t1, v1);
-    }
-    wave_sync();
-    if (g == 0 && r < nb) y[jb + r] = v0 + v1;
-    wave_sync();
+    __syncthreads();
   }
-  // backward: L^T x = y, x overwriting y block by block
-  for (int jb = (n - 1) / 16 * 16; jb >= 0; jb -= 16) {
-    const int nb = min(16, n - jb);
-    const int col = jb + min(r, nb - 1);
-    double a0 = 0.0, a1 = 0.0;
-    int i = jb + 16 + g;
-    for (; i + 4 < n; i += 8) {
-      a0 = fma(sa[i * ld + col], y[i], a0);
-      a1 = fma(sa[(i + 4) * ld + col], y[i + 4], a1);
+  // backward: L^T x = y, x overwriting y
+  if (wv == 0) rsolve_diag<false>(sa, ld, rd, y, kPB * (nb - 1), lane, all);
+  __syncthreads();
+  for (int j = nb - 1; j > 0; --j) {
+    const int i = j - 1 - wv;
+    if (i >= 0) rsolve_update<false>(sa, ld, y, kPB * i, kPB * j, lane);
+    if (wv == 0) {
+      wave_sync();
+      rsolve_diag<false>(sa, ld, rd, y, kPB * (j - 1), lane, all);
     }
-    if (i < n) a0 = fma(sa[i * ld + col], y[i], a0);
-    double acc = a0 + a1;
-    acc += __shfl_xor(acc, 16);
-    acc += __shfl_xor(acc, 32);
-    const double tr = y[col] - acc;
-    // x_r = t_r / L_rr + sum_{p > r} (L_bb^-1)[p][r] t_p, stored at sa[jb + r][jb + p]
-    double v0 = rd[col] * tr, v1 = 0.0;
-#pragma unroll
-    for (int p = 0; p < 16; p += 2) {
-      const double t0 = readlane_d(tr, p), t1 = readlane_d(tr, p + 1);
-      if (p > r && p < nb) v0 = fma(sa[col * ld + jb + p], t0, v0);
-      if (p + 1 > r && p + 1 < nb) v1 = fma(sa[col * ld + jb + p + 1], t1, v1);
-    }
-    wave_sync();
-    if (g == 0 && r < nb) y[jb + r] = v0 + v1;
-    wave_sync();
+    __syncthreads();
   }
-  for (int c = lane; c < n; c += 64) pu[c] = y[c];
+  for (int c = tid; c < n; c += kIThreads) pu[c] = y[c];
 }
 
 }  // namespace

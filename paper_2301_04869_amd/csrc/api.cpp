@@ -285,6 +285,15 @@ int rkkt_create(const rkkt_network* net, int n_scen, const double* pd, const dou
     pack_entries(s.stp_dn, b);
     b.insert(b.end(), s.stp_up.ptr.begin(), s.stp_up.ptr.end());
     b.insert(b.end(), s.stp_dn.ptr.begin(), s.stp_dn.ptr.end());
+    // largest entry count of a slot, per phase (the sweep picks its code path)
+    for (const rkkt::Sched* sc : {&s.stp_up, &s.stp_dn}) {
+      const int S = rkkt::kGroupLds, nph = (int)(sc->ptr.size() - 1) / S;
+      for (int q = 0; q < nph; ++q) {
+        int mx = 0;
+        for (int j = 0; j < S; ++j) mx = std::max(mx, sc->ptr[q * S + j + 1] - sc->ptr[q * S + j]);
+        b.push_back((unsigned)mx);
+      }
+    }
     if (b.size() % 2) b.push_back(0);
     d.blob_stp_words = (int)b.size();
     if ((e = upload(p, &d.blob_stp, b)) != hipSuccess) goto hip_error;

@@ -170,6 +170,58 @@ __device__ __forceinline__ void sweep(const int* __restrict__ ptr, const void* e
   }
 }
 
+// One sweep for a single right-hand side by one wavefront in LDS (lane =
+// slot of kGroupLds), fewest instructions per phase: a phase whose slots hold
+// at most one entry each (most phases of these schedules) is one guarded
+// multiply-add per lane; longer slots run their entries in order.  The bound
+// and first entry of the next phase are loaded while the current one runs.
+template <bool kTrans, typename Sync>
+__device__ __forceinline__ void sweep_w(const int* ptr, const uint2* ent, const int* phmax, int nphase,
+                                        int slot, const double* lu, double* X, Sync sync) {
+  auto pos = [](uint2 v) { return (int)(kTrans ? v.y >> 16 : v.y & 0xffffu); };
+  auto dst = [](uint2 v) { return (int)(v.x & 0xffffu); };
+  auto src = [](uint2 v) { return (int)(v.x >> 16); };
+  int e0 = 0, n = 0;
+  uint2 t = make_uint2(0u, 0u);
+  if (nphase > 0) {
+    e0 = ptr[slot];
+    n = ptr[slot + 1] - e0;
+    t = ent[n > 0 ? e0 : 0];
+  }
+  for (int q = 0; q < nphase; ++q) {
+    const int m = __builtin_amdgcn_readfirstlane(phmax[q]);
+    int e0n = 0, nn = 0;
+    uint2 tn = make_uint2(0u, 0u);
+    if (q + 1 < nphase) {
+      e0n = ptr[(q + 1) * kGroupLds + slot];
+      nn = ptr[(q + 1) * kGroupLds + slot + 1] - e0n;
+      tn = ent[nn > 0 ? e0n : 0];
+    }
+    if (n > 0) {
+      if (m <= 1) {
+        X[dst(t)] = fma(-lu[pos(t)], X[src(t)], X[dst(t)]);
+      } else {
+        int cur = dst(t);
+        double acc = fma(-lu[pos(t)], X[src(t)], X[cur]);
+        for (int u = 1; u < n; ++u) {
+          const uint2 v = ent[e0 + u];
+          if (dst(v) != cur) {
+            X[cur] = acc;
+            cur = dst(v);
+            acc = X[cur];
+          }
+          acc = fma(-lu[pos(v)], X[src(v)], acc);
+        }
+        X[cur] = acc;
+      }
+    }
+    sync();
+    e0 = e0n;
+    n = nn;
+    t = tn;
+  }
+}
+
 // ------------------------------------------------------------------ chain
 // The chain rows c0 .. nx - 1 (each alone in its level in both directions)
 // are solved sequentially in registers instead of one barrier-separated
@@ -890,6 +942,7 @@ struct StepView {
   double *v0, *v1, *v2, *wv;
   const int *uptr, *dptr;
   const void *uent, *dent;
+  const int *umax, *dmax;  // LDS mode: largest slot count of each phase
 };
 
 template <bool kLDS>
@@ -920,6 +973,8 @@ __device__ __forceinline__ StepView step_view(const DP& d, int k, double* smem, 
     int* ip = reinterpret_cast<int*>(de + 2 * d.n_sent);
     w.uptr = ip;
     w.dptr = ip + d.nph_u * kGroupLds + 1;
+    w.umax = w.dptr + d.nph_d * kGroupLds + 1;
+    w.dmax = w.umax + d.nph_u;
     w.uent = ue;
     w.dent = de;
     const int t0 = threadIdx.x, ts = blockDim.x;
@@ -953,6 +1008,7 @@ __device__ __forceinline__ StepView step_view(const DP& d, int k, double* smem, 
     w.v2 = d.rhat1 + (long long)k * nx;
     w.wv = d.wbuf + (long long)k * m;
     w.uptr = d.su_ptr; w.dptr = d.sd_ptr; w.uent = d.su_ent; w.dent = d.sd_ent;
+    w.umax = w.dmax = nullptr;
   }
   __syncthreads();
   return w;
@@ -964,14 +1020,16 @@ template <bool kLDS, typename Sync>
 __device__ __forceinline__ void solve_fwd(const DP& d, const StepView& w, double* X, int gl, Sync sync,
                                           const ChainPos& cp) {
   constexpr int G = kLDS ? kGroupLds : kRT;
-  sweep<kLDS, false>(w.uptr, w.uent, d.nph_u, G, gl, true, w.lu, X, 1, 0, sync);
+  if (kLDS) sweep_w<false>(w.uptr, static_cast<const uint2*>(w.uent), w.umax, d.nph_u, gl, w.lu, X, sync);
+  else sweep<kLDS, false>(w.uptr, w.uent, d.nph_u, G, gl, true, w.lu, X, 1, 0, sync);
   if (d.chain_t > 0) {
     if (gl < 64) chain_solve1<true>(d, w.lu, cp, X, gl);
     sync();
     if (gl < 64) chain_solve1<false>(d, w.lu, cp, X, gl);
     sync();
   }
-  sweep<kLDS, false>(w.dptr, w.dent, d.nph_d, G, gl, true, w.lu, X, 1, 0, sync);
+  if (kLDS) sweep_w<false>(w.dptr, static_cast<const uint2*>(w.dent), w.dmax, d.nph_d, gl, w.lu, X, sync);
+  else sweep<kLDS, false>(w.dptr, w.dent, d.nph_d, G, gl, true, w.lu, X, 1, 0, sync);
   for (int i = gl; i < d.nx; i += G) X[i] *= w.invd[i];
   sync();
 }
@@ -986,14 +1044,16 @@ template <bool kLDS, typename Sync>
 __device__ __forceinline__ void solve_adj_scaled(const DP& d, const StepView& w, double* X, int gl, Sync sync,
                                                  const ChainPos& cp) {
   constexpr int G = kLDS ? kGroupLds : kRT;
-  sweep<kLDS, true>(w.uptr, w.uent, d.nph_u, G, gl, true, w.lu, X, 1, 0, sync);
+  if (kLDS) sweep_w<true>(w.uptr, static_cast<const uint2*>(w.uent), w.umax, d.nph_u, gl, w.lu, X, sync);
+  else sweep<kLDS, true>(w.uptr, w.uent, d.nph_u, G, gl, true, w.lu, X, 1, 0, sync);
   if (d.chain_t > 0) {
     if (gl < 64) chain_solve1<true>(d, w.lu, cp, X, gl);
     sync();
     if (gl < 64) chain_solve1<false>(d, w.lu, cp, X, gl);
     sync();
   }
-  sweep<kLDS, true>(w.dptr, w.dent, d.nph_d, G, gl, true, w.lu, X, 1, 0, sync);
+  if (kLDS) sweep_w<true>(w.dptr, static_cast<const uint2*>(w.dent), w.dmax, d.nph_d, gl, w.lu, X, sync);
+  else sweep<kLDS, true>(w.dptr, w.dent, d.nph_d, G, gl, true, w.lu, X, 1, 0, sync);
   sync();
 }
 
@@ -1125,6 +1185,8 @@ __device__ __forceinline__ StepView sweep_view(const DP& d, double* lu, unsigned
   int* ip = reinterpret_cast<int*>(de + 2 * d.n_sent);
   w.uptr = ip;
   w.dptr = ip + d.nph_u * kGroupLds + 1;
+  w.umax = w.dptr + d.nph_d * kGroupLds + 1;
+  w.dmax = w.umax + d.nph_u;
   w.uent = ue;
   w.dent = de;
   return w;

@@ -68,18 +68,20 @@ __host__ __device__ inline long long refactor_lds_bytes(const LdsSizes& z) {
 }
 // Single-column step workgroup (one scenario): doubles lu[nnz_f] invd[nx]
 // K[nnz_k] H[nnz_h] G_u[nnz_gu] ra[nx] r3[nx] r2[m] r4[m] ss[m] w[m] v0 v1
-// v2 [nx each] pu[nu]; then packed entries of both solve schedules and their
-// pointer tables.
+// v2 [nx each] pu[nu]; then packed entries of both solve schedules, their
+// pointer tables and per-phase largest slot counts.
 __host__ __device__ inline long long step_lds_bytes(const LdsSizes& z) {
   return 8LL * ((long long)z.nnz_f + z.nx + z.nnz_k + z.nnz_h + z.nnz_gu + 5LL * z.nx + 4LL * z.m + z.nu) +
-         4LL * (4LL * z.nnz_l + (z.nph_u * (long long)kGroupLds + 1) + (z.nph_d * (long long)kGroupLds + 1) + 2);
+         4LL * (4LL * z.nnz_l + (z.nph_u * (long long)kGroupLds + 1) + (z.nph_d * (long long)kGroupLds + 1) +
+                z.nph_u + z.nph_d + 2);
 }
 
 // step kernels of the stacked variant: lu[nnz_f] invd[nx] v0[nx] v1[nx]
 // vu[nu] red[threads + nu] (doubles), then the step schedule blob
 __host__ __device__ inline long long step2_lds_bytes(const LdsSizes& z, int threads) {
   return 8LL * ((long long)z.nnz_f + 3LL * z.nx + 2LL * z.nu + threads) +
-         4LL * (4LL * z.nnz_l + (z.nph_u * (long long)kGroupLds + 1) + (z.nph_d * (long long)kGroupLds + 1) + 2);
+         4LL * (4LL * z.nnz_l + (z.nph_u * (long long)kGroupLds + 1) + (z.nph_d * (long long)kGroupLds + 1) +
+                z.nph_u + z.nph_d + 2);
 }
 
 }  // namespace rkkt

@@ -246,10 +246,27 @@ __device__ __forceinline__ ChainPos chain_positions(const DP& d, int lane) {
   return c;
 }
 
+// x_b from lane b of the row for every b < t in order (up) or reverse order
+// (down), rows a > b (up) or a < b (down) subtract coef[b] x_b
+template <bool kUp, int... B>
+__device__ __forceinline__ double chain_row(double x, const double (&coef)[kChainMax], int lane, int t,
+                                            std::integer_sequence<int, B...>) {
+  auto step = [&](auto bc) {
+    constexpr int b = kUp ? decltype(bc)::value : 15 - decltype(bc)::value;
+    if (b < t) {
+      const double xb = row_bcast<b>(x);
+      if (kUp ? lane > b : lane < b) x = fma(-coef[b], xb, x);
+    }
+  };
+  (step(std::integral_constant<int, B>{}), ...);
+  return x;
+}
+
 // One column, lanes 0 .. t-1 of the calling wavefront hold chain rows a;
 // x_b is broadcast with readlane.  Up: b increasing, rows a > b update;
 // down: b decreasing, rows a < b update.
-template <bool kUp>
+// (kDpp: chains of up to 16 rows broadcast with DPP instead of readlane)
+template <bool kUp, bool kDpp>
 __device__ __forceinline__ void chain_solve1(const DP& d, const double* lu, const ChainPos& cp, double* X,
                                              int lane) {
   const int t = d.chain_t, c0 = d.chain_c0;
@@ -258,7 +275,9 @@ __device__ __forceinline__ void chain_solve1(const DP& d, const double* lu, cons
   double coef[kChainMax];
 #pragma unroll
   for (int b = 0; b < kChainMax; ++b) coef[b] = cp.p[b] >= 0 ? lu[cp.p[b]] : 0.0;
-  if (kUp) {
+  if (kDpp && t <= 16) {
+    x = chain_row<kUp>(x, coef, lane, t, std::make_integer_sequence<int, 16>{});
+  } else if (kUp) {
 #pragma unroll
     for (int b = 0; b < kChainMax; ++b)
       if (b < t) {
@@ -1023,9 +1042,9 @@ __device__ __forceinline__ void solve_fwd(const DP& d, const StepView& w, double
   if (kLDS) sweep_w<false>(w.uptr, static_cast<const uint2*>(w.uent), w.umax, d.nph_u, gl, w.lu, X, sync);
   else sweep<kLDS, false>(w.uptr, w.uent, d.nph_u, G, gl, true, w.lu, X, 1, 0, sync);
   if (d.chain_t > 0) {
-    if (gl < 64) chain_solve1<true>(d, w.lu, cp, X, gl);
+    if (gl < 64) chain_solve1<true, kLDS>(d, w.lu, cp, X, gl);
     sync();
-    if (gl < 64) chain_solve1<false>(d, w.lu, cp, X, gl);
+    if (gl < 64) chain_solve1<false, kLDS>(d, w.lu, cp, X, gl);
     sync();
   }
   if (kLDS) sweep_w<false>(w.dptr, static_cast<const uint2*>(w.dent), w.dmax, d.nph_d, gl, w.lu, X, sync);
@@ -1047,9 +1066,9 @@ __device__ __forceinline__ void solve_adj_scaled(const DP& d, const StepView& w,
   if (kLDS) sweep_w<true>(w.uptr, static_cast<const uint2*>(w.uent), w.umax, d.nph_u, gl, w.lu, X, sync);
   else sweep<kLDS, true>(w.uptr, w.uent, d.nph_u, G, gl, true, w.lu, X, 1, 0, sync);
   if (d.chain_t > 0) {
-    if (gl < 64) chain_solve1<true>(d, w.lu, cp, X, gl);
+    if (gl < 64) chain_solve1<true, kLDS>(d, w.lu, cp, X, gl);
     sync();
-    if (gl < 64) chain_solve1<false>(d, w.lu, cp, X, gl);
+    if (gl < 64) chain_solve1<false, kLDS>(d, w.lu, cp, X, gl);
     sync();
   }
   if (kLDS) sweep_w<true>(w.dptr, static_cast<const uint2*>(w.dent), w.dmax, d.nph_d, gl, w.lu, X, sync);

@@ -910,6 +910,40 @@ __global__ __launch_bounds__(kRT) void k_reduce64(DP d) {
   if (kVar == 2) {
     if (kLDS && colok)
       for (int i = wv; i < nx; i += kS64) zk[(long long)i * d.nu_pad + col] = T[i * kW64 + c];
+    if (kLDS) {
+      // (row, 16-column quarter) items over all threads: a row's entries are
+      // read once per item and each multiplies 16 panel values; the lanes
+      // take the quarter's columns in lane-rotated order, so the panel reads
+      // of one instruction spread over the LDS banks.  Each value is
+      // K[r][n_x + col] plus the x entries' terms in pattern order.
+      const int ln = (tid >> 2) & 15;
+      for (int it = tid; it < nz * 4; it += kRT) {
+        const int r = it >> 2, lo = 16 * (it & 3);
+        const int e0 = k_ptr[r], eu = k_usplit[r], e1 = k_ptr[r + 1];
+        double acc[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc[j] = 0.0;
+        for (int e = eu; e < e1; ++e) {
+          const int cu = k_col[e] - nx - c0 - lo;
+          const double v = kv[e];
+#pragma unroll
+          for (int j = 0; j < 16; ++j)
+            if (((j + ln) & 15) == cu) acc[j] = v;
+        }
+        for (int e = e0; e < eu; ++e) {
+          const double v = kv[e];
+          const double* tr = T + (long long)k_col[e] * kW64 + lo;
+#pragma unroll
+          for (int j = 0; j < 16; ++j) acc[j] = fma(v, tr[(j + ln) & 15], acc[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const int cc = c0 + lo + ((j + ln) & 15);
+          if (cc < nu) kzk[(long long)r * d.nu_pad + cc] = acc[j];
+        }
+      }
+      return;
+    }
     for (int r0 = wv; r0 < nz; r0 += kRowsK * kS64) {
       double v[kRowsK];
       if (!k_rows(r0, v)) k_rows_slow(r0, v);

@@ -335,6 +335,12 @@ __device__ __forceinline__ void chain_solveW(const DP& d, const double* cv, doub
 // and then the down solve, each row subtracting its terms in the same order
 // as chain_solveW (so the results are the same).  64 columns = 16
 // wavefronts.
+// f(integral_constant<int, B>) for B in order
+template <typename F, int... B>
+__device__ __forceinline__ void for_each_const(F&& f, std::integer_sequence<int, B...>) {
+  (f(std::integral_constant<int, B>{}), ...);
+}
+
 template <bool kTrans>
 __device__ __forceinline__ void chain_solveR(const DP& d, const double* cv, double* X, int ld, int wv) {
   const int t = d.chain_t, c0 = d.chain_c0;
@@ -344,6 +350,39 @@ __device__ __forceinline__ void chain_solveR(const DP& d, const double* cv, doub
   const int col0 = 4 * wv + half, col1 = col0 + 2;
   double x = own ? X[(long long)(c0 + a) * ld + col0] : 0.0;
   double y = own ? X[(long long)(c0 + a) * ld + col1] : 0.0;
+  if (t <= 16) {
+    // rows in lanes 0..15 (and 32..47 for the other column of the pair):
+    // x_b is lane b of each row of 16 lanes, a DPP broadcast
+    auto up = [&](auto bc) {
+      constexpr int b = decltype(bc)::value;
+      if (b < t) {
+        const double cf = own ? (kTrans ? cv[b * t + a] : cv[a * t + b]) : 0.0;
+        const double xb = row_bcast<b>(x), yb = row_bcast<b>(y);
+        if (a > b) {
+          x = fma(-cf, xb, x);
+          y = fma(-cf, yb, y);
+        }
+      }
+    };
+    auto down = [&](auto bc) {
+      constexpr int b = 15 - decltype(bc)::value;
+      if (b < t) {
+        const double cf = own ? (kTrans ? cv[b * t + a] : cv[a * t + b]) : 0.0;
+        const double xb = row_bcast<b>(x), yb = row_bcast<b>(y);
+        if (a < b) {
+          x = fma(-cf, xb, x);
+          y = fma(-cf, yb, y);
+        }
+      }
+    };
+    for_each_const(up, std::make_integer_sequence<int, 16>{});
+    for_each_const(down, std::make_integer_sequence<int, 16>{});
+    if (own) {
+      X[(long long)(c0 + a) * ld + col0] = x;
+      X[(long long)(c0 + a) * ld + col1] = y;
+    }
+    return;
+  }
 #pragma unroll
   for (int b = 0; b < kChainMax; ++b)
     if (b < t) {

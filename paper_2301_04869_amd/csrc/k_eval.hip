@@ -225,21 +225,26 @@ __device__ inline double w_gather_one(const DP& d, int e, double w, const double
 // line values and the bus / Jacobian values of one scenario in one
 // workgroup, the line values in LDS (they feed only the gathers and, from
 // HBM, the kernels after; both copies are written)
-constexpr int kLvT = 512;
+// kLvSplit workgroups per scenario: each evaluates every line of its
+// scenario into LDS (the first also writes them out) and takes a strided
+// share of the gathers, so the gathers of a scenario run on several CUs.
+constexpr int kLvT = 512, kLvSplit = 4;
 
 __global__ __launch_bounds__(kLvT) void k_line_eval_gather(DP d, const double* x, const double* u) {
   extern __shared__ double lv[];
-  const int k = blockIdx.x, tid = threadIdx.x;
+  const int k = blockIdx.x / kLvSplit, part = blockIdx.x % kLvSplit, tid = threadIdx.x;
   double* glv = d.LV + (long long)k * d.nl * kLVsize;
   for (int l = tid; l < d.nl; l += kLvT) {
     double* o = lv + (long long)l * kLVsize;
     line_eval_one(d, k, l, x, u, o);
+    if (part == 0) {
 #pragma unroll
-    for (int q = 0; q < kLVsize; ++q) glv[(long long)l * kLVsize + q] = o[q];
+      for (int q = 0; q < kLVsize; ++q) glv[(long long)l * kLVsize + q] = o[q];
+    }
   }
   __syncthreads();
   double* gev = d.EV + (long long)k * d.n_ev;
-  for (int e = tid; e < d.n_ev; e += kLvT) gev[e] = gather_ev_one(d, e, lv);
+  for (int e = part * kLvT + tid; e < d.n_ev; e += kLvSplit * kLvT) gev[e] = gather_ev_one(d, e, lv);
 }
 
 __global__ void k_line_eval(DP d, const double* x, const double* u) {
@@ -335,7 +340,7 @@ hipError_t configure_eval_kernels(const DP& d) {
 
 void launch_evaluate_values(const DP& d, const double* x, const double* u, hipStream_t s) {
   if (line_fused(d)) {
-    k_line_eval_gather<<<d.N, kLvT, (size_t)line_lds_bytes(d), s>>>(d, x, u);
+    k_line_eval_gather<<<d.N * kLvSplit, kLvT, (size_t)line_lds_bytes(d), s>>>(d, x, u);
     return;
   }
   long long nl = (long long)d.N * d.nl;

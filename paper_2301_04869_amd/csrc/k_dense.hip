@@ -829,6 +829,7 @@ __global__ __launch_bounds__(kRThreads) void k_reduced_solve(DP d, const double*
 // (L^-1)[r][p] t_p, t broadcast along the row of 16 lanes with DPP).  The
 // backward pass runs the same way on the transposed tiles.
 constexpr int kIThreads = 512, kIWaves = kIThreads / 64;
+constexpr int kRhsPre = 16;   // scenarios per wavefront whose parts are loaded ahead
 
 __host__ __device__ inline long long rsolve_blk_lds_bytes(int n) {
   const long long np = (n + 15) / 16 * 16;
@@ -877,6 +878,18 @@ __global__ __launch_bounds__(kIThreads) void k_reduced_solve_blk(DP d, const dou
   double* sa = sm;
   double* y = sa + (long long)np * ld;
   double* rd = y + np;
+  // the right-hand side's loads first (up to kRhsPre scenarios of each of
+  // the two column chunks per lane), in flight during the staging
+  const int per = (d.N + kIWaves - 1) / kIWaves;
+  const int k0 = wv * per, k1 = min(d.N, k0 + per);
+  double pre[2][kRhsPre];
+#pragma unroll
+  for (int ch = 0; ch < 2; ++ch) {
+    const int c = 64 * ch + lane;
+#pragma unroll
+    for (int u = 0; u < kRhsPre; ++u)
+      pre[ch][u] = c < n && k0 + u < k1 ? d.rpart[(long long)(k0 + u) * n + c] : 0.0;
+  }
   {
     // lower block triangle: tile tau of block row bi, block column bl <= bi,
     // in row-major order
@@ -902,22 +915,18 @@ __global__ __launch_bounds__(kIThreads) void k_reduced_solve_blk(DP d, const dou
         if (o[u] >= 0) sa[o[u]] = v[u];
     }
   }
-  // right-hand side: sum of the scenario parts, scenario slices per wavefront
-  const int per = (d.N + kIWaves - 1) / kIWaves;
-  const int k0 = wv * per, k1 = min(d.N, k0 + per);
-  for (int c0 = 0; c0 < np; c0 += 64) {
-    const int c = c0 + lane;
+  // right-hand side: sum of the scenario parts, scenario slices per
+  // wavefront, each slice in scenario order
+#pragma unroll
+  for (int ch = 0; ch < 2; ++ch) {
+    const int c0 = 64 * ch, c = c0 + lane;
+    if (c0 >= np) break;
     double acc = 0.0;
     if (c < n) {
-      int k = k0;
-      for (; k + 8 <= k1; k += 8) {
-        double v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = d.rpart[(long long)(k + u) * n + c];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) acc += v[u];
-      }
-      for (; k < k1; ++k) acc += d.rpart[(long long)k * n + c];
+      for (int u = 0; u < kRhsPre; ++u)
+        if (k0 + u < k1) acc += pre[ch][u];
+      for (int k = k0 + kRhsPre; k < k1; ++k) acc += d.rpart[(long long)k * n + c];
     }
     red[wv * 64 + lane] = acc;
     __syncthreads();

@@ -167,38 +167,77 @@ def batch_main(args):
 
 
 def stage_work(d):
-    """Algorithmic flops and HBM bytes of one launch of every stage.
+    """The method's own work per launch of every stage: (flops, bytes).
 
-    Bytes count every value array read or written once (inputs, cached
-    Jacobian / Hessian / K / LU values, outputs) and every shared index array
-    once; flops count the multiply-adds of the method (2 flops each)."""
+    Bytes: every input read once, every value array the method materialises
+    (the Jacobian values G_x and G_u, K = W + H^T Sigma_s H, the LU factors,
+    the reduced matrix) written once by the stage that makes it and read once
+    by each stage that needs it, outputs written once; the shared index
+    arrays (patterns, schedules) once per pass, charged to the reduction.
+    Flops: the multiply-adds (2 flops each) of the sparse LU, of the
+    triangular solves with the n_u right-hand sides and the sparse K and G_u
+    products of the paper's adjoint closure (two forward and two adjoint
+    solves per column), the condensation products, the scenario sum and the
+    Cholesky; no evaluation flops are counted.  Work a launch does beyond
+    this (the stacked variant's dense Z^T (K Z) product and its panels of Z
+    and K Z in device memory, per-scenario partial matrices) is returned in
+    a second dict, "beyond", stage -> (flops, bytes)."""
     N, nx, nu, m = d["n_scen"], d["n_x"], d["n_u"], d["m"]
-    nlu, nk, nkx, ngu, ngx, nh = d["nnz_lu"], d["nnz_k"], d["nnz_kx"], d["nnz_gu"], d["nnz_gx"], d["nnz_h"]
-    nev, ntrip = d["n_ev"], d["n_trip"]
-    nl = d["n_line"]
-    w = {}
-    w["evaluate"] = (N * (nl * 200 + 2 * ntrip),
-                     8 * N * (2 * nx + m + nu) + 8 * nu
-                     + 8 * N * (1 + 2 * nx + m + nu) + 8 * N * (nev + nk))
-    w["condense_values"] = (N * 3 * ntrip, 8 * N * (nk + nh + m + nx + nk) + 4 * 3 * ntrip)
-    w["refactor"] = (N * 2 * d["lu_update_flops"], 8 * N * (ngx + nlu + nx) + 4 * 3 * nlu)
     nz = nx + nu
+    nlu, ngu, ngx, nh = d["nnz_lu"], d["nnz_gu"], d["nnz_gx"], d["nnz_h"]
+    kxx, kxu, kuu = d["nnz_kxx"], d["nnz_kxu"], d["nnz_kuu"]
+    nload, ntrip, idx = d["n_load"], d["n_trip"], d["idx_bytes"]
+    nu_pad = (nu + 63) // 64 * 64      # row pitch of the stacked panels
+    w, beyond = {}, {}
+    w["evaluate"] = (0.0, 8 * N * (2 * nx + m + 2 * nload) + 8 * nu            # x, y, z, loads; u
+                     + 8 * N * (1 + 2 * nx + m + nu)                          # f, g, h, gradients
+                     + 8 * N * (ngx + ngu))                                   # G_x, G_u values
+    w["condense_values"] = (3.0 * N * ntrip, 8 * N * (nx + m) + 8 * N * (kxx + 2 * kxu + kuu))
+    w["refactor"] = (2.0 * N * d["lu_update_flops"], 8 * N * (ngx + nlu))
     if d["variant"] == 2:
-        # forward solves and K products; the T rows of Z (its identity rows
-        # are written once at set-up) and K Z written once
-        w["reduce"] = (N * nu * (2 * nlu + 2 * nkx),
-                       8 * N * (nlu + nx + nk + ngu + (nx + nz) * nu) + 4 * (3 * nlu + 2 * nk))
-        # lower triangle of Z^T (K Z): Z and K Z read once, partials written
-        w["stacked_product"] = (N * nz * nu * (nu + 1), 8 * 2 * N * nz * nu + 8 * nu * nu)
+        # forward solves and K products; the closure is the stacked product
+        w["reduce"] = (2.0 * N * nu * (nlu + kxx + kxu),
+                       8 * N * (nlu + kxx + 2 * kxu + kuu + ngu) + idx)
+        beyond["reduce"] = (0.0, 8 * N * (nx + nz) * nu_pad)
+        w["stacked_product"] = (2.0 * N * nu * (nlu + ngu), 8 * nu * nu)
+        beyond["stacked_product"] = (1.0 * N * nz * nu * (nu + 1), 16 * N * nz * nu_pad)
     else:
-        w["reduce"] = (N * nu * (4 * nlu + 2 * nkx + 2 * ngu),
-                       8 * N * (nlu + nx + nk + ngu + nu * nu) + 4 * (3 * nlu + 2 * nk))
-    w["scenario_sum"] = (N * nu * nu, 8 * (N + 1) * nu * nu + 8 * nu)
-    w["factor"] = (nu ** 3 / 3.0, 8 * 2 * nu * nu)
-    w["step_rhs"] = (N * (8 * nlu + 4 * nkx + 4 * nh), 8 * N * (nlu + nk + nh + 2 * nx + 3 * m + nu))
-    w["reduced_solve"] = (2 * nu * nu + N * nu, 8 * (nu * nu + N * nu + 2 * nu))
-    w["step_recover"] = (N * (8 * nlu + 4 * nk + 4 * nh), 8 * N * (nlu + nk + nh + 4 * nx + 5 * m))
-    return w
+        w["reduce"] = (2.0 * N * nu * (2 * nlu + kxx + kxu + ngu),
+                       8 * N * (nlu + kxx + 2 * kxu + kuu + ngu) + idx)
+        beyond["reduce"] = (0.0, 8 * N * nu * nu)
+    w["scenario_sum"] = (1.0 * N * nu * nu, 8 * nu * nu + 8 * nu)
+    w["factor"] = (nu ** 3 / 3.0, 16 * nu * nu)
+    # reduced right-hand side: H^T w, adjoint solve of r1_hat, forward solve of
+    # r3, K_xx q and its adjoint solve, G_u^T and K_ux products
+    w["step_rhs"] = (2.0 * N * (3 * nlu + nh + kxx + kxu + 2 * ngu),
+                     8 * N * (2 * nx + 3 * m) + 8 * N * (nlu + kxx + kxu + nh + ngu) + 8 * N * nu)
+    w["reduced_solve"] = (2.0 * nu * nu + N * nu, 8 * (nu * nu + N * nu + 2 * nu))
+    # p_x (forward solve), p_y (adjoint solve), H p_d, p_s, p_z
+    w["step_recover"] = (2.0 * N * (2 * nlu + ngu + kxx + kxu + 2 * nh),
+                         8 * N * (2 * nx + 3 * m) + 8 * N * (nlu + kxx + kxu + nh + ngu)
+                         + 8 * N * (2 * nx + 2 * m))
+    return w, beyond
+
+
+def method_totals(d):
+    """Per-iteration totals of the method's work as the scope table defines
+    them for condense + factor: F = N [F_LU + n_u (4 nnz_LU + 2 nnz_Kxx +
+    2 nnz_Kxu + 2 nnz_Gu)] + N n_u^2 + n_u^3 / 3 and B = 8 N [(3 n_x + 2 m +
+    2 n_load) + 2 (nnz_Gx + nnz_Gu + nnz_Kxx + nnz_Kxu + nnz_LU)] + idx +
+    24 n_u^2."""
+    N, nx, nu, m = d["n_scen"], d["n_x"], d["n_u"], d["m"]
+    nlu, ngu, ngx = d["nnz_lu"], d["nnz_gu"], d["nnz_gx"]
+    kxx, kxu = d["nnz_kxx"], d["nnz_kxu"]
+    F = N * (2.0 * d["lu_update_flops"] + nu * (4 * nlu + 2 * kxx + 2 * kxu + 2 * ngu)) \
+        + N * nu * nu + nu ** 3 / 3.0
+    B = 8.0 * N * ((3 * nx + 2 * m + 2 * d["n_load"]) + 2 * (ngx + ngu + kxx + kxu + nlu)) \
+        + d["idx_bytes"] + 24.0 * nu * nu
+    return F, B
+
+
+def roof_time(flops, nbytes):
+    """Time at the roofline: max(bytes / HBM peak, flops / FP64 peak), s."""
+    return max(nbytes / (HBM_PEAK_GBS * 1e9), flops / (FP64_PEAK_TFS * 1e12))
 
 
 def measured_traffic(stage, workload):
@@ -223,20 +262,38 @@ def measured_traffic(stage, workload):
 
 
 def roofline_entry(stage, ms, count, d, workload):
-    flops, nbytes = stage_work(d)[stage]
+    work, beyond = stage_work(d)
+    flops, nbytes = work[stage]
     traffic = measured_traffic(stage, workload)
     t = ms / count * 1e-3
     t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
     t_alu = flops / (FP64_PEAK_TFS * 1e12)
+    extra = {"kernel_stage": stage, "avg_ms": ms / count, "algorithmic_bytes": nbytes,
+             "algorithmic_flops": flops}
+    if stage in beyond:
+        extra["beyond_algorithmic"] = {"flops": beyond[stage][0], "bytes": beyond[stage][1]}
     if t_hbm >= t_alu:
         ach = nbytes / t / 1e9
         return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "kernel_stage": stage,
-                "avg_ms": ms / count, "algorithmic_bytes": nbytes, "algorithmic_flops": flops}
+                "frac": ach / HBM_PEAK_GBS, "traffic": traffic, **extra}
     ach = flops / t / 1e12
     return {"bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
-            "frac": ach / FP64_PEAK_TFS, "traffic": traffic, "kernel_stage": stage,
-            "avg_ms": ms / count, "algorithmic_bytes": nbytes, "algorithmic_flops": flops}
+            "frac": ach / FP64_PEAK_TFS, "traffic": traffic, **extra}
+
+
+def pass_roofline(d, ms_per_step, cf_ms):
+    """Whole-pass and condense+factor fractions: roofline time of the method's
+    work over the measured time."""
+    work, _ = stage_work(d)
+    fl = sum(v[0] for v in work.values())
+    by = sum(v[1] for v in work.values())
+    t_pass = roof_time(fl, by)
+    F, B = method_totals(d)
+    t_cf = roof_time(F, B)
+    return {"pass": {"flops": fl, "bytes": by, "roof_us": t_pass * 1e6, "measured_us": ms_per_step * 1e3,
+                     "frac": t_pass / (ms_per_step * 1e-3)},
+            "condense_factor": {"flops": F, "bytes": B, "roof_us": t_cf * 1e6,
+                                "measured_us": cf_ms * 1e3, "frac": t_cf / (cf_ms * 1e-3)}}
 
 
 def find_delta_w(R, torch, p, t, khat, chol, info):
@@ -419,6 +476,7 @@ def main():
         "condense_factor_value": N / (cf_ms * 1e-3),
         "stage_ms": {s: stages[s][0] / max(stages[s][1], 1) for s in stages},
         "roofline": roof,
+        "roofline_pass": pass_roofline(d, ms, cf_ms),
     }
 
     if not args.no_plain:

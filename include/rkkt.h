@@ -95,6 +95,15 @@ typedef struct {
                        dense FP64 matrix-core product over the stacked rows of
                        all scenarios;
                      0 picks 2 when the reduction's data fits on chip, else 1 */
+  int scen_per_group;  /* level-schedule grouping of the refactorisation and
+                          step kernels: at most this many scenarios (1, 2 or
+                          4, one wavefront each) per workgroup; 0 the most
+                          that fit in LDS                                      */
+  int chain_rows;      /* longest run of single-row levels at the end of the
+                          elimination order solved sequentially in registers
+                          instead of one barrier-separated phase per row:
+                          0 the length with the fewest phases (at most 32),
+                          -1 none, 1..32 at most that many                    */
 } rkkt_options;
 
 typedef struct {
@@ -115,6 +124,11 @@ typedef struct {
   int chain_rows;                   /* rows at the top of the elimination order,
                                        each alone in its level, that the solves
                                        and the refactorisation take sequentially */
+  long long nnz_kxx, nnz_kxu, nnz_kuu; /* blocks of K (K_ux has nnz_kxu entries) */
+  long long idx_bytes;              /* device bytes of the shared index arrays
+                                       (patterns, schedules, gather lists); 0
+                                       from rkkt_analyze                        */
+  int n_load;                       /* load buses                               */
 } rkkt_dims;
 
 /*
@@ -355,25 +369,34 @@ int rkkt_graph_capture(rkkt_problem* p, const rkkt_iteration* it);
 int rkkt_graph_launch(rkkt_problem* p, hipStream_t stream);
 
 /*
- * Independent instances of uneven sizes in one launch: the passes of n
- * handles (each with its own rkkt_iteration) are captured as n parallel
- * branches of one HIP graph (fork from and join into one capture stream) and
- * replayed with a single rkkt_batch_launch.  Each handle keeps its own
- * reduced matrix (no sum across instances).  The batch does not own the
- * handles; they must outlive it.  rkkt_batch_create allocates the graph and
- * one capture stream per instance.
+ * Independent instances of uneven sizes in one launch (the paper batches
+ * independent blocks on one device; here whole instances of different
+ * sizes): the pass of each of n distinct handles (each with its own
+ * rkkt_iteration) is captured by rkkt_graph_capture on that handle, which
+ * replaces the handle's own captured graph, and the n graphs become
+ * independent child nodes of one HIP graph, replayed by a single
+ * rkkt_batch_launch.  Each handle keeps its own reduced matrix (no sum across
+ * instances).  The batch holds copies of the instance graphs and does not own
+ * the handles; they and every buffer named in `its` must outlive it.
+ * RKKT_ERR_ARG if a handle appears twice (its workspace would be shared);
+ * an instance that fails to capture is named in the message.
  */
 typedef struct rkkt_batch rkkt_batch;
 
 /*
- * Autotuner of the reduction's launch shape: builds one handle per candidate
- * (reduction variant 1 and 2, each with the automatic column tile and with
- * 8, 16, 32, 64 up to n_u, each in the LDS or global layout it implies;
- * variant 2 only while its stacked panels stay under 4 GiB), evaluates them
- * at a fixed interior point (angles 0, magnitudes 1, outputs mid-range,
- * multipliers 0, all IPM diagonals 1) and times `reps` condense calls with
- * HIP events.  Writes the fastest choice into *best (device copied from opt)
- * and its mean time; allocates and frees device memory and synchronises.
+ * Autotuner of the launch shape (a project addition: the paper fixes its
+ * batch width by hand).  Builds one handle per candidate, evaluates it at a
+ * fixed interior point (angles 0, magnitudes 1, outputs mid-range,
+ * multipliers 0, all IPM diagonals and residuals 1, delta_w = 1) and times
+ * `reps` calls with HIP events, in two stages: (1) every reduction variant
+ * (1 and 2; 2 only while its stacked panels stay under 4 GiB) with the
+ * automatic column tile and with 8, 16, 32, 64 up to n_u, each in the LDS or
+ * global layout it implies, timed on condense; (2) the level-schedule
+ * grouping for the winner of (1): scen_per_group 0, 1, 2, 4 x chain_rows 0,
+ * -1, timed on whole rkkt_iterate passes.  Writes the fastest options (device
+ * copied from opt; col_tile and variant as resolved, scen_per_group and
+ * chain_rows as requested) into *best and its mean pass time in ms into
+ * *best_ms; allocates and frees device memory and synchronises.
  */
 int rkkt_autotune(const rkkt_network* net, int n_scen, const double* pd, const double* qd,
                   const rkkt_options* opt, int reps, rkkt_options* best, double* best_ms);

@@ -236,12 +236,16 @@ def newton_condensed(prob: Problem, ev: Eval, dg: Diag, rs: Resid, delta_w: floa
 
 
 # --------------------------------------------------------------- reduction
+# Largest n_x factorised densely (LAPACK); larger G_x blocks go to SuperLU.
+DENSE_MAX = 3000
+
+
 class _GxFactor:
-    """LU of one G_x block (dense LAPACK for small n_x, SuperLU beyond)."""
+    """LU of one G_x block (dense LAPACK for n_x <= DENSE_MAX, SuperLU beyond)."""
 
     def __init__(self, Gx):
         self.n = Gx.shape[0]
-        if self.n <= 3000:
+        if self.n <= DENSE_MAX:
             self.lu = sla.lu_factor(Gx.toarray())
             self.sparse = False
         else:

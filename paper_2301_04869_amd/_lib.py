@@ -54,7 +54,8 @@ class Network(ctypes.Structure):
 
 
 class Options(ctypes.Structure):
-    _fields_ = [("col_tile", ctypes.c_int), ("device", ctypes.c_int), ("variant", ctypes.c_int)]
+    _fields_ = [("col_tile", ctypes.c_int), ("device", ctypes.c_int), ("variant", ctypes.c_int),
+                ("scen_per_group", ctypes.c_int), ("chain_rows", ctypes.c_int)]
 
 
 class Dims(ctypes.Structure):
@@ -70,7 +71,10 @@ class Dims(ctypes.Structure):
                 ("col_tile", ctypes.c_int), ("workspace_bytes", ctypes.c_longlong),
                 ("variant", ctypes.c_int), ("lds_reduce", ctypes.c_int),
                 ("lds_group", ctypes.c_int), ("scen_per_group", ctypes.c_int),
-                ("lds_step", ctypes.c_int), ("chain_rows", ctypes.c_int)]
+                ("lds_step", ctypes.c_int), ("chain_rows", ctypes.c_int),
+                ("nnz_kxx", ctypes.c_longlong), ("nnz_kxu", ctypes.c_longlong),
+                ("nnz_kuu", ctypes.c_longlong), ("idx_bytes", ctypes.c_longlong),
+                ("n_load", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -226,16 +230,18 @@ class Handle:
             self.ptr = None
 
 
-def rkkt_analyze(net, n_scen, col_tile=0, variant=0):
+def rkkt_analyze(net, n_scen, col_tile=0, variant=0, scen_per_group=0, chain_rows=0):
     s, keep = _host_network(net)
     d = Dims()
     _check(lib().rkkt_analyze(ctypes.byref(s), int(n_scen),
-                              ctypes.byref(Options(col_tile, 0, variant)), ctypes.byref(d)))
+                              ctypes.byref(Options(col_tile, 0, variant, scen_per_group, chain_rows)),
+                              ctypes.byref(d)))
     return d.as_dict()
 
 
-def rkkt_create(net, pd, qd, col_tile=0, device=0, variant=0):
-    """pd, qd: host [N][n_load] arrays (scenario-major)."""
+def rkkt_create(net, pd, qd, col_tile=0, device=0, variant=0, scen_per_group=0, chain_rows=0):
+    """pd, qd: host [N][n_load] arrays (scenario-major); the launch-shape
+    options of rkkt_options (0 = automatic)."""
     s, keep = _host_network(net)
     pd = np.ascontiguousarray(pd, dtype=np.float64)
     qd = np.ascontiguousarray(qd, dtype=np.float64)
@@ -244,7 +250,8 @@ def rkkt_create(net, pd, qd, col_tile=0, device=0, variant=0):
     h = ctypes.c_void_p()
     _check(lib().rkkt_create(ctypes.byref(s), pd.shape[0], pd.ctypes.data_as(c_dbl_p),
                              qd.ctypes.data_as(c_dbl_p),
-                             ctypes.byref(Options(col_tile, device, variant)),
+                             ctypes.byref(Options(col_tile, device, variant, scen_per_group,
+                                                  chain_rows)),
                              ctypes.byref(h)))
     d = Dims()
     _check(lib().rkkt_dims_get(h, ctypes.byref(d)), h)
@@ -267,12 +274,12 @@ def rkkt_analyze_lu(net, n_scen, col_tile=0):
 SCHEDULES = ("reduce_up", "reduce_down", "step_up", "step_down", "refactor")
 
 
-def rkkt_analyze_schedule(net, n_scen, which, col_tile=0, variant=0):
+def rkkt_analyze_schedule(net, n_scen, which, col_tile=0, variant=0, scen_per_group=0, chain_rows=0):
     """Host-only export of a level-sliced schedule: dict with nphase, slots,
     ptr [nphase*slots+1], ent [n_ent][4], chain_rows, chain_pos [t][t]."""
     s, keep = _host_network(net)
     w = SCHEDULES.index(which) if isinstance(which, str) else int(which)
-    o = Options(col_tile, 0, variant)
+    o = Options(col_tile, 0, variant, scen_per_group, chain_rows)
     nph, sl, ne, ct, nu_ = (ctypes.c_int() for _ in range(5))
     L = lib()
     _check(L.rkkt_analyze_schedule(ctypes.byref(s), int(n_scen), ctypes.byref(o), w, ctypes.byref(nph),
@@ -292,7 +299,8 @@ def rkkt_analyze_schedule(net, n_scen, which, col_tile=0, variant=0):
 
 
 def rkkt_autotune(net, pd, qd, reps=5, device=0):
-    """Returns ({"col_tile", "variant"} of the fastest shape, mean condense ms)."""
+    """Returns (the fastest launch shape as rkkt_create keyword arguments,
+    its mean time of one hot-path pass in ms)."""
     s, keep = _host_network(net)
     pd = np.ascontiguousarray(pd, dtype=np.float64)
     qd = np.ascontiguousarray(qd, dtype=np.float64)
@@ -301,7 +309,8 @@ def rkkt_autotune(net, pd, qd, reps=5, device=0):
     _check(lib().rkkt_autotune(ctypes.byref(s), pd.shape[0], pd.ctypes.data_as(c_dbl_p),
                                qd.ctypes.data_as(c_dbl_p), ctypes.byref(Options(0, device, 0)),
                                int(reps), ctypes.byref(best), ctypes.byref(ms)))
-    return {"col_tile": best.col_tile, "variant": best.variant}, ms.value
+    return ({"col_tile": best.col_tile, "variant": best.variant, "scen_per_group": best.scen_per_group,
+             "chain_rows": best.chain_rows}, ms.value)
 
 
 def rkkt_dims_get(p):

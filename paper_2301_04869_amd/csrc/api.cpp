@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "device.h"
@@ -45,12 +46,13 @@ hipError_t upload(rkkt_problem* p, const T** out, const std::vector<T>& v) {
   T* ptr = nullptr;
   hipError_t e = dalloc(p, &ptr, v.size());
   if (e != hipSuccess) return e;
+  if (std::is_integral<T>::value) p->idx_bytes += (long long)(v.size() * sizeof(T));
   if (!v.empty()) e = hipMemcpy(ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
   *out = ptr;
   return e;
 }
 
-void fill_dims(const rkkt::Sym& s, rkkt_dims* o, long long bytes) {
+void fill_dims(const rkkt::Sym& s, rkkt_dims* o, long long bytes, long long idx_bytes) {
   std::memset(o, 0, sizeof(*o));
   o->n_x = s.nx; o->n_u = s.nu; o->m = s.m; o->n_scen = s.N;
   o->n_bus = s.nb; o->n_line = s.nl; o->n_gen = s.ng;
@@ -75,6 +77,17 @@ void fill_dims(const rkkt::Sym& s, rkkt_dims* o, long long bytes) {
   o->lds_step = s.lds_step ? 1 : 0;
   o->chain_rows = s.chain_t;
   o->scen_per_group = s.spw;
+  for (int r = 0; r < s.nz; ++r) {
+    const long long nxc = s.k_usplit[r] - s.k_ptr[r], nuc = s.k_ptr[r + 1] - s.k_usplit[r];
+    if (r < s.nx) {
+      o->nnz_kxx += nxc;
+      o->nnz_kxu += nuc;
+    } else {
+      o->nnz_kuu += nuc;
+    }
+  }
+  o->idx_bytes = idx_bytes;
+  o->n_load = s.nload;
 }
 
 // Appends the entries of a level-sliced schedule packed as two words of
@@ -127,9 +140,9 @@ extern "C" {
 int rkkt_analyze(const rkkt_network* net, int n_scen, const rkkt_options* opt, rkkt_dims* out) {
   if (!net || !out) return fail(nullptr, RKKT_ERR_ARG, "rkkt_analyze: null argument");
   rkkt::Sym s;
-  std::string m = rkkt::build_symbolic(*net, n_scen, opt ? opt->col_tile : 0, opt ? opt->variant : 0, s);
+  std::string m = rkkt::build_symbolic(*net, n_scen, opt, s);
   if (!m.empty()) return fail(nullptr, RKKT_ERR_ARG, "rkkt_analyze: " + m);
-  fill_dims(s, out, 0);
+  fill_dims(s, out, 0, 0);
   return RKKT_OK;
 }
 
@@ -137,7 +150,7 @@ int rkkt_analyze_lu(const rkkt_network* net, int n_scen, const rkkt_options* opt
                     int* f_ptr, int* f_col) {
   if (!net || !perm || !f_ptr || !f_col) return fail(nullptr, RKKT_ERR_ARG, "rkkt_analyze_lu: null argument");
   rkkt::Sym s;
-  std::string m = rkkt::build_symbolic(*net, n_scen, opt ? opt->col_tile : 0, opt ? opt->variant : 0, s);
+  std::string m = rkkt::build_symbolic(*net, n_scen, opt, s);
   if (!m.empty()) return fail(nullptr, RKKT_ERR_ARG, "rkkt_analyze_lu: " + m);
   std::memcpy(perm, s.perm.data(), s.perm.size() * sizeof(int));
   std::memcpy(f_ptr, s.f_ptr.data(), s.f_ptr.size() * sizeof(int));
@@ -151,7 +164,7 @@ int rkkt_analyze_schedule(const rkkt_network* net, int n_scen, const rkkt_option
   if (!net || !nphase || !slots || !n_ent || !chain_rows || which < 0 || which > 4)
     return fail(nullptr, RKKT_ERR_ARG, "rkkt_analyze_schedule: bad argument");
   rkkt::Sym s;
-  std::string m = rkkt::build_symbolic(*net, n_scen, opt ? opt->col_tile : 0, opt ? opt->variant : 0, s);
+  std::string m = rkkt::build_symbolic(*net, n_scen, opt, s);
   if (!m.empty()) return fail(nullptr, RKKT_ERR_ARG, "rkkt_analyze_schedule: " + m);
   const rkkt::Sched* sc[5] = {&s.red_up, &s.red_dn, &s.stp_up, &s.stp_dn, &s.fac};
   const rkkt::Sched& q = *sc[which];
@@ -175,7 +188,7 @@ int rkkt_create(const rkkt_network* net, int n_scen, const double* pd, const dou
   if (net->n_load > 0 && (!pd || !qd)) return fail(nullptr, RKKT_ERR_ARG, "rkkt_create: null loads");
   rkkt_problem* p = new rkkt_problem();
   p->device = opt ? opt->device : 0;
-  std::string m = rkkt::build_symbolic(*net, n_scen, opt ? opt->col_tile : 0, opt ? opt->variant : 0, p->sym);
+  std::string m = rkkt::build_symbolic(*net, n_scen, opt, p->sym);
   if (!m.empty()) {
     delete p;
     return fail(nullptr, RKKT_ERR_ARG, "rkkt_create: " + m);
@@ -411,7 +424,7 @@ int rkkt_set_line_status(rkkt_problem* p, const double* status_dev, hipStream_t 
 
 int rkkt_dims_get(const rkkt_problem* p, rkkt_dims* out) {
   if (!p || !out) return fail(nullptr, RKKT_ERR_ARG, "rkkt_dims_get: null argument");
-  fill_dims(p->sym, out, p->bytes);
+  fill_dims(p->sym, out, p->bytes, p->idx_bytes);
   return RKKT_OK;
 }
 
@@ -602,8 +615,6 @@ int rkkt_graph_launch(rkkt_problem* p, hipStream_t stream) {
 }
 
 struct rkkt_batch {
-  std::vector<hipStream_t> streams;
-  std::vector<hipEvent_t> events;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
 };
@@ -612,151 +623,187 @@ int rkkt_batch_destroy(rkkt_batch* b) {
   if (!b) return RKKT_OK;
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
-  for (hipEvent_t e : b->events) (void)hipEventDestroy(e);
-  for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
   delete b;
   return RKKT_OK;
 }
 
+// Every instance's pass is captured alone, by rkkt_graph_capture on its own
+// handle (one capture stream, the pass's own fork to the handle's side
+// stream), and the batch graph holds those graphs as child-graph nodes with
+// no edges between them: one launch replays all passes as independent
+// branches.  No capture ever spans more than one handle's streams.
 int rkkt_batch_create(rkkt_problem* const* problems, const rkkt_iteration* its, int n,
                       rkkt_batch** out) {
   if (!problems || !its || !out || n < 1) return fail(nullptr, RKKT_ERR_ARG, "rkkt_batch_create: bad argument");
   *out = nullptr;
-  for (int i = 0; i < n; ++i)
+  for (int i = 0; i < n; ++i) {
     if (!problems[i]) return fail(nullptr, RKKT_ERR_ARG, "rkkt_batch_create: null handle");
+    for (int j = 0; j < i; ++j)
+      if (problems[j] == problems[i])
+        return fail(nullptr, RKKT_ERR_ARG,
+                    "rkkt_batch_create: instance " + std::to_string(i) + " repeats the handle of instance " +
+                        std::to_string(j) + " (passes of one handle share its workspace)");
+  }
   (void)hipGetLastError();
   rkkt_batch* b = new rkkt_batch();
-  hipError_t e = hipSuccess;
-  b->streams.resize(n + 1, nullptr);
-  b->events.resize(n + 1, nullptr);
-  for (int i = 0; i <= n && e == hipSuccess; ++i) {
-    e = hipStreamCreateWithFlags(&b->streams[i], hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->events[i], hipEventDisableTiming);
-  }
+  hipError_t e = hipGraphCreate(&b->graph, 0);
   if (e != hipSuccess) {
     rkkt_batch_destroy(b);
-    return hip_fail(nullptr, e, "rkkt_batch_create: streams");
+    return hip_fail(nullptr, e, "rkkt_batch_create: graph");
   }
-  hipStream_t root = b->streams[n];
-  e = hipStreamBeginCapture(root, hipStreamCaptureModeThreadLocal);
-  if (e != hipSuccess) { rkkt_batch_destroy(b); return hip_fail(nullptr, e, "rkkt_batch_create: begin"); }
-  int rc = RKKT_OK;
-  e = hipEventRecord(b->events[n], root);
-  for (int i = 0; i < n && e == hipSuccess && rc == RKKT_OK; ++i) {
-    e = hipStreamWaitEvent(b->streams[i], b->events[n], 0);
-    if (e != hipSuccess) break;
-    const bool prof = problems[i]->prof;
-    problems[i]->prof = false;
-    // the instances are concurrent branches already; each pass stays on its
-    // instance's stream (no second level of forked streams in the capture)
-    rc = iterate_impl(problems[i], &its[i], b->streams[i], false);
-    problems[i]->prof = prof;
-    if (rc != RKKT_OK) break;
-    e = hipEventRecord(b->events[i], b->streams[i]);
-    if (e == hipSuccess) e = hipStreamWaitEvent(root, b->events[i], 0);
+  for (int i = 0; i < n; ++i) {
+    const int rc = rkkt_graph_capture(problems[i], &its[i]);
+    if (rc != RKKT_OK) {
+      const std::string msg = problems[i]->err;
+      rkkt_batch_destroy(b);
+      return fail(nullptr, rc, "rkkt_batch_create: instance " + std::to_string(i) + ": " + msg);
+    }
+    hipGraphNode_t node = nullptr;
+    e = hipGraphAddChildGraphNode(&node, b->graph, nullptr, 0, problems[i]->graph);
+    if (e != hipSuccess) {
+      rkkt_batch_destroy(b);
+      return hip_fail(nullptr, e, ("rkkt_batch_create: child graph of instance " + std::to_string(i)).c_str());
+    }
   }
-  hipGraph_t g = nullptr;
-  hipError_t e2 = hipStreamEndCapture(root, &g);
-  b->graph = g;
-  if (rc != RKKT_OK) {
-    std::string msg = problems[0]->err;
+  e = hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
     rkkt_batch_destroy(b);
-    return fail(nullptr, rc, "rkkt_batch_create: " + msg);
+    return hip_fail(nullptr, e, "rkkt_batch_create: instantiate");
   }
-  if (e == hipSuccess) e = e2;
-  if (e == hipSuccess) e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
-  if (e != hipSuccess) { rkkt_batch_destroy(b); return hip_fail(nullptr, e, "rkkt_batch_create: capture"); }
   *out = b;
   return RKKT_OK;
 }
 
+// Launch-shape autotuner.  Stage 1 times `reps` condense calls (the
+// reduction dominates them) for every reduction variant x column tile; stage
+// 2 keeps the winner's variant and tile and times `reps` whole passes
+// (rkkt_iterate) for every level-schedule grouping: scenarios per
+// refactorisation / step workgroup (automatic, 1, 2, 4) x chain of
+// single-row levels (automatic, none).  Candidates whose analysis lands on
+// a shape already timed are skipped.
 int rkkt_autotune(const rkkt_network* net, int n_scen, const double* pd, const double* qd,
                   const rkkt_options* opt, int reps, rkkt_options* best, double* best_ms) {
   if (!net || !best || !best_ms || reps < 1)
     return fail(nullptr, RKKT_ERR_ARG, "rkkt_autotune: bad argument");
   rkkt::Sym s0;
-  std::string m = rkkt::build_symbolic(*net, n_scen, 0, 0, s0);
+  std::string m = rkkt::build_symbolic(*net, n_scen, nullptr, s0);
   if (!m.empty()) return fail(nullptr, RKKT_ERR_ARG, "rkkt_autotune: " + m);
   const int N = n_scen, nx = s0.nx, nu = s0.nu, mm = s0.m;
-  std::vector<std::pair<int, int>> cands;  // (variant, col_tile request)
+  const rkkt_options base = opt ? *opt : rkkt_options{};
+  std::vector<rkkt_options> stage1;
   const double stacked_bytes = 2.0 * 8.0 * N * (double)s0.nz * s0.nu_pad;
   for (int v : {1, 2}) {
     if (v == 2 && stacked_bytes > 4.0 * (1ull << 30)) continue;
-    cands.push_back({v, 0});
-    for (int w : {8, 16, 32, 64})
-      if (w <= nu) cands.push_back({v, w});
+    for (int w : {0, 8, 16, 32, 64}) {
+      if (w > nu) continue;
+      rkkt_options o = base;
+      o.variant = v;
+      o.col_tile = w;
+      o.scen_per_group = 0;
+      o.chain_rows = 0;
+      stage1.push_back(o);
+    }
   }
-  // fixed interior point (host), copied once
-  std::vector<double> hx((size_t)N * nx), hu(nu), hz((size_t)N * mm, 0.0), hy((size_t)N * nx, 0.0);
+  // fixed interior point (host), copied once; residuals all ones
+  const size_t NX = (size_t)N * nx, NM = (size_t)N * mm, NU = (size_t)N * nu;
+  std::vector<double> hx(NX), hu(nu), zeros_m(NM, 0.0), zeros_x(NX, 0.0);
   for (int k = 0; k < N; ++k)
     for (int i = 0; i < nx; ++i) hx[(size_t)k * nx + i] = i < s0.nb - 1 ? 0.0 : 1.0;
   for (int c = 0; c < nu; ++c) hu[c] = c < s0.ng ? 1.0 : 0.5 * (s0.ul[c] + s0.uu[c]);
-  std::vector<double> ones_x((size_t)N * nx, 1.0), ones_u(nu, 1.0), ones_s((size_t)N * mm, 1.0);
+  std::vector<double> ones(std::max({NX, NM, (size_t)nu}), 1.0);
   double* buf = nullptr;
-  const size_t nbuf = 3 * (size_t)N * nx + 2 * (size_t)N * mm + 2 * nu + (size_t)N * (1 + nx + nu + mm) +
-                      (size_t)N * nu + (size_t)nu * nu;
-  hipError_t e = hipMalloc((void**)&buf, nbuf * sizeof(double));
+  const size_t nbuf = 6 * NX + 6 * NM + 5 * (size_t)nu + N + NU + 2 * (size_t)nu * nu;
+  hipError_t e = hipMalloc((void**)&buf, nbuf * sizeof(double) + sizeof(int));
   if (e != hipSuccess) return hip_fail(nullptr, e, "rkkt_autotune: buffers");
-  double* p = buf;
-  auto take = [&](size_t n) { double* q = p; p += n; return q; };
-  double *dx = take((size_t)N * nx), *dy = take((size_t)N * nx), *dsx = take((size_t)N * nx);
-  double *dz = take((size_t)N * mm), *dss = take((size_t)N * mm), *du = take(nu), *dsu = take(nu);
-  double *f = take(N), *gx = take((size_t)N * nx), *gu = take((size_t)N * nu), *g = take((size_t)N * nx);
-  double *h = take((size_t)N * mm), *kh = take((size_t)nu * nu);
-  auto up = [&](double* d, const std::vector<double>& v) {
-    return hipMemcpy(d, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice);
+  double* q = buf;
+  auto take = [&](size_t n) { double* r = q; q += n; return r; };
+  rkkt_iteration it{};
+  double *dx = take(NX), *dy = take(NX), *dsx = take(NX), *r1x = take(NX), *r3 = take(NX);
+  double *dz = take(NM), *dss = take(NM), *r2 = take(NM), *r4 = take(NM);
+  double *du = take(nu), *dsu = take(nu), *r1u = take(nu);
+  it.x = dx; it.u = du; it.y = dy; it.z = dz; it.obj_weight = 1.0 / N;
+  it.f = take(N); it.grad_x = take(NX); it.grad_u = take(NU); it.g = take(NX); it.h = take(NM);
+  it.sigma_x = dsx; it.sigma_u = dsu; it.sigma_s = dss; it.delta_w = 1.0;
+  it.khat = take((size_t)nu * nu); it.chol = take((size_t)nu * nu);
+  it.r1x = r1x; it.r1u = r1u; it.r2 = r2; it.r3 = r3; it.r4 = r4;
+  it.px = take(NX); it.pu = take(nu); it.ps = take(NM); it.py = take(NX); it.pz = take(NM);
+  it.info = reinterpret_cast<int*>(q);
+  auto up = [&](double* d, const double* v, size_t n) {
+    return hipMemcpy(d, v, n * sizeof(double), hipMemcpyHostToDevice);
   };
-  e = up(dx, hx);
-  if (e == hipSuccess) e = up(dy, hy);
-  if (e == hipSuccess) e = up(dz, hz);
-  if (e == hipSuccess) e = up(du, hu);
-  if (e == hipSuccess) e = up(dsx, ones_x);
-  if (e == hipSuccess) e = up(dss, ones_s);
-  if (e == hipSuccess) e = up(dsu, ones_u);
+  for (auto pr : {std::make_pair(dx, hx.data()), std::make_pair(du, hu.data())})
+    if (e == hipSuccess) e = up(pr.first, pr.second, pr.first == dx ? NX : nu);
+  if (e == hipSuccess) e = up(dy, zeros_x.data(), NX);
+  if (e == hipSuccess) e = up(dz, zeros_m.data(), NM);
+  for (double* d : {dsx, r1x, r3})
+    if (e == hipSuccess) e = up(d, ones.data(), NX);
+  for (double* d : {dss, r2, r4})
+    if (e == hipSuccess) e = up(d, ones.data(), NM);
+  for (double* d : {dsu, r1u})
+    if (e == hipSuccess) e = up(d, ones.data(), nu);
   hipEvent_t t0 = nullptr, t1 = nullptr;
   if (e == hipSuccess) e = hipEventCreate(&t0);
   if (e == hipSuccess) e = hipEventCreate(&t1);
-  rkkt_options bopt = opt ? *opt : rkkt_options{0, 0, 0};
-  double bms = 1e300;
   int rc = RKKT_OK;
-  std::vector<std::pair<int, int>> seen;
-  for (size_t ci = 0; ci < cands.size() && e == hipSuccess && rc == RKKT_OK; ++ci) {
-    rkkt_options o = opt ? *opt : rkkt_options{0, 0, 0};
-    o.variant = cands[ci].first;
-    o.col_tile = cands[ci].second;
-    rkkt_problem* q = nullptr;
-    rc = rkkt_create(net, n_scen, pd, qd, &o, &q);
-    if (rc != RKKT_OK) break;
-    const std::pair<int, int> got{q->sym.variant, q->sym.col_tile};
-    if (std::find(seen.begin(), seen.end(), got) != seen.end()) {
-      rkkt_destroy(q);
-      continue;
+  // times `reps` condense calls (whole = false) or passes (whole = true) of
+  // one shape; returns the mean ms (1e300 when the shape was seen already)
+  std::vector<std::vector<int>> seen;
+  auto time_shape = [&](const rkkt_options& o, bool whole, rkkt_options* got) -> double {
+    rkkt_problem* h = nullptr;
+    rc = rkkt_create(net, n_scen, pd, qd, &o, &h);
+    if (rc != RKKT_OK) return 1e300;
+    const rkkt::Sym& sy = h->sym;
+    const std::vector<int> key{whole ? 1 : 0, sy.variant, sy.col_tile, sy.spw, sy.chain_t};
+    if (std::find(seen.begin(), seen.end(), key) != seen.end()) {
+      rkkt_destroy(h);
+      return 1e300;
     }
-    seen.push_back(got);
-    rc = rkkt_evaluate(q, dx, du, dy, dz, 1.0 / N, f, gx, gu, g, h, nullptr);
-    if (rc == RKKT_OK) rc = rkkt_condense(q, dsx, dsu, dss, 1.0, kh, nullptr);
+    seen.push_back(key);
+    *got = o;
+    got->variant = sy.variant;
+    got->col_tile = sy.col_tile;
+    float ms = 0.f;
+    rc = rkkt_evaluate(h, dx, du, dy, dz, it.obj_weight, it.f, it.grad_x, it.grad_u, it.g, it.h, nullptr);
+    auto one = [&]() {
+      return whole ? rkkt_iterate(h, &it, nullptr)
+                   : rkkt_condense(h, dsx, dsu, dss, 1.0, it.khat, nullptr);
+    };
+    if (rc == RKKT_OK) rc = one();
     if (rc == RKKT_OK) e = hipEventRecord(t0, nullptr);
-    for (int r = 0; r < reps && rc == RKKT_OK && e == hipSuccess; ++r)
-      rc = rkkt_condense(q, dsx, dsu, dss, 1.0, kh, nullptr);
+    for (int r = 0; r < reps && rc == RKKT_OK && e == hipSuccess; ++r) rc = one();
     if (rc == RKKT_OK && e == hipSuccess) e = hipEventRecord(t1, nullptr);
     if (rc == RKKT_OK && e == hipSuccess) e = hipEventSynchronize(t1);
-    float ms = 0.f;
     if (rc == RKKT_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
-    if (rc == RKKT_OK && e == hipSuccess && ms / reps < bms) {
-      bms = ms / reps;
-      bopt.variant = got.first;
-      bopt.col_tile = got.second;
-    }
-    if (rc != RKKT_OK) g_err = q->err;
-    rkkt_destroy(q);
+    if (rc != RKKT_OK) g_err = h->err;
+    rkkt_destroy(h);
+    return (rc == RKKT_OK && e == hipSuccess) ? ms / reps : 1e300;
+  };
+  rkkt_options b1 = base;
+  double ms1 = 1e300;
+  for (size_t ci = 0; ci < stage1.size() && e == hipSuccess && rc == RKKT_OK; ++ci) {
+    rkkt_options got{};
+    const double ms = time_shape(stage1[ci], false, &got);
+    if (ms < ms1) { ms1 = ms; b1 = got; }
   }
+  rkkt_options b2 = b1;
+  double ms2 = 1e300;
+  for (int spw : {0, 1, 2, 4})
+    for (int chain : {0, -1}) {
+      if (e != hipSuccess || rc != RKKT_OK) break;
+      rkkt_options o = b1;
+      o.scen_per_group = spw;
+      o.chain_rows = chain;
+      rkkt_options got{};
+      const double ms = time_shape(o, true, &got);
+      if (ms < ms2) { ms2 = ms; b2 = got; }
+    }
   if (t0) (void)hipEventDestroy(t0);
   if (t1) (void)hipEventDestroy(t1);
   (void)hipFree(buf);
   if (rc != RKKT_OK) return fail(nullptr, rc, "rkkt_autotune: " + g_err);
   if (e != hipSuccess) return hip_fail(nullptr, e, "rkkt_autotune");
-  *best = bopt;
-  *best_ms = bms;
+  *best = b2;
+  *best_ms = ms2;
   return RKKT_OK;
 }
 

@@ -16,6 +16,7 @@ struct rkkt_problem {
   int device = 0;
   std::vector<void*> allocs;
   long long bytes = 0;
+  long long idx_bytes = 0;  // of which shared index arrays
   std::string err;
   // stage timing (rkkt_profile_begin / rkkt_profile_end)
   bool prof = false;

@@ -248,11 +248,12 @@ std::string build_fac_sched(const Sym& s, int S, Sched& out, std::vector<int>& u
 // one with the fewest barrier-separated phases, counting a chain step as an
 // eighth of a phase.  chain_pos[a t + b] is the position of (c0 + a, c0 + b)
 // in the filled pattern, -1 where structurally zero.
-void find_chain(Sym& s) {
+void find_chain(Sym& s, int chain_req) {
   const int nx = s.nx;
   int best_t = 0;
   double best = 1e300;
-  for (int t = 0; t <= kChainMax && t <= nx; ++t) {
+  const int tmax = chain_req > 0 ? chain_req : chain_req < 0 ? 0 : kChainMax;
+  for (int t = 0; t <= tmax && t <= nx; ++t) {
     const double cost = (double)phase_groups_t(s, true, t).size() + (double)phase_groups_t(s, false, t).size() +
                         t / 8.0;
     if (cost < best - 1e-9) { best = cost; best_t = t; }
@@ -282,8 +283,11 @@ LdsSizes lds_sizes(const Sym& s, int w, int variant, int spw) {
   return z;
 }
 
-std::string build_symbolic(const rkkt_network& net, int N, int col_tile_req, int variant_req,
-                           Sym& s) {
+std::string build_symbolic(const rkkt_network& net, int N, const rkkt_options* opt, Sym& s) {
+  const int col_tile_req = opt ? opt->col_tile : 0, variant_req = opt ? opt->variant : 0;
+  const int spw_req = opt ? opt->scen_per_group : 0, chain_req = opt ? opt->chain_rows : 0;
+  if (spw_req != 0 && spw_req != 1 && spw_req != 2 && spw_req != 4) return "scen_per_group must be 0, 1, 2 or 4";
+  if (chain_req < -1 || chain_req > kChainMax) return "chain_rows must be in [-1, 32]";
   char msg[256];
   const int nb = net.n_bus, nl = net.n_line, ng = net.n_gen, nload = net.n_load;
   if (nb < 2 || nl < 1 || ng < 1 || nload < 0 || N < 1) return "bad sizes";
@@ -686,7 +690,7 @@ std::string build_symbolic(const rkkt_network& net, int N, int col_tile_req, int
     }
   }
 
-  find_chain(s);  // depends on the level structure only
+  find_chain(s, chain_req);  // depends on the level structure only
 
   // ---- launch shapes.  Packed 16-bit schedule entries need every index
   // below 2^16, which holds whenever the data they index fits in LDS.
@@ -696,6 +700,7 @@ std::string build_symbolic(const rkkt_network& net, int N, int col_tile_req, int
   // wavefront each, when a scenario's LU values and vectors fit in LDS
   s.spw = 0;
   for (int spw : {4, 2, 1}) {
+    if (spw_req > 0 && spw > spw_req) continue;
     for (int staged : {1, 0}) {
       s.upd_lds = staged;
       if (pack_ok && refactor_lds_bytes(lds_sizes(s, 1, 1, spw)) <= lds_max) {

@@ -112,8 +112,7 @@ struct Sym {
 };
 
 // Returns an empty string on success, else the error message.
-std::string build_symbolic(const rkkt_network& net, int n_scen, int col_tile_req, int variant_req,
-                           Sym& s);
+std::string build_symbolic(const rkkt_network& net, int n_scen, const rkkt_options* opt, Sym& s);
 
 // sizes fixing the LDS layouts, for a tile width
 LdsSizes lds_sizes(const Sym& s, int w, int variant, int spw);

@@ -87,6 +87,45 @@ def cond2(a):
     return float(np.linalg.cond(a))
 
 
+STEP_BLOCKS = ("px", "pu", "ps", "py", "pz")
+EPS = float(np.finfo(float).eps)
+
+
+def step_bar(kappa):
+    """Bar on the relative error of each Newton-step block against the
+    oracle: 1e-10, or 10 eps kappa_2(K_hat) when the reduced matrix's
+    conditioning makes 1e-10 unreachable for any FP64 solve.  Two correct FP64
+    computations of the same step (the oracle's dense augmented LU and its
+    reduced Cholesky) differ per block by at most eps kappa_2(K_hat) on
+    interior-point iterates from first to last (tests/test_oracle_pins.py,
+    test_full_and_reduced_steps_agree_within_the_conditioning_bound)."""
+    return max(1e-10, 10.0 * EPS * kappa)
+
+
+def step_errors(gpu, orc):
+    """Relative 2-norm error of every block and of the concatenated step."""
+    errs = {}
+    for k in STEP_BLOCKS:
+        a, b = np.asarray(gpu[k]).ravel(), np.asarray(orc[k]).ravel()
+        errs[k] = float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+    a = np.concatenate([np.asarray(gpu[k]).ravel() for k in STEP_BLOCKS])
+    b = np.concatenate([np.asarray(orc[k]).ravel() for k in STEP_BLOCKS])
+    errs["all"] = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    return errs
+
+
+def check_step(gpu, orc, kappa, label=""):
+    """Asserts every block (and the concatenation) within step_bar(kappa);
+    prints the errors."""
+    errs = step_errors(gpu, orc)
+    bar = step_bar(kappa)
+    print(f"  step{label}: bar {bar:.1e} (kappa {kappa:.2e}) " +
+          " ".join(f"{k} {v:.2e}" for k, v in errs.items()), flush=True)
+    bad = {k: v for k, v in errs.items() if not v <= bar}
+    assert not bad, (label, bad, bar)
+    return errs
+
+
 def oracle_step(prob, ev, dg, red, dw, it):
     rs = kkt.Resid(it["r1x"], it["r1u"], it["r2"], it["r3"], it["r4"])
     return kkt.newton_reduced(prob, ev, dg, rs, dw, red)
@@ -102,3 +141,25 @@ def instance(name, n_scen=None):
 
 def iterate(inst, seed):
     return random_iterate(inst.net, inst.scen.n_scen, seed)
+
+
+def snapshot_inputs(prob, snap):
+    """GPU inputs (the random_iterate dict layout) from an oracle interior-point
+    snapshot: the iterate, its diagonals and its Newton residuals at the
+    snapshot's barrier parameter."""
+    it = snap["it"]
+    ev = kkt.evaluate(prob, it, snap["wf"])
+    dg = kkt.diagonals(prob, it)
+    rs = kkt.residuals(prob, it, ev, snap["mu"])
+    return dict(x=it.x, u=it.u, y=it.y, z=it.z, obj_weight=snap["wf"], sigma_x=dg.sx,
+                sigma_u=dg.su, sigma_s=dg.ss, r1x=rs.r1x, r1u=rs.r1u, r2=rs.r2, r3=rs.r3, r4=rs.r4)
+
+
+def iter_args(run):
+    """rkkt_iterate / graph arguments of a GpuRun (chol must be set)."""
+    i, o = run.inp, run.out
+    return dict(x=i["x"], u=i["u"], y=i["y"], z=i["z"], obj_weight=run.w, f=run.f, grad_x=run.gx,
+                grad_u=run.gu, g=run.g, h=run.h, sigma_x=i["sigma_x"], sigma_u=i["sigma_u"],
+                sigma_s=i["sigma_s"], delta_w=run.delta_w, khat=run.khat, chol=run.chol,
+                info=run.info, r1x=i["r1x"], r1u=i["r1u"], r2=i["r2"], r3=i["r3"], r4=i["r4"],
+                px=o["px"], pu=o["pu"], ps=o["ps"], py=o["py"], pz=o["pz"])

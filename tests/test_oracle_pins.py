@@ -380,3 +380,125 @@ def test_augmented_residual_vanishes_at_the_newton_step():
     bad["pu"] = st["pu"] * (1 + 1e-6)
     r2, _ = kkt.augmented_residual(prob, ev, dg, rs, dw, bad)
     assert r2 > 1e3 * r
+
+
+# ------------------------------------------- sparse and dense G_x factors
+@pytest.mark.parametrize("n_bus,n_line,n_gen", [(118, 186, 54), (2000, 3000, 300)])
+def test_sparse_and_dense_gx_factors_agree(monkeypatch, n_bus, n_line, n_gen):
+    """The SuperLU branch of the G_x factor (taken when n_x > 3000, as at the
+    9241-bus size) and the dense LAPACK branch give the same solves, plain
+    and transposed, on a grid below and one above the threshold; both solve
+    the system to rounding (residual against the sparse matrix)."""
+    inst = sg.make_instance(n_bus, n_line, n_gen, 1, 4242)
+    prob = kkt.Problem(inst)
+    rng = np.random.default_rng(5)
+    x, u = rand_point(prob.model, rng)
+    Gx, Gu = prob.model.jacobians(x, u, inst.scen.pd[:, 0], inst.scen.qd[:, 0], 0.01)[:2]
+    B = np.concatenate([Gu.toarray()[:, :7], rng.normal(size=(prob.n_x, 3))], axis=1)
+    out = {}
+    for dense_max in (0, 10 ** 9):
+        monkeypatch.setattr(kkt, "DENSE_MAX", dense_max)
+        fac = kkt._GxFactor(Gx)
+        assert fac.sparse == (dense_max == 0)
+        X, Y = fac.solve(B), fac.solve(B, trans=True)
+        scale = spla.norm(Gx, 1) * np.abs(X).max()
+        assert np.abs(Gx @ X - B).max() <= 1e-11 * scale
+        assert np.abs(Gx.T @ Y - B).max() <= 1e-11 * spla.norm(Gx, 1) * np.abs(Y).max()
+        out[dense_max] = (X, Y)
+    for a, b in zip(out[0], out[10 ** 9]):
+        assert np.linalg.norm(a - b) <= 1e-10 * np.linalg.norm(b)
+
+
+def test_reduced_matrix_same_with_sparse_gx_factor(monkeypatch):
+    inst = sg.preset("c1", n_scen=3)
+    prob = kkt.Problem(inst)
+    it = rand_iterate(prob, np.random.default_rng(17))
+    ev = kkt.evaluate(prob, it, 0.01)
+    dg = kkt.diagonals(prob, it)
+    a = kkt.reduced_hessian(prob, ev, dg, 0.5).khat
+    monkeypatch.setattr(kkt, "DENSE_MAX", 0)
+    b = kkt.reduced_hessian(prob, ev, dg, 0.5).khat
+    assert np.linalg.norm(a - b) <= 1e-11 * np.linalg.norm(a)
+
+
+# ------------------------------------------------ bounds of the slack form
+def _network_quantities(md, inst, xk, u, k):
+    """Bus voltages, generator outputs and line flows at a point, written from
+    the network data (textbook pi-line flows of realeval), not from the
+    oracle's h or its bounds."""
+    net = inst.net
+    th = np.zeros(md.nb)
+    v = np.zeros(md.nb)
+    th[md.nonref] = xk[: md.nb - 1]
+    v[md.pq] = xk[md.nb - 1:]
+    v[net.gen_bus] = u[: md.ng]
+    pf, qf, pt, qt = realeval.line_flows(md, th, v)
+    P = np.zeros(md.nb)
+    Q = np.zeros(md.nb)
+    np.add.at(P, net.line_from, pf)
+    np.add.at(P, net.line_to, pt)
+    np.add.at(Q, net.line_from, qf)
+    np.add.at(Q, net.line_to, qt)
+    Pd = np.zeros(md.nb)
+    Qd = np.zeros(md.nb)
+    np.add.at(Pd, net.load_bus, inst.scen.pd[:, k])
+    np.add.at(Qd, net.load_bus, inst.scen.qd[:, k])
+    pg = np.zeros(md.ng)
+    pg[md.gnr] = u[md.ng:]
+    pg[md.gref] = P[md.ref] + Pd[md.ref]
+    qg = Q[net.gen_bus] + Qd[net.gen_bus]
+    return v, pg, qg, pf ** 2 + qf ** 2, pt ** 2 + qt ** 2
+
+
+@pytest.mark.parametrize("name,n_scen", [("c0", None), ("c1", 4)])
+def test_converged_point_respects_the_network_limits(name, n_scen):
+    """The boxes of the slack form (s in [-h_U, -h_L] and the x, u boxes) are
+    the network's limits: at a converged interior point every bus voltage is
+    in [Vmin, Vmax], every generator's active and reactive output in its
+    range and every line end's |S|^2 <= rate^2 (1e-8), and in each family at
+    least one limit is active (1e-6), so a misplaced or mis-signed bound
+    would show."""
+    inst = sg.preset(name, n_scen=n_scen)
+    prob = kkt.Problem(inst)
+    res = ipm.solve(prob)
+    assert res.status == "converged"
+    md, net = prob.model, inst.net
+    slack = {"V": [], "Pg": [], "Qg": [], "flow": []}
+    for k in range(prob.N):
+        v, pg, qg, sf, st = _network_quantities(md, inst, res.it.x[k], res.it.u, k)
+        slack["V"].append(np.concatenate([v - net.vmin, net.vmax - v]))
+        slack["Pg"].append(np.concatenate([pg - net.pmin, net.pmax - pg]))
+        slack["Qg"].append(np.concatenate([qg - net.qmin, net.qmax - qg]))
+        slack["flow"].append(np.concatenate([net.rate ** 2 - sf, net.rate ** 2 - st]))
+    for fam, parts in slack.items():
+        a = np.concatenate(parts)
+        assert a.min() >= -1e-8, fam
+        assert a.min() <= 1e-6, fam
+
+
+# ---------------------------- two FP64 steps and the conditioning of K_hat
+def test_full_and_reduced_steps_agree_within_the_conditioning_bound():
+    """On interior-point iterates from the first to the last (the oracle's own
+    trajectory on the 30-bus grid, Sigma spreading over up to 20 decades near
+    the end), the dense LU solve of the augmented system and the reduced
+    Cholesky solve agree block by block within eps kappa_2(K_hat): the reading
+    of a relative 1e-10 step tolerance when kappa_2(K_hat) eps exceeds it."""
+    prob = kkt.Problem(sg.preset("c0"))
+    res = ipm.solve(prob, snapshot_iters=tuple(range(0, 40, 3)) + (19, 20))
+    assert len(res.history) >= 6
+    eps = np.finfo(float).eps
+    worst = 0.0
+    for h in res.history:
+        it = h["it"]
+        ev = kkt.evaluate(prob, it, h["wf"])
+        dg = kkt.diagonals(prob, it)
+        rs = kkt.residuals(prob, it, ev, h["mu"])
+        red = kkt.reduced_hessian(prob, ev, dg, h["delta_w"])
+        a = kkt.newton_reduced(prob, ev, dg, rs, h["delta_w"], red)
+        b = kkt.newton_full(prob, ev, dg, rs, h["delta_w"])
+        bound = max(1e-12, eps * np.linalg.cond(red.khat))
+        for k in ("px", "pu", "ps", "py", "pz"):
+            e = np.linalg.norm(a[k] - b[k]) / np.linalg.norm(b[k])
+            assert e <= bound, (h["k"], k, e, bound)
+            worst = max(worst, e / bound)
+    assert worst > 0

@@ -53,7 +53,7 @@ def warm_main(args):
     n_tr, n_va, n_te = args.n_train, args.n_val, args.n_test
     inst = sg.preset("c3", n_scen=n_tr + n_va + n_te)
     res = ws.experiment(torch, inst.net, inst.scen.pd, inst.scen.qd, n_train=n_tr, n_val=n_va,
-                        mu0s=(1e-2, 1e-3, 1e-4, 1e-5, 1e-6), steps=args.train_steps,
+                        mu0s=(1e-4, 1e-5, 1e-6, 1e-7, 1e-8), steps=args.train_steps,
                         log=lambda m: print(m, file=sys.stderr, flush=True))
     # training-step rate of the perceptron alone (batch 256), HIP events
     dd = sg.dims(inst.net.n_bus, inst.net.n_line, inst.net.n_gen)
@@ -88,6 +88,8 @@ def warm_main(args):
                       "train_steps": args.train_steps, "mu0_warm": res["mu0_warm"],
                       "validation_mean_iters": res["validation_mean_iters"]},
            "cold_mean_iters": res["cold_mean_iters"], "fallback_rate": res["fallback_rate"],
+           "mean_start_mean_iters": res["mean_start_mean_iters"],
+           "mean_start_fallback_rate": res["mean_start_fallback_rate"],
            "max_rel_obj_diff": res["max_rel_obj_diff"], "cold_solve_seconds": res["cold_solve_seconds"],
            "train_seconds": res["train_seconds"],
            "mlp_train_step_ms": step_ms, "mlp_samples_per_s": 256 / (step_ms * 1e-3),
@@ -164,6 +166,10 @@ def batch_main(args):
            "sequential_ms_per_step": seq_ms, "speedup_vs_sequential": seq_ms / bat_ms,
            "batch_equals_sequential": same}
     print(json.dumps(out), flush=True)
+
+
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def stage_work(d):
@@ -353,6 +359,7 @@ def cpu_baseline(inst, it, dw, budget_s=12.0):
         return nsub * passes / el, passes, el
 
     v, passes, el = timed(cores, ns, budget_s)
+    progress(f"oracle on {cores} threads: {v:.3g} scenario-IPM-iterations/s")
     # the same oracle on one host thread, on a smaller sample
     n1 = 1 if net.n_bus > 1000 else 8
     v1, p1, el1 = timed(1, n1, budget_s / 2)
@@ -376,10 +383,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--seed", type=int, default=2024)
-    ap.add_argument("--n-train", type=int, default=2000, help="warm: training draws")
-    ap.add_argument("--n-val", type=int, default=100, help="warm: validation draws (choice of mu0)")
-    ap.add_argument("--n-test", type=int, default=200, help="warm: held-out draws")
-    ap.add_argument("--train-steps", type=int, default=10000, help="warm: Adam steps")
+    ap.add_argument("--n-train", type=int, default=20000, help="warm: training draws")
+    ap.add_argument("--n-val", type=int, default=200, help="warm: validation draws (choice of mu0)")
+    ap.add_argument("--n-test", type=int, default=2000, help="warm: held-out draws")
+    ap.add_argument("--train-steps", type=int, default=20000, help="warm: Adam steps")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device copies of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -456,6 +463,7 @@ def main():
     torch.cuda.synchronize()
     stages = R.rkkt_profile_end(p)
     eager_ms = e0.elapsed_time(e1) / args.steps
+    progress(f"eager calls timed: {eager_ms:.3f} ms per pass")
     # timed region 2: the same pass captured once and replayed
     iter_args = dict(x=t["x"], u=t["u"], y=t["y"], z=t["z"], obj_weight=w, f=f, grad_x=gx,
                      grad_u=gu, g=g, h=h, sigma_x=t["sigma_x"], sigma_u=t["sigma_u"],
@@ -472,6 +480,7 @@ def main():
     e1.record(stream)
     torch.cuda.synchronize()
     graph_ms = e0.elapsed_time(e1) / args.steps
+    progress(f"graph replays timed: {graph_ms:.3f} ms per pass")
     ms = min(graph_ms, eager_ms)
     value = N / (ms * 1e-3)
     cf_ms = sum(stages[s][0] for s in ("condense_values", "refactor", "reduce", "stacked_product",
@@ -530,6 +539,7 @@ def main():
         e1.record(stream)
         torch.cuda.synchronize()
         pms = e0.elapsed_time(e1) / n_pl
+        progress(f"plain per-scenario form timed: {pms:.3f} ms per iteration")
         out["plain_form"] = {"ms_per_iteration": pms, "value": N / (pms * 1e-3),
                              "unit": "scenario-IPM-iterations/s",
                              "what": "condense launched once per scenario (N = 1 handles), "

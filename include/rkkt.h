@@ -281,6 +281,8 @@ typedef struct {
   int max_iter;    /* < 0 means 200 */
   double mu0;      /* initial barrier parameter; <= 0 means 0.1 */
   int verbose;     /* one line per iteration on stdout */
+  int warm_duals;  /* warm starts: bound multipliers 0 = implied by stationarity at the
+                      start point plus complementarity at mu0, 1 = complementarity only */
 } rkkt_ipm_options;
 
 typedef struct {
@@ -302,7 +304,14 @@ int rkkt_solve(rkkt_problem* p, const rkkt_ipm_options* opt, double* x, double* 
  * multipliers for the objective weighted 1/N (the solver rescales them to its
  * own objective scaling; a cold solve's multipliers convert with the factor
  * 1 / (N res.obj_weight)), and every bound multiplier is set from
- * complementarity at opt->mu0, which is also the starting barrier parameter.
+ * complementarity at opt->mu0, which is also the starting barrier parameter,
+ * plus (opt->warm_duals = 0) the part of the stationarity condition of its
+ * variable that it must carry: with v the derivative of the Lagrangian
+ * without bound terms at the start point (grad f + G^T y + H^T z for x and
+ * u, z for s), the lower-bound multiplier gets max(v, 0) and the upper-bound
+ * multiplier max(-v, 0), so that the start is dual feasible where the
+ * multipliers are right (the slack form's dual condition z = z_L - z_U for
+ * s, and its counterparts for x and u).
  * Device arrays; RKKT_ERR_ARG if any start array is null.
  */
 int rkkt_solve_warm(rkkt_problem* p, const rkkt_ipm_options* opt, const double* x0, const double* u0,

@@ -20,7 +20,7 @@
  * `stream`, allocate nothing (rkkt_mlp_create allocates all workspace for
  * up to batch_max rows) and never synchronise; a handle is used by one stream
  * at a time.  Errors: 0 OK, -1 bad argument (batch > batch_max, null
- * pointer), -2 HIP or BLAS error, -6 out of memory (create); message in
+ * pointer), -2 HIP error, -6 out of memory (create); message in
  * rkkt_mlp_last_error.
  */
 #ifndef RKKT_MLP_H

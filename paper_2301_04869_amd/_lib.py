@@ -92,7 +92,7 @@ class Iteration(ctypes.Structure):
 
 class IpmOptions(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("mu0", ctypes.c_double),
-                ("verbose", ctypes.c_int)]
+                ("verbose", ctypes.c_int), ("warm_duals", ctypes.c_int)]
 
 
 class IpmResult(ctypes.Structure):
@@ -396,7 +396,7 @@ def rkkt_solve(p, x=None, u=None, y=None, z=None, s=None, tol=0.0, max_iter=-1, 
     def opt(t, name, n):
         return ctypes.c_void_p(None) if t is None else _ptr(t, name, n)
     r = IpmResult()
-    _check(lib().rkkt_solve(p.ptr, ctypes.byref(IpmOptions(tol, max_iter, mu0, int(verbose))),
+    _check(lib().rkkt_solve(p.ptr, ctypes.byref(IpmOptions(tol, max_iter, mu0, int(verbose), 0)),
                             opt(x, "x", N * nx), opt(u, "u", nu), opt(y, "y", N * nx),
                             opt(z, "z", N * m), opt(s, "s", N * m), ctypes.byref(r),
                             _stream(stream)), p.ptr)
@@ -406,7 +406,7 @@ def rkkt_solve(p, x=None, u=None, y=None, z=None, s=None, tol=0.0, max_iter=-1, 
 
 
 def rkkt_solve_warm(p, x0, u0, y0, z0, x=None, u=None, y=None, z=None, s=None, tol=0.0, max_iter=-1,
-                    mu0=0.0, verbose=False, stream=None):
+                    mu0=0.0, verbose=False, warm_duals=0, stream=None):
     """Device interior-point solve from a start point (device float64 x0
     [N][n_x], u0 [n_u], y0 [N][n_x], z0 [N][m]; multipliers for the objective
     weighted 1/N).  Returns the result fields as a dict."""
@@ -416,7 +416,8 @@ def rkkt_solve_warm(p, x0, u0, y0, z0, x=None, u=None, y=None, z=None, s=None, t
     def opt(t, name, n):
         return ctypes.c_void_p(None) if t is None else _ptr(t, name, n)
     r = IpmResult()
-    _check(lib().rkkt_solve_warm(p.ptr, ctypes.byref(IpmOptions(tol, max_iter, mu0, int(verbose))),
+    _check(lib().rkkt_solve_warm(p.ptr, ctypes.byref(IpmOptions(tol, max_iter, mu0, int(verbose),
+                                                                int(warm_duals))),
                                  _ptr(x0, "x0", N * nx), _ptr(u0, "u0", nu), _ptr(y0, "y0", N * nx),
                                  _ptr(z0, "z0", N * m), opt(x, "x", N * nx), opt(u, "u", nu),
                                  opt(y, "y", N * nx), opt(z, "z", N * m), opt(s, "s", N * m),

@@ -90,11 +90,13 @@ static int solve_impl(rkkt_problem* p, const rkkt_ipm_options* uopt, const doubl
   const bool warm = x0 != nullptr;
   Opt o;
   int verbose = 0;
+  bool warm_implied = true;
   if (uopt) {
     if (uopt->tol > 0) o.tol = uopt->tol;
     if (uopt->max_iter >= 0) o.max_iter = uopt->max_iter;
     if (uopt->mu0 > 0) o.mu0 = uopt->mu0;
     verbose = uopt->verbose;
+    warm_implied = uopt->warm_duals == 0;
   }
   *res = rkkt_ipm_result{};
   hipError_t e = ipm_workspace(p);
@@ -162,6 +164,10 @@ static int solve_impl(rkkt_problem* p, const rkkt_ipm_options* uopt, const doubl
   double mu = o.mu0;
   double tau = std::max(o.tau_min, 1.0 - mu);
   CR(eval(false, w));
+  if (warm && warm_implied) {
+    rkkt::ipm_resid(d, s, mu, st);
+    rkkt::ipm_warm_implied(d, s, o.mu0, st);
+  }
   rkkt::ipm_resid(d, s, mu, st);
   rkkt::ipm_merit(d, s, false, s.scal, st);
   CK(fetch(4));

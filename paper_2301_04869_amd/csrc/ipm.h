@@ -39,5 +39,6 @@ void ipm_warm_primal(const DP& d, const IpmDev& s, const double* x0, const doubl
                      hipStream_t st);
 void ipm_warm_duals(const DP& d, const IpmDev& s, const double* y0, const double* z0, double mult, double mu0,
                     hipStream_t st);
+void ipm_warm_implied(const DP& d, const IpmDev& s, double mu0, hipStream_t st);
 
 }  // namespace rkkt

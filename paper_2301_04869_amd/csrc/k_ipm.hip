@@ -432,6 +432,40 @@ __global__ void k_warm_duals(DP d, IpmDev s, const double* y0, const double* z0,
   }
 }
 
+// warm start, bound multipliers implied by stationarity (after k_resid with
+// the complementarity multipliers of k_warm_duals): v = the derivative of the
+// Lagrangian without bound terms (dual infeasibility plus the current bound
+// terms), lower multiplier mu0 / gap + max(v, 0), upper mu0 / gap + max(-v, 0)
+__device__ inline void implied_pair(double val, double lo, double hi, double v, double mu0, double* zl,
+                                    double* zu) {
+  *zl = fin(lo) ? mu0 / (val - lo) + fmax(v, 0.0) : 0.0;
+  *zu = fin(hi) ? mu0 / (hi - val) + fmax(-v, 0.0) : 0.0;
+}
+
+__global__ void k_warm_implied(DP d, IpmDev s, double mu0) {
+  const long long nxN = (long long)d.N * d.nx, nmN = (long long)d.N * d.m;
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < nxN) {
+    const int i = (int)(t % d.nx);
+    const double v = s.dx[t] + s.zlx[t] - s.zux[t];
+    implied_pair(s.x[t], s.xl[i], s.xu[i], v, mu0, &s.zlx[t], &s.zux[t]);
+    return;
+  }
+  t -= nxN;
+  if (t < nmN) {
+    const int i = (int)(t % d.m);
+    const double v = s.ds[t] + s.zls[t] - s.zus[t];
+    implied_pair(s.s[t], s.sl[i], s.su[i], v, mu0, &s.zls[t], &s.zus[t]);
+    return;
+  }
+  t -= nmN;
+  if (t < d.nu) {
+    const int c = (int)t;
+    const double v = s.du[c] + s.zlu[c] - s.zuu[c];
+    implied_pair(s.u[c], s.ul[c], s.uu[c], v, mu0, &s.zlu[c], &s.zuu[c]);
+  }
+}
+
 // out[0] = max(max |grad_x f_i|, max |sum_i grad_u f_i|)
 __global__ __launch_bounds__(kRed) void k_grad_max(DP d, IpmDev s, double* out) {
   __shared__ double sh[kRed];
@@ -496,6 +530,11 @@ void ipm_warm_primal(const DP& d, const IpmDev& s, const double* x0, const doubl
                      hipStream_t st) {
   const long long n = (long long)d.N * d.nx + d.nu;
   k_warm_primal<<<grid_for(n), kBlock, 0, st>>>(d, s, x0, u0, k1, k2);
+}
+
+void ipm_warm_implied(const DP& d, const IpmDev& s, double mu0, hipStream_t st) {
+  const long long n = (long long)d.N * (d.nx + d.m) + d.nu;
+  k_warm_implied<<<grid_for(n), kBlock, 0, st>>>(d, s, mu0);
 }
 
 void ipm_warm_duals(const DP& d, const IpmDev& s, const double* y0, const double* z0, double mult, double mu0,

@@ -1,9 +1,31 @@
-// Elementwise and reduction kernels of the warm-start perceptron (the
-// products run on the BLAS library, BF16 in, FP32 accumulation and out).
+// Kernels of the warm-start perceptron: BF16 products on the matrix cores
+// with FP32 accumulation and fused epilogues, the output-layer gradient and
+// loss, and the Adam step.
 //
 // GELU in the erf form, g(a) = a Phi(a) = a (1 + erf(a / sqrt 2)) / 2, with
 // g'(a) = Phi(a) + a phi(a); loss 1/(2B) sum ||y - t||^2, so the output
 // gradient is (y - t) / B; Adam as published by Kingma and Ba.
+//
+// Products.  Every product of a layer is C[m][n] = sum_k A[m][k] B[n][k] with
+// both operands stored k-contiguous in BF16 (row pitch a multiple of 8
+// elements, so 8 consecutive k are one aligned 16-byte load):
+//   forward   Z_l  = A_l W_l + b_l   A = A_l [B][fi],   B = W_l^T [fo][fi]
+//   dW        dW_l = A_l^T dZ_l      A = A_l^T [fi][B], B = dZ_l^T [fo][B]
+//   dA        dA   = dZ_l W_l^T      A = dZ_l [B][fo],  B = W_l [fi][fo]
+// so the parameters keep two BF16 copies per layer (W_l and W_l^T) and the
+// forward and backward epilogues write each activation and output gradient in
+// both orientations.  The transposed activations carry one extra row of ones
+// (row fi of A_l^T): the dW product over fi + 1 rows then also yields the
+// bias gradient, the column sums of dZ_l, in the row that follows W_l in the
+// parameter layout.
+//
+// One wavefront per 32 x 32 output tile, as 2 x 2 blocks of
+// v_mfma_f32_16x16x32_bf16 (A operand: lane holds row lane % 16, k group
+// lane / 16 of 8 consecutive k; B operand: column lane % 16, the same k
+// group; result register r of a lane: row 4 (lane / 16) + r, column
+// lane % 16).  Operands come straight from global memory (each 16-byte
+// fragment is used by two products), the next k step's fragments loaded
+// while the current step's products run.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -12,6 +34,9 @@
 
 namespace rkkt {
 namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kT = 256;
 inline unsigned blocks(long long n) { return (unsigned)((n + kT - 1) / kT); }
@@ -30,82 +55,183 @@ __device__ __forceinline__ float gelu_grad(float a) {
   return 0.5f * (1.0f + erff(a * 0.70710678118654752f)) + a * expf(-0.5f * a * a) * 0.39894228040143268f;
 }
 
-__global__ void k_to_bf16(const float* __restrict__ s, uint16_t* __restrict__ d, long long n) {
-  const long long i = (long long)blockIdx.x * kT + threadIdx.x;
-  if (i < n) d[i] = to_bf16(s[i]);
+// 8 consecutive BF16 values row[kk .. kk + 7], zero from k = K on.  The row's
+// pitch is at least K rounded up to 8, so a granule that starts below K lies
+// inside the row.
+__device__ __forceinline__ uint4 frag8(const uint16_t* __restrict__ row, int kk, int K) {
+  if (kk >= K) return make_uint4(0u, 0u, 0u, 0u);
+  uint4 v = *reinterpret_cast<const uint4*>(row + kk);
+  const int nv = K - kk;
+  if (nv < 8) {
+    uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t lo = 2 * q < nv ? 0x0000ffffu : 0u;
+      const uint32_t hi = 2 * q + 1 < nv ? 0xffff0000u : 0u;
+      w[q] &= lo | hi;
+    }
+    v = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+  return v;
 }
 
-// Z [rows][cols] += b; hidden layers also A = bf16(g(Z)); the output layer
-// also copies Z to y when y is given
-__global__ void k_bias_act(float* __restrict__ Z, const float* __restrict__ b, uint16_t* __restrict__ A,
-                           float* __restrict__ y, int rows, int cols, int act) {
+__device__ __forceinline__ f32x4 mfma(uint4 a, uint4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
+                                                 c, 0, 0, 0);
+}
+
+template <int EPI>
+__global__ __launch_bounds__(64) void k_gemm(MlpGemm g) {
+  const int lane = threadIdx.x;
+  const int m0 = blockIdx.y * 32, n0 = blockIdx.x * 32;
+  const int r16 = lane & 15, kq = (lane >> 4) * 8;
+  const uint16_t* pa[2];
+  const uint16_t* pb[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    pa[i] = g.A + (long long)min(m0 + 16 * i + r16, g.M - 1) * g.lda;
+    pb[i] = g.B + (long long)min(n0 + 16 * i + r16, g.N - 1) * g.ldb;
+  }
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  uint4 a[2], b[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    a[i] = frag8(pa[i], kq, g.K);
+    b[i] = frag8(pb[i], kq, g.K);
+  }
+  for (int k0 = 0; k0 < g.K; k0 += 32) {
+    uint4 an[2], bn[2];
+    const int kn = k0 + 32 + kq;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      an[i] = frag8(pa[i], kn, g.K);
+      bn[i] = frag8(pb[i], kn, g.K);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = mfma(a[i], b[j], acc[i][j]);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      a[i] = an[i];
+      b[i] = bn[i];
+    }
+  }
+  // epilogue: lane holds rows mr .. mr + 3 of column nc in each block
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int mr = m0 + 16 * i + 4 * (lane >> 4);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int nc = n0 + 16 * j + r16;
+      if (nc >= g.N) continue;
+      float v[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) v[r] = acc[i][j][r];
+      uint16_t h[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = mr + r;
+        if (m >= g.M) break;
+        const long long o = (long long)m * g.ldz + nc;
+        if (EPI == kMlpStore) {
+          g.zout[o] = v[r];
+        } else if (EPI == kMlpBiasGelu || EPI == kMlpBiasOut) {
+          const float z = v[r] + g.bias[nc];
+          if (g.zout) g.zout[o] = z;
+          if (EPI == kMlpBiasOut) {
+            if (g.y) g.y[(long long)m * g.N + nc] = z;
+          } else {
+            h[r] = to_bf16(gelu(z));
+            g.hout[(long long)m * g.ldh + nc] = h[r];
+          }
+        } else {  // kMlpGeluBack: dZ_{l-1} = dA g'(Z_{l-1})
+          h[r] = to_bf16(v[r] * gelu_grad(g.zin[o]));
+          g.hout[(long long)m * g.ldh + nc] = h[r];
+        }
+      }
+      if ((EPI == kMlpBiasGelu || EPI == kMlpGeluBack) && g.tout) {
+        uint16_t* t = g.tout + (long long)nc * g.ldt + mr;
+        if (mr + 3 < g.M) {
+          *reinterpret_cast<uint2*>(t) = make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16),
+                                                    (uint32_t)h[2] | ((uint32_t)h[3] << 16));
+        } else {
+          for (int r = 0; r < 4 && mr + r < g.M; ++r) t[r] = h[r];
+        }
+      }
+    }
+  }
+}
+
+// x [rows][cols] FP32 -> BF16 row-major (pitch ldh) and transposed (pitch ldt)
+__global__ void k_input_bf16(const float* __restrict__ x, int rows, int cols, uint16_t* __restrict__ h, int ldh,
+                             uint16_t* __restrict__ t, int ldt) {
   const long long i = (long long)blockIdx.x * kT + threadIdx.x;
   if (i >= (long long)rows * cols) return;
-  const float z = Z[i] + b[i % cols];
-  Z[i] = z;
-  if (act) A[i] = to_bf16(gelu(z));
-  else if (y) y[i] = z;
+  const int r = (int)(i / cols), c = (int)(i % cols);
+  const uint16_t v = to_bf16(x[i]);
+  h[(long long)r * ldh + c] = v;
+  if (t) t[(long long)c * ldt + r] = v;
 }
 
-// dZ = (Y - T) / B (FP32 and BF16), and per-block partial sums of (Y - T)^2
-__global__ void k_out_grad(const float* __restrict__ Y, const float* __restrict__ T, float* __restrict__ dZ,
-                           uint16_t* __restrict__ dZb, float* __restrict__ part, long long n, float inv_b) {
-  __shared__ float red[kT];
-  const long long i = (long long)blockIdx.x * kT + threadIdx.x;
+// one workgroup: dZ = (Y - T) / B in BF16 (row-major and transposed) and the
+// loss 1/(2B) sum (Y - T)^2, summed in a fixed order
+constexpr int kLossT = 1024;
+__global__ __launch_bounds__(kLossT) void k_out_grad(const float* __restrict__ Y, const float* __restrict__ T,
+                                                     int rows, int cols, float inv_b, uint16_t* __restrict__ h,
+                                                     int ldh, uint16_t* __restrict__ t, int ldt,
+                                                     float* __restrict__ loss) {
+  __shared__ float red[kLossT];
+  const long long n = (long long)rows * cols;
   float sq = 0.0f;
-  if (i < n) {
-    const float r = Y[i] - T[i];
-    sq = r * r;
-    const float g = r * inv_b;
-    dZ[i] = g;
-    dZb[i] = to_bf16(g);
+  for (long long i = threadIdx.x; i < n; i += kLossT) {
+    const int r = (int)(i / cols), c = (int)(i % cols);
+    const float d = Y[i] - T[i];
+    sq = fmaf(d, d, sq);
+    const uint16_t v = to_bf16(d * inv_b);
+    h[(long long)r * ldh + c] = v;
+    t[(long long)c * ldt + r] = v;
   }
   red[threadIdx.x] = sq;
   __syncthreads();
-  for (int s = kT / 2; s > 0; s >>= 1) {
+  for (int s = kLossT / 2; s > 0; s >>= 1) {
     if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
-}
-
-// loss = 0.5 inv_b sum of the partials, in a fixed order
-__global__ void k_loss_final(const float* __restrict__ part, int np, float inv_b, float* __restrict__ loss) {
-  __shared__ float red[kT];
-  float s = 0.0f;
-  for (int i = threadIdx.x; i < np; i += kT) s += part[i];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = kT / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x == 0) *loss = 0.5f * inv_b * red[0];
 }
 
-// dZ = dA g'(Z) (FP32 and BF16)
-__global__ void k_act_back(const float* __restrict__ dA, const float* __restrict__ Z, float* __restrict__ dZ,
-                           uint16_t* __restrict__ dZb, long long n) {
-  const long long i = (long long)blockIdx.x * kT + threadIdx.x;
-  if (i >= n) return;
-  const float g = dA[i] * gelu_grad(Z[i]);
-  dZ[i] = g;
-  dZb[i] = to_bf16(g);
+// BF16 copies of parameter i: W_l entries into W_l [fi][pitch fo] and
+// W_l^T [fo][pitch fi], biases nowhere (they stay FP32)
+__device__ __forceinline__ void store_copies(const MlpLayers& L, long long i, float p, uint16_t* __restrict__ wb,
+                                             uint16_t* __restrict__ wt) {
+  for (int l = 0; l < L.n; ++l) {
+    const long long rel = i - L.woff[l];
+    const long long nw = (long long)L.fi[l] * L.fo[l];
+    if (rel >= 0 && rel < nw) {
+      const int r = (int)(rel / L.fo[l]), c = (int)(rel % L.fo[l]);
+      const uint16_t v = to_bf16(p);
+      wb[L.wb_off[l] + (long long)r * L.fo_p[l] + c] = v;
+      wt[L.wt_off[l] + (long long)c * L.fi_p[l] + r] = v;
+      return;
+    }
+  }
 }
 
-// db[c] = sum over rows of dZ[r][c] (rows in order)
-__global__ void k_col_sum(const float* __restrict__ dZ, int rows, int cols, float* __restrict__ db) {
-  const int c = blockIdx.x * kT + threadIdx.x;
-  if (c >= cols) return;
-  float s = 0.0f;
-  for (int r = 0; r < rows; ++r) s += dZ[(long long)r * cols + c];
-  db[c] = s;
+__global__ void k_param_copies(const float* __restrict__ p, long long n, MlpLayers L, uint16_t* __restrict__ wb,
+                               uint16_t* __restrict__ wt) {
+  const long long i = (long long)blockIdx.x * kT + threadIdx.x;
+  if (i < n) store_copies(L, i, p[i], wb, wt);
 }
 
 // Adam on the master parameters, then their BF16 copies
 __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
-                       float* __restrict__ v, uint16_t* __restrict__ pb, long long n, float lr, float b1,
-                       float b2, float c1, float c2, float eps) {
+                       float* __restrict__ v, long long n, float lr, float b1, float b2, float c1, float c2,
+                       float eps, MlpLayers L, uint16_t* __restrict__ wb, uint16_t* __restrict__ wt) {
   const long long i = (long long)blockIdx.x * kT + threadIdx.x;
   if (i >= n) return;
   const float gi = g[i];
@@ -115,41 +241,51 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
   v[i] = vi;
   const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
   p[i] = pi;
-  pb[i] = to_bf16(pi);
+  store_copies(L, i, pi, wb, wt);
+}
+
+__global__ void k_fill_bf16(uint16_t* __restrict__ d, long long n, uint16_t v) {
+  const long long i = (long long)blockIdx.x * kT + threadIdx.x;
+  if (i < n) d[i] = v;
 }
 
 }  // namespace
 
-void mlp_to_bf16(const float* s, uint16_t* d, long long n, hipStream_t st) {
-  k_to_bf16<<<blocks(n), kT, 0, st>>>(s, d, n);
+void mlp_gemm(int epi, const MlpGemm& g, hipStream_t st) {
+  const dim3 grid((unsigned)((g.N + 31) / 32), (unsigned)((g.M + 31) / 32));
+  switch (epi) {
+    case kMlpStore: k_gemm<kMlpStore><<<grid, 64, 0, st>>>(g); break;
+    case kMlpBiasGelu: k_gemm<kMlpBiasGelu><<<grid, 64, 0, st>>>(g); break;
+    case kMlpBiasOut: k_gemm<kMlpBiasOut><<<grid, 64, 0, st>>>(g); break;
+    default: k_gemm<kMlpGeluBack><<<grid, 64, 0, st>>>(g); break;
+  }
 }
 
-void mlp_bias_act(float* Z, const float* b, uint16_t* A, float* y, int rows, int cols, bool act, hipStream_t st) {
-  k_bias_act<<<blocks((long long)rows * cols), kT, 0, st>>>(Z, b, A, y, rows, cols, act ? 1 : 0);
+void mlp_input_bf16(const float* x, int rows, int cols, uint16_t* h, int ldh, uint16_t* t, int ldt,
+                    hipStream_t st) {
+  k_input_bf16<<<blocks((long long)rows * cols), kT, 0, st>>>(x, rows, cols, h, ldh, t, ldt);
 }
 
-int mlp_out_grad_blocks(long long n) { return (int)blocks(n); }
-
-void mlp_out_grad(const float* Y, const float* T, float* dZ, uint16_t* dZb, float* part, float* loss,
-                  long long n, int batch, hipStream_t st) {
-  const float inv_b = 1.0f / (float)batch;
-  k_out_grad<<<blocks(n), kT, 0, st>>>(Y, T, dZ, dZb, part, n, inv_b);
-  k_loss_final<<<1, kT, 0, st>>>(part, (int)blocks(n), inv_b, loss);
+void mlp_out_grad(const float* Y, const float* T, int rows, int cols, uint16_t* h, int ldh, uint16_t* t,
+                  int ldt, float* loss, hipStream_t st) {
+  k_out_grad<<<1, kLossT, 0, st>>>(Y, T, rows, cols, 1.0f / (float)rows, h, ldh, t, ldt, loss);
 }
 
-void mlp_act_back(const float* dA, const float* Z, float* dZ, uint16_t* dZb, long long n, hipStream_t st) {
-  k_act_back<<<blocks(n), kT, 0, st>>>(dA, Z, dZ, dZb, n);
+void mlp_param_copies(const float* p, long long n, const MlpLayers& L, uint16_t* wb, uint16_t* wt,
+                      hipStream_t st) {
+  k_param_copies<<<blocks(n), kT, 0, st>>>(p, n, L, wb, wt);
 }
 
-void mlp_col_sum(const float* dZ, int rows, int cols, float* db, hipStream_t st) {
-  k_col_sum<<<blocks(cols), kT, 0, st>>>(dZ, rows, cols, db);
-}
-
-void mlp_adam(float* p, const float* g, float* m, float* v, uint16_t* pb, long long n, float lr, int t,
-              hipStream_t st) {
+void mlp_adam(float* p, const float* g, float* m, float* v, long long n, float lr, int t, const MlpLayers& L,
+              uint16_t* wb, uint16_t* wt, hipStream_t st) {
   const float b1 = 0.9f, b2 = 0.999f;
   const float c1 = 1.0f - powf(b1, (float)t), c2 = 1.0f - powf(b2, (float)t);
-  k_adam<<<blocks(n), kT, 0, st>>>(p, g, m, v, pb, n, lr, b1, b2, c1, c2, 1e-8f);
+  k_adam<<<blocks(n), kT, 0, st>>>(p, g, m, v, n, lr, b1, b2, c1, c2, 1e-8f, L, wb, wt);
+}
+
+void mlp_fill_bf16(uint16_t* d, long long n, float v, hipStream_t st) {
+  const uint32_t u = __builtin_bit_cast(uint32_t, v);
+  k_fill_bf16<<<blocks(n), kT, 0, st>>>(d, n, (uint16_t)(u >> 16));
 }
 
 }  // namespace rkkt

@@ -1,11 +1,6 @@
 // The warm-start perceptron behind the C ABI of rkkt_mlp.h: workspace,
-// forward pass, backward pass and Adam step.  Products C = op(A) op(B) of
-// row-major BF16 operands with FP32 accumulation and output go to rocBLAS
-// (a row-major product is the column-major product of the transposes, so
-// the operands are passed swapped with their transpose flags unchanged);
-// everything else runs in k_mlp.hip.
-#include <rocblas/rocblas.h>
-
+// forward pass, backward pass and Adam step, all in k_mlp.hip (BF16 products
+// on the matrix cores with FP32 accumulation and fused epilogues).
 #include <algorithm>
 #include <string>
 #include <vector>
@@ -13,19 +8,21 @@
 #include "mlp_dev.h"
 #include "rkkt_mlp.h"
 
+using rkkt::mlp_pad8;
+
 struct rkkt_mlp {
-  int L = 0, bmax = 0;
+  int L = 0, bmax = 0, bpit = 0;      // bpit: batch_max rounded up to 8
   std::vector<int> sz;
   std::vector<long long> woff, boff;  // parameter offsets of W_l, b_l
   long long P = 0;
   float *p = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
-  uint16_t* pb = nullptr;           // BF16 copy of the parameters
-  std::vector<uint16_t*> A;         // A_l [bmax][sz[l]], BF16 (A_0 = input)
-  std::vector<float*> Z;            // Z_l [bmax][sz[l + 1]], FP32 pre-activations
-  float *dZ = nullptr, *dA = nullptr, *part = nullptr;
-  uint16_t* dZb = nullptr;
+  rkkt::MlpLayers lay{};
+  uint16_t *wb = nullptr, *wt = nullptr;  // BF16 W_l [fi][fo_p] and W_l^T [fo][fi_p]
+  std::vector<uint16_t*> A;           // A_l [bmax][pad8(sz[l])], BF16 (A_0 = input)
+  std::vector<uint16_t*> AT;          // A_l^T [sz[l] + 1][bpit], BF16, last row ones
+  std::vector<float*> Z;              // Z_l [bmax][sz[l + 1]], FP32 pre-activations
+  uint16_t *dZb[2] = {nullptr, nullptr}, *dZT[2] = {nullptr, nullptr};  // output gradients, both orientations
   int t = 0;
-  rocblas_handle h = nullptr;
   std::vector<void*> allocs;
   std::string err;
 };
@@ -42,63 +39,92 @@ int fail(rkkt_mlp* m, int code, const std::string& msg) {
 template <typename T>
 hipError_t dalloc(rkkt_mlp* m, T** ptr, long long n) {
   void* q = nullptr;
-  hipError_t e = hipMalloc(&q, (size_t)std::max(n, 1LL) * sizeof(T));
-  if (e == hipSuccess) m->allocs.push_back(q);
+  const size_t bytes = (size_t)std::max(n, 1LL) * sizeof(T);
+  hipError_t e = hipMalloc(&q, bytes);
+  if (e == hipSuccess) {
+    m->allocs.push_back(q);
+    e = hipMemset(q, 0, bytes);
+  }
   *ptr = static_cast<T*>(q);
   return e;
 }
 
-// row-major C [M][N] = op(A) op(B) + beta C, op(A) [M][K], op(B) [K][N]
-rocblas_status rm_gemm(rocblas_handle h, bool ta, bool tb, int M, int N, int K, const uint16_t* A, int lda,
-                       const uint16_t* B, int ldb, float beta, float* C, int ldc) {
-  const float one = 1.0f;
-  return rocblas_gemm_ex(h, tb ? rocblas_operation_transpose : rocblas_operation_none,
-                         ta ? rocblas_operation_transpose : rocblas_operation_none, N, M, K, &one, B,
-                         rocblas_datatype_bf16_r, ldb, A, rocblas_datatype_bf16_r, lda, &beta, C,
-                         rocblas_datatype_f32_r, ldc, C, rocblas_datatype_f32_r, ldc,
-                         rocblas_datatype_f32_r, rocblas_gemm_algo_standard, 0, 0);
-}
-
-int check(rkkt_mlp* m, const char* where, rocblas_status bs = rocblas_status_success) {
-  if (bs != rocblas_status_success)
-    return fail(m, -2, std::string(where) + ": rocBLAS status " + std::to_string((int)bs));
+int check(rkkt_mlp* m, const char* where) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(m, -2, std::string(where) + ": " + hipGetErrorString(e));
   return 0;
 }
 
-int forward_impl(rkkt_mlp* m, const float* x, int B, float* y, hipStream_t st) {
-  rocblas_set_stream(m->h, st);
-  rkkt::mlp_to_bf16(x, m->A[0], (long long)B * m->sz[0], st);
-  for (int l = 0; l < m->L; ++l) {
+// Forward pass over B rows of x.  With `train`, the FP32 pre-activations and
+// the transposed activations (operands of the dW products) are kept;
+// otherwise only y is written.
+int forward_impl(rkkt_mlp* m, const float* x, int B, float* y, bool train, hipStream_t st) {
+  const int L = m->L;
+  rkkt::mlp_input_bf16(x, B, m->sz[0], m->A[0], mlp_pad8(m->sz[0]), train ? m->AT[0] : nullptr, m->bpit, st);
+  for (int l = 0; l < L; ++l) {
     const int fi = m->sz[l], fo = m->sz[l + 1];
-    const rocblas_status bs = rm_gemm(m->h, false, false, B, fo, fi, m->A[l], fi, m->pb + m->woff[l], fo,
-                                      0.0f, m->Z[l], fo);
-    if (int rc = check(m, "rkkt_mlp forward", bs)) return rc;
-    const bool act = l + 1 < m->L;
-    rkkt::mlp_bias_act(m->Z[l], m->p + m->boff[l], act ? m->A[l + 1] : nullptr, act ? nullptr : y, B, fo,
-                       act, st);
+    const bool last = l + 1 == L;
+    rkkt::MlpGemm g{};
+    g.A = m->A[l];
+    g.lda = mlp_pad8(fi);
+    g.B = m->wt + m->lay.wt_off[l];
+    g.ldb = m->lay.fi_p[l];
+    g.M = B;
+    g.N = fo;
+    g.K = fi;
+    g.bias = m->p + m->boff[l];
+    g.zout = train ? m->Z[l] : nullptr;
+    g.ldz = fo;
+    if (!last) {
+      g.hout = m->A[l + 1];
+      g.ldh = mlp_pad8(fo);
+      g.tout = train ? m->AT[l + 1] : nullptr;
+      g.ldt = m->bpit;
+    } else {
+      g.y = y;
+    }
+    rkkt::mlp_gemm(last ? rkkt::kMlpBiasOut : rkkt::kMlpBiasGelu, g, st);
   }
   return check(m, "rkkt_mlp forward");
 }
 
 int gradients_impl(rkkt_mlp* m, const float* x, const float* t, int B, float* loss, hipStream_t st) {
-  if (int rc = forward_impl(m, x, B, nullptr, st)) return rc;
+  if (int rc = forward_impl(m, x, B, nullptr, true, st)) return rc;
   const int L = m->L;
-  const long long nout = (long long)B * m->sz[L];
-  rkkt::mlp_out_grad(m->Z[L - 1], t, m->dZ, m->dZb, m->part, loss, nout, B, st);
+  int c = 0;
+  rkkt::mlp_out_grad(m->Z[L - 1], t, B, m->sz[L], m->dZb[c], mlp_pad8(m->sz[L]), m->dZT[c], m->bpit, loss, st);
   for (int l = L - 1; l >= 0; --l) {
     const int fi = m->sz[l], fo = m->sz[l + 1];
-    // dW_l = A_l^T dZ_l, db_l = column sums of dZ_l
-    rocblas_status bs = rm_gemm(m->h, true, false, fi, fo, B, m->A[l], fi, m->dZb, fo, 0.0f,
-                                m->g + m->woff[l], fo);
-    if (int rc = check(m, "rkkt_mlp backward", bs)) return rc;
-    rkkt::mlp_col_sum(m->dZ, B, fo, m->g + m->boff[l], st);
+    // [dW_l; db_l] = [A_l^T; 1^T] dZ_l: fi + 1 rows, the last one lands on b_l
+    rkkt::MlpGemm gw{};
+    gw.A = m->AT[l];
+    gw.lda = m->bpit;
+    gw.B = m->dZT[c];
+    gw.ldb = m->bpit;
+    gw.M = fi + 1;
+    gw.N = fo;
+    gw.K = B;
+    gw.zout = m->g + m->woff[l];
+    gw.ldz = fo;
+    rkkt::mlp_gemm(rkkt::kMlpStore, gw, st);
     if (l == 0) break;
-    // dA_{l-1} = dZ_l W_l^T, dZ_{l-1} = dA_{l-1} g'(Z_{l-1})
-    bs = rm_gemm(m->h, false, true, B, fi, fo, m->dZb, fo, m->pb + m->woff[l], fo, 0.0f, m->dA, fi);
-    if (int rc = check(m, "rkkt_mlp backward", bs)) return rc;
-    rkkt::mlp_act_back(m->dA, m->Z[l - 1], m->dZ, m->dZb, (long long)B * fi, st);
+    // dZ_{l-1} = (dZ_l W_l^T) g'(Z_{l-1})
+    rkkt::MlpGemm ga{};
+    ga.A = m->dZb[c];
+    ga.lda = mlp_pad8(fo);
+    ga.B = m->wb + m->lay.wb_off[l];
+    ga.ldb = m->lay.fo_p[l];
+    ga.M = B;
+    ga.N = fi;
+    ga.K = fo;
+    ga.zin = m->Z[l - 1];
+    ga.ldz = fi;
+    ga.hout = m->dZb[c ^ 1];
+    ga.ldh = mlp_pad8(fi);
+    ga.tout = m->dZT[c ^ 1];
+    ga.ldt = m->bpit;
+    rkkt::mlp_gemm(rkkt::kMlpGeluBack, ga, st);
+    c ^= 1;
   }
   return check(m, "rkkt_mlp backward");
 }
@@ -115,46 +141,65 @@ extern "C" {
 
 int rkkt_mlp_create(const int* sizes, int n_layers, int batch_max, rkkt_mlp** out) {
   if (!sizes || !out || n_layers < 1 || batch_max < 1) return fail(nullptr, -1, "rkkt_mlp_create: bad argument");
+  if (n_layers > rkkt::kMlpMaxLayers)
+    return fail(nullptr, -1, "rkkt_mlp_create: more than " + std::to_string(rkkt::kMlpMaxLayers) + " layers");
   for (int l = 0; l <= n_layers; ++l)
     if (sizes[l] < 1) return fail(nullptr, -1, "rkkt_mlp_create: layer width < 1");
   *out = nullptr;
   rkkt_mlp* m = new rkkt_mlp();
   m->L = n_layers;
   m->bmax = batch_max;
+  m->bpit = mlp_pad8(batch_max);
   m->sz.assign(sizes, sizes + n_layers + 1);
   int wmax = 0;
+  long long nwb = 0, nwt = 0;
+  m->lay.n = n_layers;
   for (int l = 0; l < n_layers; ++l) {
+    const int fi = m->sz[l], fo = m->sz[l + 1];
     m->woff.push_back(m->P);
-    m->P += (long long)m->sz[l] * m->sz[l + 1];
+    m->P += (long long)fi * fo;
     m->boff.push_back(m->P);
-    m->P += m->sz[l + 1];
+    m->P += fo;
+    m->lay.woff[l] = m->woff[l];
+    m->lay.fi[l] = fi;
+    m->lay.fo[l] = fo;
+    m->lay.fi_p[l] = mlp_pad8(fi);
+    m->lay.fo_p[l] = mlp_pad8(fo);
+    m->lay.wb_off[l] = nwb;
+    m->lay.wt_off[l] = nwt;
+    nwb += (long long)fi * m->lay.fo_p[l];
+    nwt += (long long)fo * m->lay.fi_p[l];
   }
   for (int w : m->sz) wmax = std::max(wmax, w);
-  const long long bw = (long long)batch_max * wmax;
   hipError_t e = hipSuccess;
   m->A.assign(n_layers, nullptr);
+  m->AT.assign(n_layers, nullptr);
   m->Z.assign(n_layers, nullptr);
   if (e == hipSuccess) e = dalloc(m, &m->p, m->P);
   if (e == hipSuccess) e = dalloc(m, &m->m, m->P);
   if (e == hipSuccess) e = dalloc(m, &m->v, m->P);
   if (e == hipSuccess) e = dalloc(m, &m->g, m->P);
-  if (e == hipSuccess) e = dalloc(m, &m->pb, m->P);
+  if (e == hipSuccess) e = dalloc(m, &m->wb, nwb);
+  if (e == hipSuccess) e = dalloc(m, &m->wt, nwt);
   for (int l = 0; l < n_layers && e == hipSuccess; ++l) {
-    e = dalloc(m, &m->A[l], (long long)batch_max * m->sz[l]);
+    e = dalloc(m, &m->A[l], (long long)batch_max * mlp_pad8(m->sz[l]));
+    if (e == hipSuccess) e = dalloc(m, &m->AT[l], (long long)(m->sz[l] + 1) * m->bpit);
     if (e == hipSuccess) e = dalloc(m, &m->Z[l], (long long)batch_max * m->sz[l + 1]);
   }
-  if (e == hipSuccess) e = dalloc(m, &m->dZ, bw);
-  if (e == hipSuccess) e = dalloc(m, &m->dA, bw);
-  if (e == hipSuccess) e = dalloc(m, &m->dZb, bw);
-  if (e == hipSuccess) e = dalloc(m, &m->part, rkkt::mlp_out_grad_blocks((long long)batch_max * m->sz[n_layers]));
+  for (int c = 0; c < 2 && e == hipSuccess; ++c) {
+    e = dalloc(m, &m->dZb[c], (long long)batch_max * mlp_pad8(wmax));
+    if (e == hipSuccess) e = dalloc(m, &m->dZT[c], (long long)wmax * m->bpit);
+  }
+  if (e == hipSuccess) {
+    for (int l = 0; l < n_layers; ++l)
+      rkkt::mlp_fill_bf16(m->AT[l] + (long long)m->sz[l] * m->bpit, m->bpit, 1.0f, nullptr);
+    e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipGetLastError();
+  }
   if (e != hipSuccess) {
     std::string msg = std::string("rkkt_mlp_create: ") + hipGetErrorString(e);
     rkkt_mlp_destroy(m);
     return fail(nullptr, -6, msg);
-  }
-  if (rocblas_create_handle(&m->h) != rocblas_status_success) {
-    rkkt_mlp_destroy(m);
-    return fail(nullptr, -2, "rkkt_mlp_create: rocblas_create_handle");
   }
   *out = m;
   return 0;
@@ -162,7 +207,6 @@ int rkkt_mlp_create(const int* sizes, int n_layers, int batch_max, rkkt_mlp** ou
 
 int rkkt_mlp_destroy(rkkt_mlp* m) {
   if (!m) return 0;
-  if (m->h) rocblas_destroy_handle(m->h);
   for (void* q : m->allocs) (void)hipFree(q);
   delete m;
   return 0;
@@ -178,7 +222,7 @@ int rkkt_mlp_set_params(rkkt_mlp* m, const float* params, hipStream_t st) {
   if (e == hipSuccess) e = hipMemsetAsync(m->m, 0, m->P * sizeof(float), st);
   if (e == hipSuccess) e = hipMemsetAsync(m->v, 0, m->P * sizeof(float), st);
   if (e != hipSuccess) return fail(m, -2, std::string("rkkt_mlp_set_params: ") + hipGetErrorString(e));
-  rkkt::mlp_to_bf16(m->p, m->pb, m->P, st);
+  rkkt::mlp_param_copies(m->p, m->P, m->lay, m->wb, m->wt, st);
   m->t = 0;
   return check(m, "rkkt_mlp_set_params");
 }
@@ -194,7 +238,7 @@ int rkkt_mlp_forward(rkkt_mlp* m, const float* x, int batch, float* y, hipStream
   if (int rc = args_ok(m, batch, "rkkt_mlp_forward")) return rc;
   if (!x || !y) return fail(m, -1, "rkkt_mlp_forward: null array");
   (void)hipGetLastError();
-  return forward_impl(m, x, batch, y, st);
+  return forward_impl(m, x, batch, y, false, st);
 }
 
 int rkkt_mlp_gradients(rkkt_mlp* m, const float* x, const float* t, int batch, float* grads, float* loss,
@@ -217,7 +261,7 @@ int rkkt_mlp_train_step(rkkt_mlp* m, const float* x, const float* t, int batch, 
   (void)hipGetLastError();
   if (int rc = gradients_impl(m, x, t, batch, loss, st)) return rc;
   m->t += 1;
-  rkkt::mlp_adam(m->p, m->g, m->m, m->v, m->pb, m->P, lr, m->t, st);
+  rkkt::mlp_adam(m->p, m->g, m->m, m->v, m->P, lr, m->t, m->lay, m->wb, m->wt, st);
   return check(m, "rkkt_mlp_train_step");
 }
 

@@ -37,7 +37,7 @@ class Solver:
         self.qd.copy_(self.torch.as_tensor(qd))
         L.rkkt_set_loads(self.p, self.pd, self.qd)
 
-    def solve(self, tol=1e-8, warm=None, mu0=0.0):
+    def solve(self, tol=1e-8, warm=None, mu0=0.0, warm_duals=0):
         """Returns (result dict, solution vector [x, u, y, z] with the
         multipliers for objective weight 1 / N)."""
         if warm is None:
@@ -45,7 +45,7 @@ class Solver:
         else:
             x0, u0, y0, z0 = warm
             r = L.rkkt_solve_warm(self.p, x0, u0, y0, z0, self.x, self.u, self.y, self.zz, self.s,
-                                  tol=tol, mu0=mu0)
+                                  tol=tol, mu0=mu0, warm_duals=warm_duals)
         scale = 1.0 / r["obj_weight"]   # N = 1
         sol = self.torch.cat([self.x, self.u, self.y * scale, self.zz * scale]).cpu().numpy()
         return r, sol
@@ -57,12 +57,15 @@ class Solver:
         return t[:a].contiguous(), t[a:b].contiguous(), t[b:c].contiguous(), t[c:].contiguous()
 
 
-def solve_draws(solver, pd, qd, tol=1e-8):
+def solve_draws(solver, pd, qd, tol=1e-8, log=None):
     """Cold solves of the draws pd, qd [n_load][K]: (solutions [K][n_out],
-    iterations [K], objectives [K], converged [K])."""
+    iterations [K], objectives [K], converged [K]); a progress line through
+    log every 1000 solves."""
     K = pd.shape[1]
     sols, its, objs, ok = [], [], [], []
     for k in range(K):
+        if log and k and k % 1000 == 0:
+            log(f"cold solves: {k} of {K}")
         solver.set_loads(pd[:, k], qd[:, k])
         r, sol = solver.solve(tol)
         sols.append(sol)
@@ -123,13 +126,13 @@ def predict(torch, m, X):
     return out.cpu().numpy().astype(np.float64)
 
 
-def warm_solves(solver, torch, pd, qd, idx, pred, objs, its, mu0, tol):
+def warm_solves(solver, torch, pd, qd, idx, pred, objs, its, mu0, tol, warm_duals=0):
     """Warm solves of the draws idx from the predictions; (iterations with
     fallbacks counted, number of fallbacks, relative objective differences)."""
     warm_its, fallbacks, obj_err = [], 0, []
     for j, k in enumerate(idx):
         solver.set_loads(pd[:, k], qd[:, k])
-        r, _ = solver.solve(tol, warm=solver.split(pred[j]), mu0=mu0)
+        r, _ = solver.solve(tol, warm=solver.split(pred[j]), mu0=mu0, warm_duals=warm_duals)
         rel = abs(r["obj"] - objs[k]) / max(abs(objs[k]), 1e-300)
         obj_err.append(rel)
         n = r["iters"]
@@ -143,13 +146,15 @@ def warm_solves(solver, torch, pd, qd, idx, pred, objs, its, mu0, tol):
 def experiment(torch, net, pd, qd, n_train, n_val=0, mu0s=(1e-4,), tol=1e-8, steps=2000, seed=0, log=print):
     """Cold solves of every draw; training on the first n_train, the warm
     start's barrier parameter chosen among mu0s on the next n_val draws (the
-    first of mu0s without validation draws), warm solves of the rest.
+    first of mu0s without validation draws), warm solves of the rest, from the
+    perceptron's predictions and, as the ablation, from the mean training
+    solution at the same barrier parameter.
     Iterations are counted with fallbacks: a warm solve that fails or whose
     objective differs from the cold one by more than 1e-6 relative adds the
     cold iterations."""
     solver = Solver(net, torch)
     t0 = time.time()
-    sols, its, objs, ok = solve_draws(solver, pd, qd, tol)
+    sols, its, objs, ok = solve_draws(solver, pd, qd, tol, log=log)
     t_solve = time.time() - t0
     log(f"cold solves: {len(its)} in {t_solve:.1f} s, mean {its.mean():.2f} iterations, "
         f"{(~ok).sum()} not converged")
@@ -174,12 +179,20 @@ def experiment(torch, net, pd, qd, n_train, n_val=0, mu0s=(1e-4,), tol=1e-8, ste
         mu0 = min(val, key=val.get)
     pred = sy.inv(predict(torch, mlp, sx.fwd(X[te])))
     warm_its, fallbacks, obj_err = warm_solves(solver, torch, pd, qd, te, pred, objs, its, mu0, tol)
+    # ablation: the same warm solve from the mean training solution (no
+    # network), at the same mu0, so that the gain of the perceptron is
+    # separated from the gain of starting with a small barrier parameter
+    mean_pred = np.repeat(sols[tr].mean(axis=0)[None, :], len(te), axis=0)
+    mean_its, mean_fb, mean_err = warm_solves(solver, torch, pd, qd, te, mean_pred, objs, its, mu0, tol)
     out = {"n_train": int(len(tr)), "n_val": int(len(va)), "n_test": int(len(te)),
            "cold_mean_iters": float(its[te].mean()), "warm_mean_iters": float(warm_its.mean()),
            "fallback_rate": fallbacks / max(len(te), 1),
-           "max_rel_obj_diff": float(np.max(obj_err)) if len(obj_err) else 0.0, "train_loss": hist,
-           "cold_solve_seconds": t_solve, "train_seconds": t_train, "mu0_warm": mu0,
+           "max_rel_obj_diff": float(np.max(obj_err)) if len(obj_err) else 0.0,
+           "mean_start_mean_iters": float(mean_its.mean()),
+           "mean_start_fallback_rate": mean_fb / max(len(te), 1),
+           "train_loss": hist, "cold_solve_seconds": t_solve, "train_seconds": t_train, "mu0_warm": mu0,
            "validation_mean_iters": {f"{k:g}": v for k, v in val.items()}}
     log(f"test: cold {out['cold_mean_iters']:.2f} vs warm {out['warm_mean_iters']:.2f} mean iterations "
-        f"(mu0 {mu0:g}), fallback rate {out['fallback_rate']:.3f}")
+        f"(mu0 {mu0:g}), fallback rate {out['fallback_rate']:.3f}; from the mean training solution "
+        f"{out['mean_start_mean_iters']:.2f}, fallback rate {out['mean_start_fallback_rate']:.3f}")
     return out

@@ -380,6 +380,8 @@ def main():
     ap.add_argument("--col-tile", type=int, default=0)
     ap.add_argument("--variant", type=int, default=0, choices=(0, 1, 2),
                     help="reduction: 1 adjoint solves, 2 stacked product, 0 automatic")
+    ap.add_argument("--sweep-form", type=int, default=0, choices=(0, 1, 2),
+                    help="reduction solve schedules: 1 push, 2 pull, 0 automatic")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--seed", type=int, default=2024)
@@ -421,7 +423,7 @@ def main():
     net, N = inst.net, inst.scen.n_scen
     it = random_iterate(net, N, args.seed)
     p = R.rkkt_create(net, inst.scen.pd.T, inst.scen.qd.T, col_tile=args.col_tile,
-                      variant=args.variant)
+                      variant=args.variant, sweep_form=args.sweep_form)
     d = p.dims
     nx, nu, m = d["n_x"], d["n_u"], d["m"]
     t = {k: torch.tensor(np.ascontiguousarray(v), dtype=torch.float64, device="cuda")
@@ -495,7 +497,8 @@ def main():
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": WORKLOADS[args.config], "n_scen": N, "n_x": nx, "n_u": nu, "m": m,
                    "nnz_lu": d["nnz_lu"], "col_tile": d["col_tile"], "variant": d["variant"],
-                   "lds_reduce": d["lds_reduce"], "lds_group": d["lds_group"], "delta_w": dw,
+                   "lds_reduce": d["lds_reduce"], "lds_group": d["lds_group"],
+                   "sweep_form": d["sweep_form"], "delta_w": dw,
                    "seed": args.seed},
         "graph_ms_per_step": graph_ms, "eager_ms_per_step": eager_ms,
         "condense_factor_value": N / (cf_ms * 1e-3),

@@ -104,6 +104,15 @@ typedef struct {
                           instead of one barrier-separated phase per row:
                           0 the length with the fewest phases (at most 32),
                           -1 none, 1..32 at most that many                    */
+  int sweep_form;      /* schedule of the reduction's triangular solves:
+                          1 push: in the phase of each level, every row that
+                            depends on that level's rows subtracts their terms
+                            (a row is updated once per level it depends on);
+                          2 pull: every row subtracts all its terms once, in
+                            the phase of its own level, which needs its sources
+                            only (forces the reduction's panels into device
+                            memory, where it writes each row once per solve);
+                          0 push when the reduction runs in LDS, else pull   */
 } rkkt_options;
 
 typedef struct {
@@ -129,6 +138,7 @@ typedef struct {
                                        (patterns, schedules, gather lists); 0
                                        from rkkt_analyze                        */
   int n_load;                       /* load buses                               */
+  int sweep_form;                   /* reduction solve schedules: 1 push, 2 pull */
 } rkkt_dims;
 
 /*

@@ -55,7 +55,8 @@ class Network(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("col_tile", ctypes.c_int), ("device", ctypes.c_int), ("variant", ctypes.c_int),
-                ("scen_per_group", ctypes.c_int), ("chain_rows", ctypes.c_int)]
+                ("scen_per_group", ctypes.c_int), ("chain_rows", ctypes.c_int),
+                ("sweep_form", ctypes.c_int)]
 
 
 class Dims(ctypes.Structure):
@@ -74,7 +75,7 @@ class Dims(ctypes.Structure):
                 ("lds_step", ctypes.c_int), ("chain_rows", ctypes.c_int),
                 ("nnz_kxx", ctypes.c_longlong), ("nnz_kxu", ctypes.c_longlong),
                 ("nnz_kuu", ctypes.c_longlong), ("idx_bytes", ctypes.c_longlong),
-                ("n_load", ctypes.c_int)]
+                ("n_load", ctypes.c_int), ("sweep_form", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -230,16 +231,17 @@ class Handle:
             self.ptr = None
 
 
-def rkkt_analyze(net, n_scen, col_tile=0, variant=0, scen_per_group=0, chain_rows=0):
+def rkkt_analyze(net, n_scen, col_tile=0, variant=0, scen_per_group=0, chain_rows=0, sweep_form=0):
     s, keep = _host_network(net)
     d = Dims()
     _check(lib().rkkt_analyze(ctypes.byref(s), int(n_scen),
-                              ctypes.byref(Options(col_tile, 0, variant, scen_per_group, chain_rows)),
+                              ctypes.byref(Options(col_tile, 0, variant, scen_per_group, chain_rows,
+                                                   sweep_form)),
                               ctypes.byref(d)))
     return d.as_dict()
 
 
-def rkkt_create(net, pd, qd, col_tile=0, device=0, variant=0, scen_per_group=0, chain_rows=0):
+def rkkt_create(net, pd, qd, col_tile=0, device=0, variant=0, scen_per_group=0, chain_rows=0, sweep_form=0):
     """pd, qd: host [N][n_load] arrays (scenario-major); the launch-shape
     options of rkkt_options (0 = automatic)."""
     s, keep = _host_network(net)
@@ -251,7 +253,7 @@ def rkkt_create(net, pd, qd, col_tile=0, device=0, variant=0, scen_per_group=0, 
     _check(lib().rkkt_create(ctypes.byref(s), pd.shape[0], pd.ctypes.data_as(c_dbl_p),
                              qd.ctypes.data_as(c_dbl_p),
                              ctypes.byref(Options(col_tile, device, variant, scen_per_group,
-                                                  chain_rows)),
+                                                  chain_rows, sweep_form)),
                              ctypes.byref(h)))
     d = Dims()
     _check(lib().rkkt_dims_get(h, ctypes.byref(d)), h)
@@ -274,12 +276,13 @@ def rkkt_analyze_lu(net, n_scen, col_tile=0):
 SCHEDULES = ("reduce_up", "reduce_down", "step_up", "step_down", "refactor")
 
 
-def rkkt_analyze_schedule(net, n_scen, which, col_tile=0, variant=0, scen_per_group=0, chain_rows=0):
+def rkkt_analyze_schedule(net, n_scen, which, col_tile=0, variant=0, scen_per_group=0, chain_rows=0,
+                          sweep_form=0):
     """Host-only export of a level-sliced schedule: dict with nphase, slots,
     ptr [nphase*slots+1], ent [n_ent][4], chain_rows, chain_pos [t][t]."""
     s, keep = _host_network(net)
     w = SCHEDULES.index(which) if isinstance(which, str) else int(which)
-    o = Options(col_tile, 0, variant, scen_per_group, chain_rows)
+    o = Options(col_tile, 0, variant, scen_per_group, chain_rows, sweep_form)
     nph, sl, ne, ct, nu_ = (ctypes.c_int() for _ in range(5))
     L = lib()
     _check(L.rkkt_analyze_schedule(ctypes.byref(s), int(n_scen), ctypes.byref(o), w, ctypes.byref(nph),

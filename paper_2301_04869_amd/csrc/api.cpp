@@ -88,6 +88,7 @@ void fill_dims(const rkkt::Sym& s, rkkt_dims* o, long long bytes, long long idx_
   }
   o->idx_bytes = idx_bytes;
   o->n_load = s.nload;
+  o->sweep_form = s.sweep_form;
 }
 
 // Appends the entries of a level-sliced schedule packed as two words of
@@ -211,8 +212,10 @@ int rkkt_create(const rkkt_network* net, int n_scen, const double* pd, const dou
   d.nnz_l = s.nnz_l;
   d.nlev_up = (int)s.lvu_ptr.size() - 1;
   d.nlev_dn = (int)s.lvd_ptr.size() - 1;
-  d.nph_u = s.red_up.nphase;
-  d.nph_d = s.red_dn.nphase;
+  d.nph_u = s.stp_up.nphase;
+  d.nph_d = s.stp_dn.nphase;
+  d.nph_ru = s.red_up.nphase;
+  d.nph_rd = s.red_dn.nphase;
   d.n_upd = (int)s.upd_dst.size();
   d.n_sent = (int)(s.red_up.ent.size() / 4);
   d.chain_t = s.chain_t;

@@ -49,7 +49,8 @@ struct DP {
   // pairs when the kernel stages them in LDS, int4 otherwise)
   const int *ru_ptr, *rd_ptr, *su_ptr, *sd_ptr, *fa_ptr;
   const void *ru_ent, *rd_ent, *su_ent, *sd_ent, *fa_ent;
-  int nph_u, nph_d, n_upd;
+  int nph_u, nph_d, n_upd;  // phases of the step and refactorisation schedules
+  int nph_ru, nph_rd;       // phases of the reduction's schedules (ru_*, rd_*)
   int n_sent;             // entries of every schedule (pairs outside the chain)
   int fac_npiv;           // levels whose pivots the refactorisation's phases take
   int chain_t, chain_c0;  // chain rows chain_c0 .. nx - 1

@@ -65,6 +65,7 @@ __host__ __device__ __forceinline__ LdsSizes sizes_of(const DP& d) {
   z.nx = d.nx; z.nu = d.nu; z.nz = d.nz; z.nnz_f = d.nnz_f; z.nnz_k = d.nnz_k;
   z.nnz_gu = d.nnz_gu; z.nnz_l = d.n_sent; z.nlu = d.nlev_up; z.nph_u = d.nph_u;
   z.nph_d = d.nph_d; z.n_upd = d.n_upd; z.w = d.col_tile; z.variant = d.variant; z.spw = d.spw;
+  z.nph_ru = d.nph_ru; z.nph_rd = d.nph_rd;
   z.upd_lds = d.upd_lds;
   z.nnz_h = d.nnz_h; z.m = d.m;
   z.chain_t = d.chain_t;
@@ -611,8 +612,8 @@ __global__ __launch_bounds__(kRT) void k_reduce(DP d) {
     unsigned* ue = reinterpret_cast<unsigned*>(smem + reduce_lds_doubles(z));
     unsigned* de = ue + 2 * d.n_sent;
     int* ip = reinterpret_cast<int*>(de + 2 * d.n_sent);
-    int* a_up = ip; ip += d.nph_u * S + 1;
-    int* a_dp = ip; ip += d.nph_d * S + 1;
+    int* a_up = ip; ip += d.nph_ru * S + 1;
+    int* a_dp = ip; ip += d.nph_rd * S + 1;
     int* a_kp = ip; ip += nz + 1;
     int* a_ku = ip; ip += nz;
     int* a_kc = ip; ip += d.nnz_k;
@@ -662,14 +663,14 @@ __global__ __launch_bounds__(kRT) void k_reduce(DP d) {
   __syncthreads();
   // step 1
   const bool chain_lane = slot == 0 && (kLDS || colok);
-  sweep<kLDS, false>(uptr, uent, d.nph_u, S, slot, colok, lu, T, ldT, c, bsync);
+  sweep<kLDS, false>(uptr, uent, d.nph_ru, S, slot, colok, lu, T, ldT, c, bsync);
   if (d.chain_t > 0) {
     if (chain_lane) chain_solveW<true, false>(d, cv, T, ldT, c);
     __syncthreads();
     if (chain_lane) chain_solveW<false, false>(d, cv, T, ldT, c);
     __syncthreads();
   }
-  sweep<kLDS, false>(dptr, dent, d.nph_d, S, slot, colok, lu, T, ldT, c, bsync);
+  sweep<kLDS, false>(dptr, dent, d.nph_rd, S, slot, colok, lu, T, ldT, c, bsync);
   if (colok)
     for (int i = slot; i < nx; i += S) T[(long long)i * ldT + c] *= invd[i];
   __syncthreads();
@@ -697,14 +698,14 @@ __global__ __launch_bounds__(kRT) void k_reduce(DP d) {
     }
   __syncthreads();
   // step 3: U^T sweep, L^T sweep, then L_u - G_u^T (G_x^-T L_x)
-  sweep<kLDS, true>(uptr, uent, d.nph_u, S, slot, colok, lu, Lx, W, c, bsync);
+  sweep<kLDS, true>(uptr, uent, d.nph_ru, S, slot, colok, lu, Lx, W, c, bsync);
   if (d.chain_t > 0) {
     if (chain_lane) chain_solveW<true, true>(d, cv, Lx, W, c);
     __syncthreads();
     if (chain_lane) chain_solveW<false, true>(d, cv, Lx, W, c);
     __syncthreads();
   }
-  sweep<kLDS, true>(dptr, dent, d.nph_d, S, slot, colok, lu, Lx, W, c, bsync);
+  sweep<kLDS, true>(dptr, dent, d.nph_rd, S, slot, colok, lu, Lx, W, c, bsync);
   if (colok)
     for (int ru = slot; ru < nu; ru += S) {
       double acc = out[(long long)ru * nu + col];
@@ -786,6 +787,80 @@ __device__ __forceinline__ void sweep64(const int* __restrict__ ptr, const int4*
   }
 }
 
+// The same sweep with the panel X and the factor in global memory (panels
+// too large for LDS): each load is a round trip to L2 or HBM, so the
+// entries of a phase are taken in batches of kGB whose panel loads (the
+// source row's value and the destination row's current value) are all
+// issued before the batch's multiply-adds.  Within a phase the source rows
+// are final and each destination row belongs to one slot as one contiguous
+// group, so a prefetched destination value is current whenever its group
+// starts in the batch (a group that continues from the previous batch keeps
+// its running sum in a register).  Entries are held in lanes in chunks of
+// 64, the next chunk and its factor values loaded while the current one
+// runs.  Every destination subtracts its terms in schedule order, as in
+// sweep64.
+constexpr int kGB = 16;
+
+template <bool kTrans, typename Sync>
+__device__ __forceinline__ void sweep64g(const int* __restrict__ ptr, const int4* __restrict__ ent,
+                                         int nphase, int wv, const double* __restrict__ lu, double* X,
+                                         int ld, int c, Sync sync) {
+  const int lane = threadIdx.x & 63;
+  auto chunk = [&](int e, int b1) -> int4 { return e + lane < b1 ? ent[e + lane] : make_int4(-1, 0, 0, 0); };
+  auto values = [&](int4 ev) -> double { return ev.x >= 0 ? lu[kTrans ? ev.w : ev.z] : 0.0; };
+  int bq = lane < 2 ? ptr[wv + lane] : 0;
+  for (int q = 0; q < nphase; ++q) {
+    const int b0 = __builtin_amdgcn_readlane(bq, 0), b1 = __builtin_amdgcn_readlane(bq, 1);
+    bq = q + 1 < nphase && lane < 2 ? ptr[(q + 1) * kS64 + wv + lane] : 0;
+    int4 ev = chunk(b0, b1);
+    double lv = values(ev);
+    int cur = -1;
+    double acc = 0.0;
+    for (int e0 = b0; e0 < b1; e0 += 64) {
+      const int m = min(64, b1 - e0);
+      const int4 evn = chunk(e0 + 64, b1);
+      const double lvn = values(evn);
+      for (int u0 = 0; u0 < m; u0 += kGB) {
+        double xs[kGB], xd[kGB];
+#pragma unroll
+        for (int j = 0; j < kGB; ++j) {
+          if (u0 + j < m) {
+            const int dst = __builtin_amdgcn_readlane(ev.x, u0 + j);
+            const int src = __builtin_amdgcn_readlane(ev.y, u0 + j);
+            xs[j] = X[(long long)src * ld + c];
+            xd[j] = X[(long long)dst * ld + c];
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < kGB; ++j) {
+          if (u0 + j < m) {
+            const int dst = __builtin_amdgcn_readlane(ev.x, u0 + j);
+            const double v = readlane_d(lv, u0 + j);
+            if (dst != cur) {
+              if (cur >= 0) X[(long long)cur * ld + c] = acc;
+              cur = dst;
+              acc = xd[j];
+            }
+            acc = fma(-v, xs[j], acc);
+          }
+        }
+      }
+      ev = evn;
+      lv = lvn;
+    }
+    if (cur >= 0) X[(long long)cur * ld + c] = acc;
+    sync();
+  }
+}
+
+template <bool kTrans, bool kLDS, typename Sync>
+__device__ __forceinline__ void sweep64_any(const int* __restrict__ ptr, const int4* __restrict__ ent,
+                                            int nphase, int wv, const double* __restrict__ lu, double* X,
+                                            int ld, int c, Sync sync) {
+  if constexpr (kLDS) sweep64<kTrans>(ptr, ent, nphase, wv, lu, X, ld, c, sync);
+  else sweep64g<kTrans>(ptr, ent, nphase, wv, lu, X, ld, c, sync);
+}
+
 template <bool kLDS, int kVar>
 __global__ __launch_bounds__(kRT) void k_reduce64(DP d) {
   const int k = blockIdx.y, tile = blockIdx.x;
@@ -856,12 +931,12 @@ __global__ __launch_bounds__(kRT) void k_reduce64(DP d) {
   const int4* dent = static_cast<const int4*>(d.rd_ent);
   // every lane sweeps (barriers stay uniform); lanes past n_u work on
   // padding columns inside the panel, which nothing reads
-  sweep64<false>(d.ru_ptr, uent, d.nph_u, wv, lu, T, ldT, c, bsync);
+  sweep64_any<false, kLDS>(d.ru_ptr, uent, d.nph_ru, wv, lu, T, ldT, c, bsync);
   if (d.chain_t > 0) {
     chain_solveR<false>(d, cv, T, ldT, wv);
     __syncthreads();
   }
-  sweep64<false>(d.rd_ptr, dent, d.nph_d, wv, lu, T, ldT, c, bsync);
+  sweep64_any<false, kLDS>(d.rd_ptr, dent, d.nph_rd, wv, lu, T, ldT, c, bsync);
   if (colok)
     for (int i = wv; i < nx; i += kS64) T[(long long)i * ldT + c] *= invd[i];
   __syncthreads();
@@ -901,15 +976,22 @@ __global__ __launch_bounds__(kRT) void k_reduce64(DP d) {
         const double vm = readlane_d(valv[j], m);
         if (cm == nx + col) acc[j] = vm;
       }
-    for (int m = 0; m < len; ++m) {
+    // panel values of kRowsB entries of every row loaded before their
+    // multiply-adds (each row still sums its entries in pattern order)
+    constexpr int kRowsB = 8;
+    for (int m0 = 0; m0 < len; m0 += kRowsB) {
+      double tv[kRowsK][kRowsB];
 #pragma unroll
-      for (int j = 0; j < kRowsK; ++j) {
-        if (m < eu[j] - e[j]) {
-          const int cm = __builtin_amdgcn_readlane(colv[j], m);
-          const double vm = readlane_d(valv[j], m);
-          acc[j] = fma(vm, T[(long long)cm * ldT + c], acc[j]);
-        }
-      }
+      for (int j = 0; j < kRowsK; ++j)
+#pragma unroll
+        for (int t = 0; t < kRowsB; ++t)
+          if (m0 + t < eu[j] - e[j])
+            tv[j][t] = T[(long long)__builtin_amdgcn_readlane(colv[j], m0 + t) * ldT + c];
+#pragma unroll
+      for (int j = 0; j < kRowsK; ++j)
+#pragma unroll
+        for (int t = 0; t < kRowsB; ++t)
+          if (m0 + t < eu[j] - e[j]) acc[j] = fma(readlane_d(valv[j], m0 + t), tv[j][t], acc[j]);
     }
 #pragma unroll
     for (int j = 0; j < kRowsK; ++j) out4[j] = acc[j];
@@ -1005,17 +1087,30 @@ __global__ __launch_bounds__(kRT) void k_reduce64(DP d) {
     }
   }
   __syncthreads();
-  sweep64<true>(d.ru_ptr, uent, d.nph_u, wv, lu, Lx, kW64, c, bsync);
+  sweep64_any<true, kLDS>(d.ru_ptr, uent, d.nph_ru, wv, lu, Lx, kW64, c, bsync);
   if (d.chain_t > 0) {
     chain_solveR<true>(d, cv, Lx, kW64, wv);
     __syncthreads();
   }
-  sweep64<true>(d.rd_ptr, dent, d.nph_d, wv, lu, Lx, kW64, c, bsync);
+  sweep64_any<true, kLDS>(d.rd_ptr, dent, d.nph_rd, wv, lu, Lx, kW64, c, bsync);
+  // G_u^T product: the entries of a column of G_u loaded kGB at a time
+  // before their multiply-adds (summed in pattern order)
   if (colok)
     for (int ru = wv; ru < nu; ru += kS64) {
       double acc = out[(long long)ru * nu + col];
       const int j1 = d.guc_ptr[ru + 1];
-      for (int j = d.guc_ptr[ru]; j < j1; ++j) acc = fma(-gu_val(j), Lx[(long long)d.guc_row[j] * kW64 + c], acc);
+      for (int jb = d.guc_ptr[ru]; jb < j1; jb += kGB) {
+        double gv[kGB], lx[kGB];
+#pragma unroll
+        for (int t = 0; t < kGB; ++t)
+          if (jb + t < j1) {
+            gv[t] = gu_val(jb + t);
+            lx[t] = Lx[(long long)d.guc_row[jb + t] * kW64 + c];
+          }
+#pragma unroll
+        for (int t = 0; t < kGB; ++t)
+          if (jb + t < j1) acc = fma(-gv[t], lx[t], acc);
+      }
       out[(long long)ru * nu + col] = acc;
     }
 }

@@ -26,6 +26,7 @@ struct LdsSizes {
   int nx, nu, nz, nnz_f, nnz_k, nnz_gu;
   int nnz_l;  // entries of every level-sliced schedule (at most the strict lower count)
   int nlu, nph_u, nph_d, n_upd, w, variant, spw;
+  int nph_ru, nph_rd;  // phases of the reduction's schedules
   int upd_lds;  // refactorisation update targets staged in LDS (else read from global)
   int chain_t;  // rows of the chain (its values occupy chain_t^2 doubles in the reduction)
   int nnz_h, m;
@@ -47,7 +48,7 @@ __host__ __device__ inline long long reduce_lds_doubles(const LdsSizes& z) {
 }
 __host__ __device__ inline long long reduce_lds_ints(const LdsSizes& z) {
   const long long S = red_slots(z);
-  return 4LL * z.nnz_l + (z.nph_u * S + 1) + (z.nph_d * S + 1) + (z.nz + 1) + z.nz + z.nnz_k +
+  return 4LL * z.nnz_l + (z.nph_ru * S + 1) + (z.nph_rd * S + 1) + (z.nz + 1) + z.nz + z.nnz_k +
          (z.nu + 1) + z.nnz_gu + 2;  // + padding to whole 8-byte units
 }
 // With 64-column tiles the schedule is read from global memory (scalar

@@ -197,6 +197,85 @@ void build_solve_sched(const Sym& s, bool up, int S, Sched& out) {
   }
 }
 
+// Pull form of a solve schedule: a row subtracts its terms in few tasks
+// rather than one per level of its sources (push), so that a sweep whose
+// panel lives in device memory writes each row about once.  Levels count
+// from the rows with no sources (level 0, nothing to do); in phase q the
+// rows of level <= q are final, and a row of level L finishes in phase L - 1
+// (its home phase).  A row with more than kPullCap terms would hold one
+// slot for its whole length while the phase's other slots wait, so its terms,
+// taken latest source level first, are cut into pieces of kPullCap: the first
+// piece in the home phase, each further piece in the phase before the
+// previous one when all its sources are final by then (else it joins the
+// previous piece).  Pairs inside the chain are left to the chain solve: up,
+// the chain rows (last in the order) take their terms from rows before the
+// chain in the phases and the chain solve follows; down, the chain is solved
+// first, so its rows are final from the start (level 0).
+constexpr int kPullCap = 16;
+
+void build_pull_sched(const Sym& s, bool up, int S, Sched& out) {
+  const int nx = s.nx, c0 = nx - s.chain_t;
+  auto range = [&](int i) -> std::pair<int, int> {
+    return up ? std::make_pair(s.f_ptr[i], s.f_diag[i]) : std::make_pair(s.f_diag[i] + 1, s.f_ptr[i + 1]);
+  };
+  std::vector<int> lev(nx, 0);
+  int nlev = 0;
+  for (int t = 0; t < nx; ++t) {
+    const int i = up ? t : nx - 1 - t;
+    int L = 0;
+    const auto r = range(i);
+    for (int e = r.first; e < r.second; ++e) {
+      const int j = s.f_col[e];
+      if (i >= c0 && j >= c0) continue;
+      L = std::max(L, lev[j] + 1);
+    }
+    lev[i] = L;
+    nlev = std::max(nlev, L);
+  }
+  // pieces (row, entry positions) per phase
+  std::vector<std::vector<std::pair<int, std::vector<int>>>> ph(nlev);
+  std::vector<int> es;
+  for (int i = 0; i < nx; ++i) {
+    es.clear();
+    const auto r = range(i);
+    for (int e = r.first; e < r.second; ++e)
+      if (!(i >= c0 && s.f_col[e] >= c0)) es.push_back(e);
+    if (es.empty()) continue;
+    std::stable_sort(es.begin(), es.end(), [&](int x, int y) { return lev[s.f_col[x]] > lev[s.f_col[y]]; });
+    std::vector<std::pair<int, std::vector<int>>> pieces;
+    for (size_t k = 0; k < es.size(); k += kPullCap) {
+      std::vector<int> ch(es.begin() + k, es.begin() + std::min(es.size(), k + kPullCap));
+      const int ml = lev[s.f_col[ch[0]]];  // the piece's latest source level
+      if (pieces.empty()) pieces.push_back({lev[i] - 1, ch});
+      else if (pieces.back().first - 1 >= ml) pieces.push_back({pieces.back().first - 1, ch});
+      else pieces.back().second.insert(pieces.back().second.end(), ch.begin(), ch.end());
+    }
+    for (auto& pc : pieces) {
+      std::sort(pc.second.begin(), pc.second.end());  // terms in pattern order
+      ph[pc.first].push_back({i, std::move(pc.second)});
+    }
+  }
+  out = Sched();
+  out.S = S;
+  out.nphase = nlev;
+  out.ptr.assign(1, 0);
+  std::vector<std::vector<int>> slot_tasks(S);
+  std::vector<long long> cost;
+  for (int q = 0; q < nlev; ++q) {
+    const auto& tq = ph[q];
+    cost.resize(tq.size());
+    for (size_t t = 0; t < tq.size(); ++t) cost[t] = (long long)tq[t].second.size();
+    assign_tasks(cost, S, slot_tasks);
+    for (int sl = 0; sl < S; ++sl) {
+      for (int t : slot_tasks[sl]) {
+        const int i = tq[t].first;
+        for (int e : tq[t].second) out.ent.insert(out.ent.end(), {i, s.f_col[e], e, s.f_tpos[e]});
+      }
+      out.ptr.push_back((int)(out.ent.size() / 4));
+    }
+  }
+}
+
 // Refactorisation items: the entry l_ik of row i, taken when row k (level q)
 // is final, costs one multiply by 1/u_kk and one update of row i per entry of
 // the U part of row k.  upd receives, per item, the positions of (i, j) for
@@ -275,6 +354,8 @@ LdsSizes lds_sizes(const Sym& s, int w, int variant, int spw) {
   z.nlu = (int)s.lvu_ptr.size() - 1;
   z.nph_u = std::max(0, z.nlu - 1);
   z.nph_d = std::max(0, (int)s.lvd_ptr.size() - 1);  // the chain's merged phase may add one
+  z.nph_ru = z.nph_u;  // the reduction runs in LDS with push schedules only
+  z.nph_rd = z.nph_d;
   z.n_upd = (int)(s.lu_flops - s.nnz_l);
   z.w = w; z.variant = variant; z.spw = spw;
   z.upd_lds = s.upd_lds ? 1 : 0;
@@ -288,6 +369,8 @@ std::string build_symbolic(const rkkt_network& net, int N, const rkkt_options* o
   const int spw_req = opt ? opt->scen_per_group : 0, chain_req = opt ? opt->chain_rows : 0;
   if (spw_req != 0 && spw_req != 1 && spw_req != 2 && spw_req != 4) return "scen_per_group must be 0, 1, 2 or 4";
   if (chain_req < -1 || chain_req > kChainMax) return "chain_rows must be in [-1, 32]";
+  const int form_req = opt ? opt->sweep_form : 0;
+  if (form_req < 0 || form_req > 2) return "sweep_form must be 0, 1 or 2";
   char msg[256];
   const int nb = net.n_bus, nl = net.n_line, ng = net.n_gen, nload = net.n_load;
   if (nb < 2 || nl < 1 || ng < 1 || nload < 0 || N < 1) return "bad sizes";
@@ -735,7 +818,8 @@ std::string build_symbolic(const rkkt_network& net, int N, const rkkt_options* o
     s.col_tile = pick_tile(s.variant);
     if (s.col_tile == 0) s.col_tile = std::min(64, nu);
   }
-  s.lds_reduce = fits(s.col_tile, s.variant);
+  s.lds_reduce = form_req != 2 && fits(s.col_tile, s.variant);
+  s.sweep_form = form_req != 0 ? form_req : s.lds_reduce ? 1 : 2;
   s.lds_resident = s.lds_reduce && s.lds_group && s.lds_step;
   // stacked panels of the product variant: rows (x rows then u rows) of every
   // scenario, columns padded to a multiple of 64 (the reduction's widest tile)
@@ -754,8 +838,13 @@ std::string build_symbolic(const rkkt_network& net, int N, const rkkt_options* o
     s.nchunk = (int)nc;
   }
   // schedules
-  build_solve_sched(s, true, kRedThreads / s.col_tile, s.red_up);
-  build_solve_sched(s, false, kRedThreads / s.col_tile, s.red_dn);
+  if (s.sweep_form == 2) {
+    build_pull_sched(s, true, kRedThreads / s.col_tile, s.red_up);
+    build_pull_sched(s, false, kRedThreads / s.col_tile, s.red_dn);
+  } else {
+    build_solve_sched(s, true, kRedThreads / s.col_tile, s.red_up);
+    build_solve_sched(s, false, kRedThreads / s.col_tile, s.red_dn);
+  }
   build_solve_sched(s, true, s.step_group, s.stp_up);
   build_solve_sched(s, false, s.step_group, s.stp_dn);
   {

@@ -34,6 +34,7 @@ struct Sym {
   int col_tile = 0;
   bool lds_resident = true;  // every level-scheduled kernel keeps its data in LDS
   bool lds_reduce = true;    // the reduction's panels and factors sit in LDS
+  int sweep_form = 1;        // reduction schedules: 1 push (per source level), 2 pull (per destination row)
   bool lds_group = true;     // the refactorisation keeps its scenarios in LDS
   bool lds_step = true;      // the step keeps its scenario in LDS
 

@@ -69,8 +69,9 @@ def test_sweeps_reproduce_dense_triangular_solves(case):
             Um[i, j] = vals[e]
     eye = np.eye(nx)
     b = rng.standard_normal(nx)
-    for which, up in (("reduce_up", True), ("reduce_down", False), ("step_up", True), ("step_down", False)):
-        sc = R.rkkt_analyze_schedule(inst.net, n, which)
+    for which, up, form in (("reduce_up", True, 0), ("reduce_down", False, 0), ("reduce_up", True, 2),
+                            ("reduce_down", False, 2), ("step_up", True, 0), ("step_down", False, 0)):
+        sc = R.rkkt_analyze_schedule(inst.net, n, which, sweep_form=form)
         for trans in (False, True):
             got = _sweep(sc, vals, b, nx, up, trans)
             if up:
@@ -130,16 +131,17 @@ def test_refactor_schedule_reproduces_dense_lu(case):
 
 
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
-@pytest.mark.parametrize("which", ["reduce_up", "reduce_down", "step_up", "step_down"])
-def test_sweep_phases_group_destinations(case, which):
+@pytest.mark.parametrize("which,form", [("reduce_up", 0), ("reduce_down", 0), ("reduce_up", 2),
+                                        ("reduce_down", 2), ("step_up", 0), ("step_down", 0)])
+def test_sweep_phases_group_destinations(case, which, form):
     """What the sweeps that read a phase's values ahead rely on: within a
     phase no row is both a destination and a source, every destination
     belongs to one slot, and a slot's entries for one destination are
-    contiguous."""
+    contiguous (push and pull forms of the reduction's schedules)."""
     name, n = case
     inst = sg.preset(name)
     n = n or inst.scen.n_scen
-    sc = R.rkkt_analyze_schedule(inst.net, n, which)
+    sc = R.rkkt_analyze_schedule(inst.net, n, which, sweep_form=form)
     P, S, ptr, ent = sc["nphase"], sc["slots"], sc["ptr"], sc["ent"]
     for q in range(P):
         dsts, srcs, owner = set(), set(), {}
@@ -154,3 +156,37 @@ def test_sweep_phases_group_destinations(case, which):
                     assert d not in runs, (q, sl, d)
                     runs.append(d)
         assert not (dsts & srcs), q
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("which", ["reduce_up", "reduce_down"])
+def test_pull_form_writes_each_row_in_few_pieces(case, which):
+    """The pull form writes a row once per piece of at most 16 terms (a row's
+    pieces lie in distinct phases, each in one slot), far fewer row writes
+    than the push form, and it holds the same pairs as the push form."""
+    name, n = case
+    inst = sg.preset(name)
+    n = n or inst.scen.n_scen
+    pull = R.rkkt_analyze_schedule(inst.net, n, which, sweep_form=2)
+    push = R.rkkt_analyze_schedule(inst.net, n, which, sweep_form=1)
+
+    def pieces(sc):
+        P, S, ptr, ent = sc["nphase"], sc["slots"], sc["ptr"], sc["ent"]
+        out = {}
+        for q in range(P):
+            for sl in range(S):
+                for e in range(ptr[q * S + sl], ptr[q * S + sl + 1]):
+                    out.setdefault((int(ent[e][0]), q), set()).add(sl)
+        return out
+    pp, pu = pieces(pull), pieces(push)
+    assert all(len(v) == 1 for v in pp.values())
+    terms = {}
+    for d in pull["ent"][:, 0]:
+        terms[int(d)] = terms.get(int(d), 0) + 1
+    per_row = {}
+    for (d, q) in pp:
+        per_row[d] = per_row.get(d, 0) + 1
+    assert all(per_row[d] <= -(-terms[d] // 16) for d in terms)
+    assert len(pp) <= len(pu)
+    key = lambda a: sorted(map(tuple, a.tolist()))  # noqa: E731
+    assert key(pull["ent"]) == key(push["ent"])

@@ -50,6 +50,21 @@ int rkkt_mlp_get_params(const rkkt_mlp* m, float* params, hipStream_t stream);
 /* y [batch][out] = network(x [batch][in]). */
 int rkkt_mlp_forward(rkkt_mlp* m, const float* x, int batch, float* y, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid allocation): the same
+ * y [batch][out] = network(x [batch][in]) as rkkt_mlp_forward, with the
+ * input and hidden activations in a static 8 MiB device workspace of the
+ * library instead of the handle's buffers, so batch is limited by that
+ * workspace (not by batch_max): sum over layers l < n_layers of batch
+ * rounded-up-to-8(sizes[l]) BF16 values, each layer's region rounded up to
+ * 256 bytes, must fit in 8 MiB (2416 rows for 198 -> 512 -> 512 -> 512 -> 896);
+ * a larger batch returns -1 with the limit in the message.  Allocates
+ * nothing, frees nothing, does not synchronise.  Every call on a GPU shares
+ * that GPU's workspace, which keeps the last call's contents: calls that
+ * overlap on one GPU (two streams, two threads) race and must be ordered by
+ * the caller.  The handle is only read (its parameters). */
+int rkkt_mlp_forward_static(const rkkt_mlp* m, const float* x, int batch, float* y, hipStream_t stream);
+
 /* Loss (loss[0], device) and its gradient with respect to every parameter
  * (grads [n_params], parameter layout; may be NULL) at the current
  * parameters, for targets t [batch][out]. */

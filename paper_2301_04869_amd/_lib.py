@@ -29,7 +29,7 @@ EXPORTS = ("rkkt_create", "rkkt_analyze", "rkkt_set_loads", "rkkt_dims_get", "rk
            "rkkt_analyze_schedule", "rkkt_set_line_status", "rkkt_solve_warm")
 MLP_EXPORTS = ("rkkt_mlp_create", "rkkt_mlp_destroy", "rkkt_mlp_last_error", "rkkt_mlp_n_params",
                "rkkt_mlp_set_params", "rkkt_mlp_get_params", "rkkt_mlp_forward", "rkkt_mlp_gradients",
-               "rkkt_mlp_train_step")
+               "rkkt_mlp_train_step", "rkkt_mlp_forward_static")
 IPM_STATUS = {0: "converged", 1: "max_iter", 2: "line_search_failed",
               3: "inertia_correction_failed", 4: "device_error"}
 STAGES = ("evaluate", "condense_values", "refactor", "reduce", "scenario_sum", "factor",
@@ -159,10 +159,11 @@ def lib():
     L.rkkt_mlp_set_params.argtypes = [vp, vp, vp]
     L.rkkt_mlp_get_params.argtypes = [vp, vp, vp]
     L.rkkt_mlp_forward.argtypes = [vp, vp, ctypes.c_int, vp, vp]
+    L.rkkt_mlp_forward_static.argtypes = [vp, vp, ctypes.c_int, vp, vp]
     L.rkkt_mlp_gradients.argtypes = [vp, vp, vp, ctypes.c_int, vp, vp, vp]
     L.rkkt_mlp_train_step.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_float, vp, vp]
     for name in ("rkkt_mlp_create", "rkkt_mlp_destroy", "rkkt_mlp_set_params", "rkkt_mlp_get_params",
-                 "rkkt_mlp_forward", "rkkt_mlp_gradients", "rkkt_mlp_train_step"):
+                 "rkkt_mlp_forward", "rkkt_mlp_gradients", "rkkt_mlp_train_step", "rkkt_mlp_forward_static"):
         getattr(L, name).restype = ctypes.c_int
     for name in EXPORTS:
         if name != "rkkt_last_error":
@@ -550,6 +551,13 @@ class Mlp:
         b = x.shape[0]
         self._check(lib().rkkt_mlp_forward(self.ptr, _fptr(x, "x", b * self.sizes[0]), b,
                                            _fptr(y, "y", b * self.sizes[-1]), _stream(stream)))
+
+    def forward_static(self, x, y, stream=None):
+        """rkkt_mlp_forward_static: the forward pass in the library's static
+        workspace (no allocation; batch limited by that workspace)."""
+        b = x.shape[0]
+        self._check(lib().rkkt_mlp_forward_static(self.ptr, _fptr(x, "x", b * self.sizes[0]), b,
+                                                  _fptr(y, "y", b * self.sizes[-1]), _stream(stream)))
 
     def gradients(self, x, t, grads, loss, stream=None):
         b = x.shape[0]

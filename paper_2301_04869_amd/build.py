@@ -8,8 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["symbolic.cpp", "api.cpp", "ipm.cpp", "mlp.cpp", "k_eval.hip", "k_lu.hip", "k_dense.hip", "k_ipm.hip",
-           "k_mlp.hip"]
+SOURCES = ["symbolic.cpp", "api.cpp", "ipm.cpp", "k_eval.hip", "k_lu.hip", "k_dense.hip", "k_ipm.hip",
+           "k_mlp.hip", "mlp.hip"]
 LIB = os.path.join(HERE, "librkkt.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

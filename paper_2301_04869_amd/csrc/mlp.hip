@@ -2,6 +2,7 @@
 // forward pass, backward pass and Adam step, all in k_mlp.hip (BF16 products
 // on the matrix cores with FP32 accumulation and fused epilogues).
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -129,6 +130,50 @@ int gradients_impl(rkkt_mlp* m, const float* x, const float* t, int B, float* lo
   return check(m, "rkkt_mlp backward");
 }
 
+// ---- forward pass without the handle's workspace (rkkt_mlp_forward_static)
+// The BF16 input and hidden activations of that call live in `scratch`, one
+// copy per GPU for the life of the process.  In host code the array's name
+// only stands for the device symbol: its device address comes from
+// hipGetSymbolAddress, looked up once per device with that device current
+// (by rkkt_mlp_create, else by the first call on the device) and kept in
+// g_scratch_dev.
+constexpr size_t kMlpStaticBytes = 8u << 20;
+static __device__ __align__(256) unsigned char scratch[kMlpStaticBytes];
+constexpr int kMaxDevices = 64;
+void* g_scratch_dev[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// device address of `scratch` on the current device, or nullptr
+void* scratch_address(std::string* err) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    *err = std::string("no usable current device: ") + hipGetErrorString(e);
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      *err = std::string("hipGetSymbolAddress of the static workspace: ") + hipGetErrorString(e);
+      return nullptr;
+    }
+    g_scratch_dev[dev] = ptr;
+  }
+  return g_scratch_dev[dev];
+}
+
+inline size_t align256(size_t n) { return (n + 255) / 256 * 256; }
+
+// bytes of `scratch` that B rows need: A_l [B][pad8(sz[l])] BF16 for every
+// layer input, each region 256-byte aligned
+size_t static_bytes(const rkkt_mlp* m, long long B) {
+  size_t n = 0;
+  for (int l = 0; l < m->L; ++l) n += align256((size_t)B * mlp_pad8(m->sz[l]) * sizeof(uint16_t));
+  return n;
+}
+
 int args_ok(rkkt_mlp* m, int B, const char* where) {
   if (!m) return fail(nullptr, -1, std::string(where) + ": null handle");
   if (B < 1 || B > m->bmax) return fail(m, -1, std::string(where) + ": batch outside [1, batch_max]");
@@ -196,6 +241,13 @@ int rkkt_mlp_create(const int* sizes, int n_layers, int batch_max, rkkt_mlp** ou
     e = hipDeviceSynchronize();
     if (e == hipSuccess) e = hipGetLastError();
   }
+  if (e == hipSuccess) {
+    std::string msg;
+    if (!scratch_address(&msg)) {
+      rkkt_mlp_destroy(m);
+      return fail(nullptr, -2, "rkkt_mlp_create: " + msg);
+    }
+  }
   if (e != hipSuccess) {
     std::string msg = std::string("rkkt_mlp_create: ") + hipGetErrorString(e);
     rkkt_mlp_destroy(m);
@@ -239,6 +291,55 @@ int rkkt_mlp_forward(rkkt_mlp* m, const float* x, int batch, float* y, hipStream
   if (!x || !y) return fail(m, -1, "rkkt_mlp_forward: null array");
   (void)hipGetLastError();
   return forward_impl(m, x, batch, y, false, st);
+}
+
+int rkkt_mlp_forward_static(const rkkt_mlp* mc, const float* x, int batch, float* y, hipStream_t st) {
+  rkkt_mlp* m = const_cast<rkkt_mlp*>(mc);  // only its error string is written
+  if (!m) return fail(nullptr, -1, "rkkt_mlp_forward_static: null handle");
+  if (!x || !y) return fail(m, -1, "rkkt_mlp_forward_static: null array");
+  if (batch < 1) return fail(m, -1, "rkkt_mlp_forward_static: batch < 1");
+  const size_t need = static_bytes(m, batch);
+  if (need > kMlpStaticBytes) {
+    long long rows = 0;
+    while (static_bytes(m, rows + 1) <= kMlpStaticBytes) ++rows;
+    return fail(m, -1, "rkkt_mlp_forward_static: " + std::to_string(batch) + " rows need " +
+                           std::to_string(need) + " bytes of the " + std::to_string(kMlpStaticBytes) +
+                           "-byte static workspace (at most " + std::to_string(rows) +
+                           " rows for this network)");
+  }
+  std::string msg;
+  unsigned char* base = static_cast<unsigned char*>(scratch_address(&msg));
+  if (!base) return fail(m, -2, "rkkt_mlp_forward_static: " + msg);
+  (void)hipGetLastError();
+  std::vector<uint16_t*> act(m->L);
+  size_t off = 0;
+  for (int l = 0; l < m->L; ++l) {
+    act[l] = reinterpret_cast<uint16_t*>(base + off);
+    off += align256((size_t)batch * mlp_pad8(m->sz[l]) * sizeof(uint16_t));
+  }
+  rkkt::mlp_input_bf16(x, batch, m->sz[0], act[0], mlp_pad8(m->sz[0]), nullptr, 0, st);
+  for (int l = 0; l < m->L; ++l) {
+    const int fi = m->sz[l], fo = m->sz[l + 1];
+    const bool last = l + 1 == m->L;
+    rkkt::MlpGemm g{};
+    g.A = act[l];
+    g.lda = mlp_pad8(fi);
+    g.B = m->wt + m->lay.wt_off[l];
+    g.ldb = m->lay.fi_p[l];
+    g.M = batch;
+    g.N = fo;
+    g.K = fi;
+    g.bias = m->p + m->boff[l];
+    g.ldz = fo;
+    if (!last) {
+      g.hout = act[l + 1];
+      g.ldh = mlp_pad8(fo);
+    } else {
+      g.y = y;
+    }
+    rkkt::mlp_gemm(last ? rkkt::kMlpBiasOut : rkkt::kMlpBiasGelu, g, st);
+  }
+  return check(m, "rkkt_mlp_forward_static");
 }
 
 int rkkt_mlp_gradients(rkkt_mlp* m, const float* x, const float* t, int batch, float* grads, float* loss,

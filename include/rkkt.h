@@ -388,17 +388,13 @@ int rkkt_graph_capture(rkkt_problem* p, const rkkt_iteration* it);
 int rkkt_graph_launch(rkkt_problem* p, hipStream_t stream);
 
 /*
- * Independent instances of uneven sizes in one launch (the paper batches
- * independent blocks on one device; here whole instances of different
- * sizes): the pass of each of n distinct handles (each with its own
- * rkkt_iteration) is captured by rkkt_graph_capture on that handle, which
- * replaces the handle's own captured graph, and the n graphs become
- * independent child nodes of one HIP graph, replayed by a single
- * rkkt_batch_launch.  Each handle keeps its own reduced matrix (no sum across
- * instances).  The batch holds copies of the instance graphs and does not own
- * the handles; they and every buffer named in `its` must outlive it.
- * RKKT_ERR_ARG if a handle appears twice (its workspace would be shared);
- * an instance that fails to capture is named in the message.
+ * Graph batch of independent instances (rkkt_batch_create / launch /
+ * destroy): switched off.  A capture of several instances whose passes forked
+ * to side streams ended in a host segmentation fault inside this call and
+ * the cause was not shown, so rkkt_batch_create returns RKKT_ERR_ARG with
+ * that message and creates nothing; rkkt_batch_launch and
+ * rkkt_batch_destroy accept only what it would return.  Independent
+ * instances in one launch per stage: rkkt_multi_* below.
  */
 typedef struct rkkt_batch rkkt_batch;
 

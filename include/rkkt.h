@@ -396,6 +396,37 @@ int rkkt_graph_launch(rkkt_problem* p, hipStream_t stream);
  * rkkt_batch_destroy accept only what it would return.  Independent
  * instances in one launch per stage: rkkt_multi_* below.
  */
+/*
+ * Independent instances of uneven sizes in one launch per kernel
+ * configuration (the paper batches the independent scenario blocks of one
+ * problem on a device, parallel KKT solver section; here whole independent
+ * problems of different sizes, each with its own scenarios and reduced
+ * matrix, no sum across instances).  rkkt_multi_create takes n distinct
+ * handles (each created by rkkt_create with its own, possibly autotuned,
+ * launch shape) and one rkkt_iteration per handle (device buffers that must
+ * outlive the multi handle; their addresses are copied to the device here).
+ * rkkt_multi_iterate runs, for every instance, the pass of rkkt_iterate
+ * (evaluate, condense, factor, step) on one stream, with every kernel of the
+ * pass launched once for all instances that use the same kernel variant and
+ * block size: a table maps each block to (instance, block of that instance's
+ * own grid), the dynamic LDS is the group's largest; the outputs equal
+ * rkkt_iterate's bit for bit.  rkkt_multi_launches gives the number of
+ * launches of one pass.  rkkt_multi_capture records that pass as one HIP
+ * graph (one stream, no forks) and rkkt_multi_launch replays it.  The handles
+ * are not owned and must outlive the multi handle; rkkt_status on each handle
+ * reports its own device status.  Errors: RKKT_ERR_ARG (null or repeated
+ * handle, null array, non-finite scalar, instances on different devices),
+ * RKKT_ERR_HIP, RKKT_ERR_NOMEM; message in rkkt_multi_last_error.
+ */
+typedef struct rkkt_multi rkkt_multi;
+int rkkt_multi_create(rkkt_problem* const* problems, const rkkt_iteration* its, int n, rkkt_multi** out);
+int rkkt_multi_iterate(rkkt_multi* m, hipStream_t stream);
+int rkkt_multi_capture(rkkt_multi* m);
+int rkkt_multi_launch(rkkt_multi* m, hipStream_t stream);
+int rkkt_multi_launches(const rkkt_multi* m);
+int rkkt_multi_destroy(rkkt_multi* m);
+const char* rkkt_multi_last_error(const rkkt_multi* m);
+
 typedef struct rkkt_batch rkkt_batch;
 
 /*

@@ -7,7 +7,7 @@ from ._lib import (RkktError, lib, rkkt_analyze, rkkt_create, rkkt_set_loads, rk
                    rkkt_solve, rkkt_solve_warm, rkkt_iterate, rkkt_graph_capture, rkkt_graph_launch,
                    rkkt_batch_create, rkkt_batch_launch, rkkt_batch_destroy, rkkt_autotune,
                    rkkt_analyze_lu, rkkt_analyze_schedule, SCHEDULES, EXPORTS, STAGES, LIB_PATH,
-                   Mlp, mlp_layout, MLP_EXPORTS)
+                   Mlp, Multi, mlp_layout, MLP_EXPORTS)
 
 __all__ = ["RkktError", "lib", "rkkt_analyze", "rkkt_create", "rkkt_set_loads", "rkkt_set_line_status", "rkkt_dims_get",
            "rkkt_evaluate", "rkkt_condense", "rkkt_factor", "rkkt_step", "rkkt_status",
@@ -15,4 +15,4 @@ __all__ = ["RkktError", "lib", "rkkt_analyze", "rkkt_create", "rkkt_set_loads", 
            "rkkt_solve", "rkkt_solve_warm", "rkkt_iterate", "rkkt_graph_capture",
            "rkkt_graph_launch", "rkkt_batch_create", "rkkt_batch_launch", "rkkt_batch_destroy",
            "rkkt_autotune", "rkkt_analyze_lu", "rkkt_analyze_schedule", "SCHEDULES", "EXPORTS",
-           "STAGES", "LIB_PATH", "Mlp", "mlp_layout", "MLP_EXPORTS"]
+           "STAGES", "LIB_PATH", "Mlp", "Multi", "mlp_layout", "MLP_EXPORTS"]

@@ -26,7 +26,9 @@ EXPORTS = ("rkkt_create", "rkkt_analyze", "rkkt_set_loads", "rkkt_dims_get", "rk
            "rkkt_last_error", "rkkt_profile_begin", "rkkt_profile_end", "rkkt_solve",
            "rkkt_iterate", "rkkt_graph_capture", "rkkt_graph_launch", "rkkt_batch_create",
            "rkkt_batch_launch", "rkkt_batch_destroy", "rkkt_autotune", "rkkt_analyze_lu",
-           "rkkt_analyze_schedule", "rkkt_set_line_status", "rkkt_solve_warm")
+           "rkkt_analyze_schedule", "rkkt_set_line_status", "rkkt_solve_warm", "rkkt_multi_create",
+           "rkkt_multi_iterate", "rkkt_multi_capture", "rkkt_multi_launch", "rkkt_multi_launches",
+           "rkkt_multi_destroy", "rkkt_multi_last_error")
 MLP_EXPORTS = ("rkkt_mlp_create", "rkkt_mlp_destroy", "rkkt_mlp_last_error", "rkkt_mlp_n_params",
                "rkkt_mlp_set_params", "rkkt_mlp_get_params", "rkkt_mlp_forward", "rkkt_mlp_gradients",
                "rkkt_mlp_train_step", "rkkt_mlp_forward_static")
@@ -137,6 +139,15 @@ def lib():
     L.rkkt_iterate.argtypes = [vp, ctypes.POINTER(Iteration), vp]
     L.rkkt_graph_capture.argtypes = [vp, ctypes.POINTER(Iteration)]
     L.rkkt_graph_launch.argtypes = [vp, vp]
+    L.rkkt_multi_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Iteration), ctypes.c_int,
+                                    ctypes.POINTER(vp)]
+    L.rkkt_multi_iterate.argtypes = [vp, vp]
+    L.rkkt_multi_capture.argtypes = [vp]
+    L.rkkt_multi_launch.argtypes = [vp, vp]
+    L.rkkt_multi_launches.argtypes = [vp]
+    L.rkkt_multi_destroy.argtypes = [vp]
+    L.rkkt_multi_last_error.argtypes = [vp]
+    L.rkkt_multi_last_error.restype = ctypes.c_char_p
     L.rkkt_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Iteration), ctypes.c_int,
                                     ctypes.POINTER(vp)]
     L.rkkt_batch_launch.argtypes = [vp, vp]
@@ -166,7 +177,7 @@ def lib():
                  "rkkt_mlp_forward", "rkkt_mlp_gradients", "rkkt_mlp_train_step", "rkkt_mlp_forward_static"):
         getattr(L, name).restype = ctypes.c_int
     for name in EXPORTS:
-        if name != "rkkt_last_error":
+        if not name.endswith("last_error"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -465,6 +476,45 @@ def rkkt_graph_capture(p, args):
 
 def rkkt_graph_launch(p, stream=None):
     _check(lib().rkkt_graph_launch(p.ptr, _stream(stream)), p.ptr)
+
+
+class Multi:
+    """An rkkt_multi* (independent instances, one launch per kernel
+    configuration) with the handles and buffers it uses (kept alive with it)."""
+
+    def __init__(self, handles, args_list):
+        n = len(handles)
+        arr = (ctypes.c_void_p * n)(*[h.ptr for h in handles])
+        its = (Iteration * n)(*[_iteration(h, a) for h, a in zip(handles, args_list)])
+        ptr = ctypes.c_void_p()
+        rc = lib().rkkt_multi_create(arr, its, n, ctypes.byref(ptr))
+        if rc != RKKT_OK:
+            raise RkktError(rc, lib().rkkt_multi_last_error(None).decode())
+        self.ptr = ptr
+        self.handles = list(handles)
+        self.args = list(args_list)
+
+    def _check(self, rc):
+        if rc != RKKT_OK:
+            raise RkktError(rc, lib().rkkt_multi_last_error(self.ptr).decode())
+
+    def iterate(self, stream=None):
+        self._check(lib().rkkt_multi_iterate(self.ptr, _stream(stream)))
+
+    def capture(self):
+        self._check(lib().rkkt_multi_capture(self.ptr))
+
+    def launch(self, stream=None):
+        self._check(lib().rkkt_multi_launch(self.ptr, _stream(stream)))
+
+    @property
+    def n_launches(self):
+        return int(lib().rkkt_multi_launches(self.ptr))
+
+    def __del__(self):
+        if getattr(self, "ptr", None) and _lib is not None:
+            _lib.rkkt_multi_destroy(self.ptr)
+            self.ptr = None
 
 
 class Batch:

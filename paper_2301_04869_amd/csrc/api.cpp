@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstring>
 #include <string>
+#include <tuple>
 #include <type_traits>
 #include <vector>
 
@@ -643,6 +644,184 @@ int rkkt_batch_create(rkkt_problem* const* problems, const rkkt_iteration* its, 
               "rkkt_batch_create: switched off (a multi-instance graph capture ended in a host fault whose "
               "cause is not shown); run instances one handle at a time");
 }
+
+// ---- independent instances, one launch per kernel configuration
+// The pass of every instance (rkkt_iterate on one stream) is listed as
+// launches (launches_eval / _lu / _dense); launches with equal place in the
+// pass, kernel, template variant, block size and panel column become one
+// launch whose blocks map back to (instance, block) through a table, with
+// the largest dynamic LDS of the group.  Every block runs the same code on
+// the same data as in the instance's own launch, so the results are the
+// same bit for bit.
+struct rkkt_multi {
+  struct Group {
+    rkkt::Launch l;
+    unsigned nblk = 0;
+    long long lds = 0;
+    size_t off = 0;  // first entry of its block table
+  };
+  std::vector<rkkt_problem*> probs;
+  std::vector<Group> groups;
+  rkkt::DP* dps = nullptr;
+  rkkt_iteration* its = nullptr;
+  rkkt::MultiBlk* blk = nullptr;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::string err;
+};
+
+static std::string g_multi_err;
+static int multi_fail(rkkt_multi* m, int code, const std::string& msg) {
+  (m ? m->err : g_multi_err) = msg;
+  return code;
+}
+static hipError_t multi_dispatch(const rkkt_multi* m, const rkkt_multi::Group& g, hipStream_t s, bool prepare) {
+  bool handled = false;
+  const rkkt::MultiBlk* blk = m->blk + g.off;
+  hipError_t e = rkkt::multi_eval(g.l, g.nblk, g.lds, m->dps, m->its, blk, s, prepare, &handled);
+  if (!handled) e = rkkt::multi_lu(g.l, g.nblk, g.lds, m->dps, m->its, blk, s, prepare, &handled);
+  if (!handled) e = rkkt::multi_dense(g.l, g.nblk, g.lds, m->dps, m->its, blk, s, prepare, &handled);
+  if (!handled) return hipErrorInvalidValue;
+  return e;
+}
+
+int rkkt_multi_destroy(rkkt_multi* m) {
+  if (!m) return RKKT_OK;
+  if (m->gexec) (void)hipGraphExecDestroy(m->gexec);
+  if (m->graph) (void)hipGraphDestroy(m->graph);
+  if (m->cap) (void)hipStreamDestroy(m->cap);
+  (void)hipFree(m->dps);
+  (void)hipFree(m->its);
+  (void)hipFree(m->blk);
+  delete m;
+  return RKKT_OK;
+}
+
+const char* rkkt_multi_last_error(const rkkt_multi* m) { return m ? m->err.c_str() : g_multi_err.c_str(); }
+
+int rkkt_multi_create(rkkt_problem* const* problems, const rkkt_iteration* its, int n, rkkt_multi** out) {
+  if (!problems || !its || !out || n < 1) return multi_fail(nullptr, RKKT_ERR_ARG, "rkkt_multi_create: bad argument");
+  *out = nullptr;
+  for (int i = 0; i < n; ++i) {
+    if (!problems[i]) return multi_fail(nullptr, RKKT_ERR_ARG, "rkkt_multi_create: null handle");
+    if (problems[i]->device != problems[0]->device)
+      return multi_fail(nullptr, RKKT_ERR_ARG, "rkkt_multi_create: instances on different devices");
+    for (int j = 0; j < i; ++j)
+      if (problems[j] == problems[i])
+        return multi_fail(nullptr, RKKT_ERR_ARG,
+                          "rkkt_multi_create: instance " + std::to_string(i) + " repeats the handle of instance " +
+                              std::to_string(j) + " (instances of one handle share its workspace)");
+    const rkkt_iteration& it = its[i];
+    if (!it.x || !it.u || !it.y || !it.z || !it.f || !it.grad_x || !it.grad_u || !it.g || !it.h ||
+        !it.sigma_x || !it.sigma_u || !it.sigma_s || !it.khat || !it.chol || !it.info || !it.r1x || !it.r1u ||
+        !it.r2 || !it.r3 || !it.r4 || !it.px || !it.pu || !it.ps || !it.py || !it.pz)
+      return multi_fail(nullptr, RKKT_ERR_ARG, "rkkt_multi_create: instance " + std::to_string(i) + ": null array");
+    if (!std::isfinite(it.obj_weight) || !std::isfinite(it.delta_w))
+      return multi_fail(nullptr, RKKT_ERR_ARG,
+                        "rkkt_multi_create: instance " + std::to_string(i) + ": non-finite obj_weight or delta_w");
+  }
+  (void)hipGetLastError();
+  // every instance's launches, grouped
+  struct Item {
+    rkkt::Launch l;
+    int inst;
+  };
+  std::vector<Item> items;
+  for (int i = 0; i < n; ++i) {
+    std::vector<rkkt::Launch> ls;
+    const rkkt::DP& d = problems[i]->d;
+    rkkt::launches_eval(d, ls);
+    rkkt::launches_lu(d, ls);
+    rkkt::launches_dense(d, ls);
+    for (const auto& l : ls) items.push_back({l, i});
+  }
+  auto gkey = [](const rkkt::Launch& l) { return std::make_tuple(l.key, l.kernel, l.variant, l.threads, l.jb); };
+  std::stable_sort(items.begin(), items.end(), [&](const Item& a, const Item& b) { return gkey(a.l) < gkey(b.l); });
+  rkkt_multi* m = new rkkt_multi();
+  m->probs.assign(problems, problems + n);
+  std::vector<rkkt::MultiBlk> table;
+  for (size_t a = 0; a < items.size();) {
+    size_t b = a;
+    rkkt_multi::Group g;
+    g.l = items[a].l;
+    g.off = table.size();
+    while (b < items.size() && gkey(items[b].l) == gkey(items[a].l)) {
+      const rkkt::Launch& l = items[b].l;
+      for (int by = 0; by < l.gy; ++by)
+        for (int bx = 0; bx < l.gx; ++bx) table.push_back({items[b].inst, bx, by, l.gx});
+      g.lds = std::max(g.lds, l.lds);
+      ++b;
+    }
+    g.nblk = (unsigned)(table.size() - g.off);
+    if (g.nblk > 0) m->groups.push_back(g);
+    a = b;
+  }
+  std::vector<rkkt::DP> hd(n);
+  for (int i = 0; i < n; ++i) hd[i] = problems[i]->d;
+  hipError_t e = hipSetDevice(problems[0]->device);
+  if (e == hipSuccess) e = hipMalloc((void**)&m->dps, sizeof(rkkt::DP) * n);
+  if (e == hipSuccess) e = hipMalloc((void**)&m->its, sizeof(rkkt_iteration) * n);
+  if (e == hipSuccess) e = hipMalloc((void**)&m->blk, sizeof(rkkt::MultiBlk) * std::max<size_t>(table.size(), 1));
+  if (e == hipSuccess) e = hipMemcpy(m->dps, hd.data(), sizeof(rkkt::DP) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->its, its, sizeof(rkkt_iteration) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess && !table.empty())
+    e = hipMemcpy(m->blk, table.data(), sizeof(rkkt::MultiBlk) * table.size(), hipMemcpyHostToDevice);
+  for (size_t q = 0; q < m->groups.size() && e == hipSuccess; ++q) e = multi_dispatch(m, m->groups[q], nullptr, true);
+  if (e != hipSuccess) {
+    const std::string msg = std::string("rkkt_multi_create: ") + hipGetErrorString(e);
+    rkkt_multi_destroy(m);
+    return multi_fail(nullptr, e == hipErrorOutOfMemory ? RKKT_ERR_NOMEM : RKKT_ERR_HIP, msg);
+  }
+  *out = m;
+  return RKKT_OK;
+}
+
+int rkkt_multi_iterate(rkkt_multi* m, hipStream_t stream) {
+  if (!m) return multi_fail(nullptr, RKKT_ERR_ARG, "rkkt_multi_iterate: null handle");
+  (void)hipGetLastError();
+  for (const auto& g : m->groups) {
+    hipError_t e = multi_dispatch(m, g, stream, false);
+    if (e != hipSuccess) return multi_fail(m, RKKT_ERR_HIP, std::string("rkkt_multi_iterate: ") + hipGetErrorString(e));
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return multi_fail(m, RKKT_ERR_HIP, std::string("rkkt_multi_iterate: ") + hipGetErrorString(e));
+  return RKKT_OK;
+}
+
+int rkkt_multi_capture(rkkt_multi* m) {
+  if (!m) return multi_fail(nullptr, RKKT_ERR_ARG, "rkkt_multi_capture: null handle");
+  if (m->gexec) (void)hipGraphExecDestroy(m->gexec);
+  if (m->graph) (void)hipGraphDestroy(m->graph);
+  m->gexec = nullptr;
+  m->graph = nullptr;
+  hipError_t e = hipSuccess;
+  if (!m->cap) e = hipStreamCreateWithFlags(&m->cap, hipStreamNonBlocking);
+  if (e != hipSuccess) return multi_fail(m, RKKT_ERR_HIP, std::string("rkkt_multi_capture: ") + hipGetErrorString(e));
+  e = hipStreamBeginCapture(m->cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return multi_fail(m, RKKT_ERR_HIP, std::string("rkkt_multi_capture: ") + hipGetErrorString(e));
+  const int rc = rkkt_multi_iterate(m, m->cap);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(m->cap, &g);
+  if (rc != RKKT_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return multi_fail(m, RKKT_ERR_HIP, std::string("rkkt_multi_capture: ") + hipGetErrorString(e));
+  m->graph = g;
+  e = hipGraphInstantiate(&m->gexec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) return multi_fail(m, RKKT_ERR_HIP, std::string("rkkt_multi_capture: ") + hipGetErrorString(e));
+  return RKKT_OK;
+}
+
+int rkkt_multi_launch(rkkt_multi* m, hipStream_t stream) {
+  if (!m || !m->gexec) return multi_fail(m, RKKT_ERR_ARG, "rkkt_multi_launch: nothing captured");
+  hipError_t e = hipGraphLaunch(m->gexec, stream);
+  if (e != hipSuccess) return multi_fail(m, RKKT_ERR_HIP, std::string("rkkt_multi_launch: ") + hipGetErrorString(e));
+  return RKKT_OK;
+}
+
+int rkkt_multi_launches(const rkkt_multi* m) { return m ? (int)m->groups.size() : 0; }
 
 // Launch-shape autotuner.  Stage 1 times `reps` condense calls (the
 // reduction dominates them) for every reduction variant x column tile; stage

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <utility>
+#include <vector>
 
 #include "layout.h"
 #include "rkkt.h"
@@ -196,5 +197,43 @@ void launch_cholesky(const DP& d, double* a, int* info, hipStream_t s);
 void launch_cholesky_from(const DP& d, const double* src, double* dst, int* info, hipStream_t s);
 void launch_reduced_solve(const DP& d, const double* r1u, const double* chol, double* pu,
                           hipStream_t s);
+
+// ---- several independent instances, one launch per kernel configuration
+// (rkkt_multi_*).  A Launch is one kernel launch of an instance's pass as its
+// single-instance launcher issues it: kernel, template variant, grid gx x gy,
+// block threads, dynamic LDS bytes, and for the blocked Cholesky the panel's
+// first column jb.  key orders the launches of a pass (stage * 4096 + place
+// in the stage), so launches of equal key, kernel, variant and threads from
+// several instances become one launch whose blocks map back through MultiBlk.
+struct Launch {
+  int key, kernel, variant, gx, gy, threads, jb;
+  long long lds;
+};
+struct MultiBlk {
+  int inst, bx, by, gx;  // block (bx, by) of instance inst's own grid of width gx
+};
+enum : int {
+  kKLineEvalGather = 1, kKLineEval, kKGatherEv, kKAssemble, kKLineHess, kKWGather, kKCondense,
+  kKRefactor, kKReduce64, kKReduce, kKStepRhs2, kKStepRhs, kKStepRec2, kKStepRec,
+  kKStacked, kKSymSum, kKCholSmall, kKCopyChol, kKSetInfo, kKCholDiag, kKCholTrsm, kKCholUpdate,
+  kKRSolveBlk, kKRSolve
+};
+enum : int {
+  kStEvalValues = 0, kStEvalRest, kStCondense, kStRefactor, kStReduce, kStStepRhs, kStStacked,
+  kStSum, kStFactor, kStRSolve, kStRecover
+};
+// Launches of one pass of instance d (rkkt_iterate on one stream), by stage.
+void launches_eval(const DP& d, std::vector<Launch>& out);        // values, rest, condensed values
+void launches_lu(const DP& d, std::vector<Launch>& out);          // refactor, reduce, step kernels
+void launches_dense(const DP& d, std::vector<Launch>& out);       // product, sum, Cholesky, solve
+// One multi-instance launch of l's kernel over nblk blocks (or, with
+// prepare, only the dynamic-LDS limit of that kernel); *handled is false when
+// the kernel is not in this file.
+hipError_t multi_eval(const Launch& l, unsigned nblk, long long lds, const DP* dps, const rkkt_iteration* its,
+                      const MultiBlk* blk, hipStream_t s, bool prepare, bool* handled);
+hipError_t multi_lu(const Launch& l, unsigned nblk, long long lds, const DP* dps, const rkkt_iteration* its,
+                    const MultiBlk* blk, hipStream_t s, bool prepare, bool* handled);
+hipError_t multi_dense(const Launch& l, unsigned nblk, long long lds, const DP* dps, const rkkt_iteration* its,
+                       const MultiBlk* blk, hipStream_t s, bool prepare, bool* handled);
 
 }  // namespace rkkt

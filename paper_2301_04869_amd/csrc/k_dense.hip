@@ -26,14 +26,14 @@ __global__ void k_set_int(int* p, int v) { *p = v; }
 // result does not depend on scheduling.
 constexpr int kSumEntries = 64, kSumWaves = 16;
 
-__global__ __launch_bounds__(kSumEntries * kSumWaves) void k_sym_sum(DP d, const double* src, int cnt,
+__device__ __forceinline__ void sym_sum_body(int bx_, int by_, int gx_, const DP& d, const double* src, int cnt,
                                                                       const double* su, double dw,
                                                                       double* khat) {
   __shared__ double part[kSumWaves][kSumEntries];
   const int n = d.nu;
   const long long nn = (long long)n * n, ntri = (long long)n * (n + 1) / 2;
   const int lane = threadIdx.x % kSumEntries, wv = threadIdx.x / kSumEntries;
-  const long long t = (long long)blockIdx.x * kSumEntries + lane;
+  const long long t = (long long)bx_ * kSumEntries + lane;
   // t -> (r, c), c <= r, rows in order
   int r = 0, c = 0;
   if (t < ntri) {
@@ -71,6 +71,12 @@ __global__ __launch_bounds__(kSumEntries * kSumWaves) void k_sym_sum(DP d, const
   }
 }
 
+__global__ __launch_bounds__(kSumEntries * kSumWaves) void k_sym_sum(DP d, const double* src, int cnt,
+                                                                      const double* su, double dw,
+                                                                      double* khat) {
+  sym_sum_body((int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, d, src, cnt, su, dw, khat);
+}
+
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 // Stacked product of the reduction's product variant: for chunk c of the
@@ -91,7 +97,7 @@ constexpr int kSlab = 32, kSW = 16 * kSB + 1; // slab rows, LDS row pitch
 
 __host__ __device__ inline int sp_nblk(int nu) { return (nu + 15) / 16; }
 __host__ __device__ inline int sp_nsuper(int nu) { return (sp_nblk(nu) + kSB - 1) / kSB; }
-__host__ inline long long sp_rows_per_chunk(long long rows, int nchunk) {
+__host__ __device__ inline long long sp_rows_per_chunk(long long rows, int nchunk) {
   return ((rows + nchunk - 1) / nchunk + kSlab - 1) / kSlab * kSlab;
 }
 
@@ -99,11 +105,11 @@ __host__ inline long long sp_rows_per_chunk(long long rows, int nchunk) {
 // (a slot past the wavefront's blocks reads block (0, 0) and is not stored),
 // so the accumulators stay in fixed registers with no branches around them
 template <int kSlots>
-__global__ __launch_bounds__(256) void k_stacked_product(DP d, long long per) {
+__device__ __forceinline__ void stacked_product_body(int bx_, int by_, int gx_, const DP& d, long long per) {
   __shared__ double zs[2][kSlab * kSW], ks[2][kSlab * kSW];
-  int t = blockIdx.x, SI = 0;
+  int t = bx_, SI = 0;
   while (t > SI) { t -= SI + 1; ++SI; }
-  const int SJ = t, chunk = blockIdx.y;
+  const int SJ = t, chunk = by_;
   const int nblk = sp_nblk(d.nu);
   const int bi0 = SI * kSB, bj0 = SJ * kSB;
   const int ni = min(kSB, nblk - bi0), nj = min(kSB, nblk - bj0);
@@ -219,6 +225,11 @@ __global__ __launch_bounds__(256) void k_stacked_product(DP d, long long per) {
       }
     }
   }
+}
+
+template <int kSlots>
+__global__ __launch_bounds__(256) void k_stacked_product(DP d, long long per) {
+  stacked_product_body<kSlots>((int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, d, per);
 }
 
 
@@ -487,7 +498,7 @@ __device__ __forceinline__ void chol_tile16_write(const double* raw, double* A, 
   }
 }
 
-__global__ __launch_bounds__(kCholSmallThreads) void k_chol_small(const double* src, double* A, int n,
+__device__ __forceinline__ void chol_small_body(int bx_, int by_, int gx_, const double* src, double* A, int n,
                                                                    int* info) {
   extern __shared__ double sa[];
   __shared__ int sflag;
@@ -597,8 +608,13 @@ __global__ __launch_bounds__(kCholSmallThreads) void k_chol_small(const double* 
   if (tid == 0) *info = sflag;
 }
 
+__global__ __launch_bounds__(kCholSmallThreads) void k_chol_small(const double* src, double* A, int n,
+                                                                   int* info) {
+  chol_small_body((int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, src, A, n, info);
+}
+
 // blocked: factor the 64 x 64 diagonal block at jb
-__global__ __launch_bounds__(kThreads) void k_chol_diag(double* A, int n, int jb, int* info) {
+__device__ __forceinline__ void chol_diag_body(int bx_, int by_, int gx_, double* A, int n, int jb, int* info) {
   if (*info != 0) return;
   __shared__ double sa[kNB * (kNB + 1)];
   __shared__ int sflag;
@@ -614,13 +630,17 @@ __global__ __launch_bounds__(kThreads) void k_chol_diag(double* A, int n, int jb
   if (threadIdx.x == 0 && r) *info = jb + r;
 }
 
+__global__ __launch_bounds__(kThreads) void k_chol_diag(double* A, int n, int jb, int* info) {
+  chol_diag_body((int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, A, n, jb, info);
+}
+
 // blocked: A[i, jb:jb+nb] <- A[i, jb:jb+nb] L_jj^-T for rows below the block.
 // A wavefront takes one row at a time with lane q holding column q; lane q
 // keeps row q of L_jj in registers, so the forward substitution is 64
 // readlane broadcasts and fused multiply-adds with no memory traffic.
 constexpr int kTrsmRowsPerWave = 4;
 
-__global__ __launch_bounds__(kThreads) void k_chol_trsm(double* A, int n, int jb, const int* info) {
+__device__ __forceinline__ void chol_trsm_body(int bx_, int by_, int gx_, double* A, int n, int jb, const int* info) {
   if (*info != 0) return;
   __shared__ double sinv[kNB];
   const int nb = min(kNB, n - jb);
@@ -633,7 +653,7 @@ __global__ __launch_bounds__(kThreads) void k_chol_trsm(double* A, int n, int jb
     sinv[threadIdx.x] = threadIdx.x < nb ? 1.0 / A[(long long)(jb + threadIdx.x) * n + jb + threadIdx.x] : 0.0;
   __syncthreads();
   const int rows = n - jb - nb;
-  for (int r = blockIdx.x * kWavesD + wv; r < rows; r += gridDim.x * kWavesD) {
+  for (int r = bx_ * kWavesD + wv; r < rows; r += gx_ * kWavesD) {
     double* row = A + (long long)(jb + nb + r) * n + jb;
     double v = lane < nb ? row[lane] : 0.0;
 #pragma unroll
@@ -648,17 +668,21 @@ __global__ __launch_bounds__(kThreads) void k_chol_trsm(double* A, int n, int jb
   }
 }
 
+__global__ __launch_bounds__(kThreads) void k_chol_trsm(double* A, int n, int jb, const int* info) {
+  chol_trsm_body((int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, A, n, jb, info);
+}
+
 // blocked: trailing update A[i, l] -= sum_p A[i, p] A[l, p] over the lower
 // 64 x 64 tiles, on the FP64 matrix cores.  Each of the 4 waves owns a 32 x 32
 // quarter as 2 x 2 blocks of v_mfma_f64_16x16x4f64 (A operand: lane holds
 // row lane%16, k = lane/16; B operand: k = lane/16, column lane%16; result
 // register r of a lane: row lane/16 + 4 r, column lane%16).
 
-__global__ __launch_bounds__(kThreads) void k_chol_update(double* A, int n, int jb, const int* info) {
+__device__ __forceinline__ void chol_update_body(int bx_, int by_, int gx_, double* A, int n, int jb, const int* info) {
   if (*info != 0) return;
   const int nb = min(kNB, n - jb);
   const int s0 = jb + nb;
-  const int ti = blockIdx.y, tl = blockIdx.x;
+  const int ti = by_, tl = bx_;
   if (tl > ti) return;
   const int i0 = s0 + ti * 64, l0 = s0 + tl * 64;
   __shared__ double sa[64][kNB + 1];
@@ -692,6 +716,10 @@ __global__ __launch_bounds__(kThreads) void k_chol_update(double* A, int n, int 
       }
 }
 
+__global__ __launch_bounds__(kThreads) void k_chol_update(double* A, int n, int jb, const int* info) {
+  chol_update_body((int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, A, n, jb, info);
+}
+
 // p_u = K_hat^-1 rhs with rhs = -r1u + sum_i rpart_i, from the Cholesky
 // factor L (lower triangle of `L`, row-major).  One workgroup of kRThreads
 // (16 wavefronts).  The right-hand side is summed over scenarios in a fixed
@@ -715,7 +743,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 template <bool kLDS>
-__global__ __launch_bounds__(kRThreads) void k_reduced_solve(DP d, const double* r1u, const double* Lg,
+__device__ __forceinline__ void reduced_solve_body(int bx_, int by_, int gx_, const DP& d, const double* r1u, const double* Lg,
                                                              double* pu) {
   extern __shared__ double sm[];
   __shared__ double red[kRWaves][64];
@@ -818,6 +846,12 @@ __global__ __launch_bounds__(kRThreads) void k_reduced_solve(DP d, const double*
   for (int c = tid; c < n; c += kRThreads) pu[c] = y[c];
 }
 
+template <bool kLDS>
+__global__ __launch_bounds__(kRThreads) void k_reduced_solve(DP d, const double* r1u, const double* Lg,
+                                                             double* pu) {
+  reduced_solve_body<kLDS>((int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, d, r1u, Lg, pu);
+}
+
 // Reduced solve with the factor stored by k_chol_small.  Every wavefront
 // stages the lower block triangle of the factor (16 x 16 tiles, zeros past
 // n) into LDS while summing the scenario parts of the right-hand side.  Then
@@ -869,7 +903,7 @@ __device__ __forceinline__ void rsolve_update(const double* sa, int ld, double* 
   if (g == 0) y[i0 + r] -= acc;
 }
 
-__global__ __launch_bounds__(kIThreads) void k_reduced_solve_blk(DP d, const double* r1u,
+__device__ __forceinline__ void reduced_solve_blk_body(int bx_, int by_, int gx_, const DP& d, const double* r1u,
                                                                  const double* A, double* pu) {
   extern __shared__ double sm[];
   __shared__ double red[kIThreads];
@@ -967,6 +1001,11 @@ __global__ __launch_bounds__(kIThreads) void k_reduced_solve_blk(DP d, const dou
   for (int c = tid; c < n; c += kIThreads) pu[c] = y[c];
 }
 
+__global__ __launch_bounds__(kIThreads) void k_reduced_solve_blk(DP d, const double* r1u,
+                                                                 const double* A, double* pu) {
+  reduced_solve_blk_body((int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, d, r1u, A, pu);
+}
+
 }  // namespace
 
 // raise the dynamic LDS limit of a kernel to what this problem needs (never lowered)
@@ -992,9 +1031,13 @@ hipError_t configure_dense_kernels(const DP& d) {
   return e;
 }
 
-__global__ void k_copy(const double* a, double* b, long long n) {
-  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void copy_body(int bx_, int by_, int gx_, const double* a, double* b, long long n) {
+  long long t = (long long)bx_ * blockDim.x + threadIdx.x;
   if (t < n) b[t] = a[t];
+}
+
+__global__ void k_copy(const double* a, double* b, long long n) {
+  copy_body((int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, a, b, n);
 }
 
 void launch_copy(const double* a, double* b, long long n, hipStream_t s) {
@@ -1056,6 +1099,148 @@ void launch_reduced_solve(const DP& d, const double* r1u, const double* chol, do
     k_reduced_solve<true><<<1, kRThreads, 8 * ((size_t)d.nu * (d.nu + 1) + d.nu), s>>>(d, r1u, chol, pu);
   else
     k_reduced_solve<false><<<1, kRThreads, 8 * (size_t)d.nu, s>>>(d, r1u, chol, pu);
+}
+
+// ---- several instances in one launch (block b is block (blk[b].bx, blk[b].by)
+// of instance blk[b].inst's own grid, blk[b].gx wide)
+#define RKKT_MULTI_ARGS \
+  const DP* __restrict__ dps, const rkkt_iteration* __restrict__ its, const MultiBlk* __restrict__ blk
+#define RKKT_MULTI_PROLOGUE                          \
+  const MultiBlk mb = blk[blockIdx.x];               \
+  const DP& d = dps[mb.inst];                        \
+  const rkkt_iteration& it = its[mb.inst];     \
+  (void)it;
+
+__global__ __launch_bounds__(kSumEntries * kSumWaves) void k_sym_sum_m(RKKT_MULTI_ARGS) {
+  RKKT_MULTI_PROLOGUE
+  sym_sum_body(mb.bx, mb.by, mb.gx, d, d.variant == 2 ? d.gpart : d.part, d.variant == 2 ? d.nchunk : d.N,
+               it.sigma_u, it.delta_w, it.khat);
+}
+template <int kSlots>
+__global__ __launch_bounds__(256) void k_stacked_product_m(RKKT_MULTI_ARGS) {
+  RKKT_MULTI_PROLOGUE
+  stacked_product_body<kSlots>(mb.bx, mb.by, mb.gx, d, sp_rows_per_chunk((long long)d.N * d.nz, d.nchunk));
+}
+__global__ __launch_bounds__(kCholSmallThreads) void k_chol_small_m(RKKT_MULTI_ARGS) {
+  RKKT_MULTI_PROLOGUE
+  chol_small_body(mb.bx, mb.by, mb.gx, it.khat, it.chol, d.nu, it.info);
+}
+__global__ void k_copy_chol_m(RKKT_MULTI_ARGS) {
+  RKKT_MULTI_PROLOGUE
+  copy_body(mb.bx, mb.by, mb.gx, it.khat, it.chol, (long long)d.nu * d.nu);
+}
+__global__ void k_set_info_m(RKKT_MULTI_ARGS) {
+  RKKT_MULTI_PROLOGUE
+  (void)d;
+  if (threadIdx.x == 0) *it.info = 0;
+}
+__global__ __launch_bounds__(kThreads) void k_chol_diag_m(RKKT_MULTI_ARGS, int jb) {
+  RKKT_MULTI_PROLOGUE
+  chol_diag_body(mb.bx, mb.by, mb.gx, it.chol, d.nu, jb, it.info);
+}
+__global__ __launch_bounds__(kThreads) void k_chol_trsm_m(RKKT_MULTI_ARGS, int jb) {
+  RKKT_MULTI_PROLOGUE
+  chol_trsm_body(mb.bx, mb.by, mb.gx, it.chol, d.nu, jb, it.info);
+}
+__global__ __launch_bounds__(kThreads) void k_chol_update_m(RKKT_MULTI_ARGS, int jb) {
+  RKKT_MULTI_PROLOGUE
+  chol_update_body(mb.bx, mb.by, mb.gx, it.chol, d.nu, jb, it.info);
+}
+template <bool kLDS>
+__global__ __launch_bounds__(kRThreads) void k_reduced_solve_m(RKKT_MULTI_ARGS) {
+  RKKT_MULTI_PROLOGUE
+  reduced_solve_body<kLDS>(mb.bx, mb.by, mb.gx, d, it.r1u, it.chol, it.pu);
+}
+__global__ __launch_bounds__(kIThreads) void k_reduced_solve_blk_m(RKKT_MULTI_ARGS) {
+  RKKT_MULTI_PROLOGUE
+  reduced_solve_blk_body(mb.bx, mb.by, mb.gx, d, it.r1u, it.chol, it.pu);
+}
+
+static int stacked_slots_variant(const DP& d) {
+  const int nblk = sp_nblk(d.nu);
+  const int most = nblk > kSB ? kSB * kSB : nblk * (nblk + 1) / 2;
+  const int slots = (most + 3) / 4;
+  return slots <= 1 ? 0 : slots <= 2 ? 1 : slots <= 4 ? 2 : slots <= 7 ? 3 : 4;
+}
+
+// the launches of launch_stacked_product (stacked variant), launch_scenario_sum,
+// launch_cholesky_from (K_hat into the factor) and launch_reduced_solve
+void launches_dense(const DP& d, std::vector<Launch>& out) {
+  const int n = d.nu;
+  if (d.variant == 2) {
+    const int T = sp_nsuper(n);
+    out.push_back(Launch{kStStacked * 4096, kKStacked, stacked_slots_variant(d), T * (T + 1) / 2, d.nchunk, 256,
+                         0, 0});
+  }
+  const long long ntri = (long long)n * (n + 1) / 2;
+  out.push_back(Launch{kStSum * 4096, kKSymSum, 0, (int)((ntri + kSumEntries - 1) / kSumEntries), 1,
+                       kSumEntries * kSumWaves, 0, 0});
+  const int F = kStFactor * 4096;
+  if (n <= kSmallN) {
+    out.push_back(Launch{F, kKCholSmall, 0, 1, 1, kCholSmallThreads, 0, chol_small_lds_bytes(n)});
+  } else {
+    out.push_back(Launch{F, kKCopyChol, 0, (int)(((long long)n * n + kThreads - 1) / kThreads), 1, kThreads, 0, 0});
+    out.push_back(Launch{F + 1, kKSetInfo, 0, 1, 1, 1, 0, 0});
+    for (int jb = 0, q = 0; jb < n; jb += kNB, ++q) {
+      out.push_back(Launch{F + 2 + 3 * q, kKCholDiag, 0, 1, 1, kThreads, jb, 0});
+      const int nb = n - jb < kNB ? n - jb : kNB;
+      const int rest = n - jb - nb;
+      if (rest <= 0) break;
+      out.push_back(Launch{F + 3 + 3 * q, kKCholTrsm, 0,
+                           (rest + kWavesD * kTrsmRowsPerWave - 1) / (kWavesD * kTrsmRowsPerWave), 1, kThreads, jb,
+                           0});
+      const int nt = (rest + 63) / 64;
+      out.push_back(Launch{F + 4 + 3 * q, kKCholUpdate, 0, nt, nt, kThreads, jb, 0});
+    }
+  }
+  if (n <= kSmallN)
+    out.push_back(Launch{kStRSolve * 4096, kKRSolveBlk, 0, 1, 1, kIThreads, 0, rsolve_blk_lds_bytes(n)});
+  else if (rsolve_lds(n))
+    out.push_back(Launch{kStRSolve * 4096, kKRSolve, 1, 1, 1, kRThreads, 0, 8LL * ((long long)n * (n + 1) + n)});
+  else
+    out.push_back(Launch{kStRSolve * 4096, kKRSolve, 0, 1, 1, kRThreads, 0, 8LL * n});
+}
+
+hipError_t multi_dense(const Launch& l, unsigned nblk, long long lds, const DP* dps, const rkkt_iteration* its,
+                       const MultiBlk* blk, hipStream_t s, bool prepare, bool* handled) {
+  *handled = true;
+  const size_t L = (size_t)lds;
+  const unsigned T = (unsigned)l.threads;
+  static int cur[8] = {};
+  auto go = [&](const void* fn, int slot, auto launch) -> hipError_t {
+    if (prepare) return slot >= 0 ? allow_lds(fn, &cur[slot], (int)lds) : hipSuccess;
+    launch();
+    return hipSuccess;
+  };
+  switch (l.kernel) {
+    case kKSymSum: return go(nullptr, -1, [&] { k_sym_sum_m<<<nblk, T, 0, s>>>(dps, its, blk); });
+    case kKStacked:
+      switch (l.variant) {
+        case 0: return go(nullptr, -1, [&] { k_stacked_product_m<1><<<nblk, T, 0, s>>>(dps, its, blk); });
+        case 1: return go(nullptr, -1, [&] { k_stacked_product_m<2><<<nblk, T, 0, s>>>(dps, its, blk); });
+        case 2: return go(nullptr, -1, [&] { k_stacked_product_m<4><<<nblk, T, 0, s>>>(dps, its, blk); });
+        case 3: return go(nullptr, -1, [&] { k_stacked_product_m<7><<<nblk, T, 0, s>>>(dps, its, blk); });
+        default: return go(nullptr, -1, [&] { k_stacked_product_m<kSBMax><<<nblk, T, 0, s>>>(dps, its, blk); });
+      }
+    case kKCholSmall:
+      return go((const void*)k_chol_small_m, 0, [&] { k_chol_small_m<<<nblk, T, L, s>>>(dps, its, blk); });
+    case kKCopyChol: return go(nullptr, -1, [&] { k_copy_chol_m<<<nblk, T, 0, s>>>(dps, its, blk); });
+    case kKSetInfo: return go(nullptr, -1, [&] { k_set_info_m<<<nblk, T, 0, s>>>(dps, its, blk); });
+    case kKCholDiag: return go(nullptr, -1, [&] { k_chol_diag_m<<<nblk, T, 0, s>>>(dps, its, blk, l.jb); });
+    case kKCholTrsm: return go(nullptr, -1, [&] { k_chol_trsm_m<<<nblk, T, 0, s>>>(dps, its, blk, l.jb); });
+    case kKCholUpdate: return go(nullptr, -1, [&] { k_chol_update_m<<<nblk, T, 0, s>>>(dps, its, blk, l.jb); });
+    case kKRSolveBlk:
+      return go((const void*)k_reduced_solve_blk_m, 1, [&] { k_reduced_solve_blk_m<<<nblk, T, L, s>>>(dps, its, blk); });
+    case kKRSolve:
+      if (l.variant == 1)
+        return go((const void*)k_reduced_solve_m<true>, 2,
+                  [&] { k_reduced_solve_m<true><<<nblk, T, L, s>>>(dps, its, blk); });
+      return go((const void*)k_reduced_solve_m<false>, 3,
+                [&] { k_reduced_solve_m<false><<<nblk, T, L, s>>>(dps, its, blk); });
+    default:
+      *handled = false;
+      return hipSuccess;
+  }
 }
 
 }  // namespace rkkt

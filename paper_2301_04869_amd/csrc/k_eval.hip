@@ -230,9 +230,13 @@ __device__ inline double w_gather_one(const DP& d, int e, double w, const double
 // share of the gathers, so the gathers of a scenario run on several CUs.
 constexpr int kLvT = 512, kLvSplit = 4;
 
-__global__ __launch_bounds__(kLvT) void k_line_eval_gather(DP d, const double* x, const double* u) {
+// Every kernel of the pass is a body taking the instance (d) and its block
+// index, with two entry points: k_* (one instance, block index from the
+// grid) and k_*_m (several instances: block b is block blk[b].bx of instance
+// blk[b].inst, arguments from that instance's rkkt_iteration).
+__device__ __forceinline__ void line_eval_gather_body(const DP& d, int bx, const double* x, const double* u) {
   extern __shared__ double lv[];
-  const int k = blockIdx.x / kLvSplit, part = blockIdx.x % kLvSplit, tid = threadIdx.x;
+  const int k = bx / kLvSplit, part = bx % kLvSplit, tid = threadIdx.x;
   double* glv = d.LV + (long long)k * d.nl * kLVsize;
   for (int l = tid; l < d.nl; l += kLvT) {
     double* o = lv + (long long)l * kLVsize;
@@ -247,40 +251,40 @@ __global__ __launch_bounds__(kLvT) void k_line_eval_gather(DP d, const double* x
   for (int e = part * kLvT + tid; e < d.n_ev; e += kLvSplit * kLvT) gev[e] = gather_ev_one(d, e, lv);
 }
 
-__global__ void k_line_eval(DP d, const double* x, const double* u) {
-  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void line_eval_body(const DP& d, int bx, const double* x, const double* u) {
+  long long t = (long long)bx * blockDim.x + threadIdx.x;
   if (t >= (long long)d.N * d.nl) return;
   line_eval_one(d, (int)(t / d.nl), (int)(t % d.nl), x, u, d.LV + t * kLVsize);
 }
 
-__global__ void k_gather_ev(DP d) {
-  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void gather_ev_body(const DP& d, int bx) {
+  long long t = (long long)bx * blockDim.x + threadIdx.x;
   if (t >= (long long)d.N * d.n_ev) return;
   int k = (int)(t / d.n_ev), e = (int)(t % d.n_ev);
   d.EV[t] = gather_ev_one(d, e, d.LV + (long long)k * d.nl * kLVsize);
 }
 
-__global__ void k_assemble(DP d, const double* u, double w, double* f, double* gx, double* gu,
-                           double* g, double* h) {
+__device__ __forceinline__ void assemble_body(const DP& d, int bx, const double* u, double w, double* f,
+                                              double* gx, double* gu, double* g, double* h) {
   const int per = 2 * d.nx + d.m + d.nu + 1;
-  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long t = (long long)bx * blockDim.x + threadIdx.x;
   if (t >= (long long)d.N * per) return;
   int k = (int)(t / per), i = (int)(t % per);
   assemble_one(d, k, i, u, w, f, gx, gu, g, h, d.EV + (long long)k * d.n_ev,
                d.LV + (long long)k * d.nl * kLVsize);
 }
 
-__global__ void k_line_hess(DP d, const double* x, const double* u, const double* y,
-                            const double* z, double w) {
-  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void line_hess_body(const DP& d, int bx, const double* x, const double* u,
+                                               const double* y, const double* z, double w) {
+  long long t = (long long)bx * blockDim.x + threadIdx.x;
   if (t >= (long long)d.N * d.nl) return;
   int k = (int)(t / d.nl), l = (int)(t % d.nl);
   line_hess_one(d, k, l, x, u, y, z, w, d.EV + (long long)k * d.n_ev, d.LV + t * kLVsize,
                 d.LH + t * kLHsize);
 }
 
-__global__ void k_w_gather(DP d, double w) {
-  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void w_gather_body(const DP& d, int bx, double w) {
+  long long t = (long long)bx * blockDim.x + threadIdx.x;
   if (t >= (long long)d.N * d.nnz_k) return;
   int k = (int)(t / d.nnz_k), e = (int)(t % d.nnz_k);
   d.W[t] = w_gather_one(d, e, w, d.LH + (long long)k * d.nl * kLHsize,
@@ -300,11 +304,74 @@ __device__ inline double condense_value(const DP& d, int k, int e, double wv, co
   return acc;
 }
 
-__global__ void k_condense_values(DP d, const double* sx, const double* ss, double dw) {
-  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void condense_values_body(const DP& d, int bx, const double* sx, const double* ss,
+                                                     double dw) {
+  long long t = (long long)bx * blockDim.x + threadIdx.x;
   if (t >= (long long)d.N * d.nnz_k) return;
   int k = (int)(t / d.nnz_k), e = (int)(t % d.nnz_k);
   d.K[t] = condense_value(d, k, e, d.W[t], d.EV + (long long)k * d.n_ev + d.off_h, sx, ss, dw);
+}
+
+// ---- entry points: one instance
+__global__ __launch_bounds__(kLvT) void k_line_eval_gather(DP d, const double* x, const double* u) {
+  line_eval_gather_body(d, blockIdx.x, x, u);
+}
+__global__ void k_line_eval(DP d, const double* x, const double* u) { line_eval_body(d, blockIdx.x, x, u); }
+__global__ void k_gather_ev(DP d) { gather_ev_body(d, blockIdx.x); }
+__global__ void k_assemble(DP d, const double* u, double w, double* f, double* gx, double* gu, double* g,
+                           double* h) {
+  assemble_body(d, blockIdx.x, u, w, f, gx, gu, g, h);
+}
+__global__ void k_line_hess(DP d, const double* x, const double* u, const double* y, const double* z,
+                            double w) {
+  line_hess_body(d, blockIdx.x, x, u, y, z, w);
+}
+__global__ void k_w_gather(DP d, double w) { w_gather_body(d, blockIdx.x, w); }
+__global__ void k_condense_values(DP d, const double* sx, const double* ss, double dw) {
+  condense_values_body(d, blockIdx.x, sx, ss, dw);
+}
+
+// ---- entry points: several instances
+#define RKKT_MULTI_PROLOGUE                          \
+  const MultiBlk mb = blk[blockIdx.x];               \
+  const DP& d = dps[mb.inst];                        \
+  const rkkt_iteration& it = its[mb.inst];           \
+  (void)it;
+__global__ __launch_bounds__(kLvT) void k_line_eval_gather_m(const DP* __restrict__ dps,
+                                                             const rkkt_iteration* __restrict__ its,
+                                                             const MultiBlk* __restrict__ blk) {
+  RKKT_MULTI_PROLOGUE
+  line_eval_gather_body(d, mb.bx, it.x, it.u);
+}
+__global__ void k_line_eval_m(const DP* __restrict__ dps, const rkkt_iteration* __restrict__ its,
+                              const MultiBlk* __restrict__ blk) {
+  RKKT_MULTI_PROLOGUE
+  line_eval_body(d, mb.bx, it.x, it.u);
+}
+__global__ void k_gather_ev_m(const DP* __restrict__ dps, const rkkt_iteration* __restrict__ its,
+                              const MultiBlk* __restrict__ blk) {
+  RKKT_MULTI_PROLOGUE
+  gather_ev_body(d, mb.bx);
+}
+__global__ void k_assemble_m(const DP* __restrict__ dps, const rkkt_iteration* __restrict__ its,
+                             const MultiBlk* __restrict__ blk) {
+  RKKT_MULTI_PROLOGUE
+  assemble_body(d, mb.bx, it.u, it.obj_weight, it.f, it.grad_x, it.grad_u, it.g, it.h);
+}
+__global__ void k_line_hess_m(const DP* __restrict__ dps, const rkkt_iteration* __restrict__ its,
+                              const MultiBlk* __restrict__ blk) {
+  RKKT_MULTI_PROLOGUE
+  line_hess_body(d, mb.bx, it.x, it.u, it.y, it.z, it.obj_weight);
+}
+__global__ void k_w_gather_m(const DP* __restrict__ dps, const rkkt_iteration* __restrict__ its,
+                             const MultiBlk* __restrict__ blk) {
+  RKKT_MULTI_PROLOGUE
+  w_gather_body(d, mb.bx, it.obj_weight);
+}
+__global__ void k_condense_values_m(const DP* __restrict__ dps, const rkkt_iteration* __restrict__ its,
+                                    const MultiBlk* __restrict__ blk) {
+  RKKT_MULTI_PROLOGUE
+  condense_values_body(d, mb.bx, it.sigma_x, it.sigma_s, it.delta_w);
 }
 
 }  // namespace
@@ -371,6 +438,48 @@ void launch_condense_values(const DP& d, const double* sx, const double* ss, dou
                             hipStream_t s) {
   long long nk = (long long)d.N * d.nnz_k;
   k_condense_values<<<grid_for(nk), kBlock, 0, s>>>(d, sx, ss, dw);
+}
+
+// the launches of launch_evaluate_values, launch_evaluate_rest and
+// launch_condense_values, in that order
+void launches_eval(const DP& d, std::vector<Launch>& out) {
+  auto add = [&](int key, int kernel, long long grid, int threads, long long lds) {
+    out.push_back(Launch{key, kernel, 0, (int)grid, 1, threads, 0, lds});
+  };
+  if (line_fused(d)) {
+    add(kStEvalValues * 4096, kKLineEvalGather, (long long)d.N * kLvSplit, kLvT, line_lds_bytes(d));
+  } else {
+    add(kStEvalValues * 4096, kKLineEval, grid_for((long long)d.N * d.nl), kBlock, 0);
+    add(kStEvalValues * 4096 + 1, kKGatherEv, grid_for((long long)d.N * d.n_ev), kBlock, 0);
+  }
+  add(kStEvalRest * 4096, kKAssemble, grid_for((long long)d.N * (2 * d.nx + d.m + d.nu + 1)), kBlock, 0);
+  add(kStEvalRest * 4096 + 1, kKLineHess, grid_for((long long)d.N * d.nl), kBlock, 0);
+  add(kStEvalRest * 4096 + 2, kKWGather, grid_for((long long)d.N * d.nnz_k), kBlock, 0);
+  add(kStCondense * 4096, kKCondense, grid_for((long long)d.N * d.nnz_k), kBlock, 0);
+}
+
+hipError_t multi_eval(const Launch& l, unsigned nblk, long long lds, const DP* dps, const rkkt_iteration* its,
+                      const MultiBlk* blk, hipStream_t s, bool prepare, bool* handled) {
+  *handled = true;
+  if (prepare) {
+    static int cur = 0;
+    if (l.kernel != kKLineEvalGather || lds <= cur) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute((const void*)k_line_eval_gather_m,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess) cur = (int)lds;
+    return e;
+  }
+  switch (l.kernel) {
+    case kKLineEvalGather: k_line_eval_gather_m<<<nblk, kLvT, (size_t)lds, s>>>(dps, its, blk); break;
+    case kKLineEval: k_line_eval_m<<<nblk, kBlock, 0, s>>>(dps, its, blk); break;
+    case kKGatherEv: k_gather_ev_m<<<nblk, kBlock, 0, s>>>(dps, its, blk); break;
+    case kKAssemble: k_assemble_m<<<nblk, kBlock, 0, s>>>(dps, its, blk); break;
+    case kKLineHess: k_line_hess_m<<<nblk, kBlock, 0, s>>>(dps, its, blk); break;
+    case kKWGather: k_w_gather_m<<<nblk, kBlock, 0, s>>>(dps, its, blk); break;
+    case kKCondense: k_condense_values_m<<<nblk, kBlock, 0, s>>>(dps, its, blk); break;
+    default: *handled = false;
+  }
+  return hipSuccess;
 }
 
 }  // namespace rkkt

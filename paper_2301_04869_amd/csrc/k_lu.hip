@@ -469,11 +469,11 @@ __device__ __forceinline__ void chain_factor(const DP& d, double* lu, double* in
 // LDS mode: spw scenarios per workgroup, one wavefront each, with the shared
 // schedule staged once; global mode: one workgroup of kRT threads per scenario.
 template <bool kLDS, int kT, bool kUpdLds>
-__global__ __launch_bounds__(kT) void k_refactor(DP d) {
+__device__ __forceinline__ void refactor_body(const DP& d, int bx_, int by_, int gx_) {
   constexpr int G = kLDS ? kGroupLds : kT;
   const int tid = threadIdx.x;
   const int gi = kLDS ? tid / G : 0, gl = kLDS ? tid % G : tid;
-  const int k = blockIdx.x * (kLDS ? d.spw : 1) + gi;
+  const int k = bx_ * (kLDS ? d.spw : 1) + gi;
   const bool live = gi < (kLDS ? d.spw : 1) && k < d.N;
   const int nx = d.nx, nf = d.nnz_f;
   extern __shared__ double smem[];
@@ -573,6 +573,11 @@ __global__ __launch_bounds__(kT) void k_refactor(DP d) {
   }
 }
 
+template <bool kLDS, int kT, bool kUpdLds>
+__global__ __launch_bounds__(kT) void k_refactor(DP d) {
+  refactor_body<kLDS, kT, kUpdLds>(d, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x);
+}
+
 // ---------------------------------------------------------- local reduction
 // One workgroup per (tile of W columns of V = I, scenario): slot = thread / W
 // (S = kRT / W slots), column = thread % W.
@@ -582,8 +587,8 @@ __global__ __launch_bounds__(kT) void k_refactor(DP d) {
 //   step 3 (product, kVar 2): Z = [T; I] and K Z written to the stacked panels;
 //          the stacked product Z^T (K Z) over all scenarios closes the reduction
 template <bool kLDS, int kVar>
-__global__ __launch_bounds__(kRT) void k_reduce(DP d) {
-  const int k = blockIdx.y, tile = blockIdx.x;
+__device__ __forceinline__ void reduce_body(const DP& d, int bx_, int by_, int gx_) {
+  const int k = by_, tile = bx_;
   const int W = d.col_tile, c0 = tile * W, nx = d.nx, nu = d.nu, nz = d.nz;
   const int S = kRT / W;
   const int tid = threadIdx.x, slot = tid / W, c = tid - slot * W;
@@ -636,7 +641,7 @@ __global__ __launch_bounds__(kRT) void k_reduce(DP d) {
       T = zk + c0;  // solved in place in the stacked panel
       ldT = d.nu_pad;
     } else {
-      T = d.panel + ((long long)k * gridDim.x + tile) * 2LL * nx * W;
+      T = d.panel + ((long long)k * gx_ + tile) * 2LL * nx * W;
       Lx = T + (long long)nx * W;
     }
     uptr = d.ru_ptr; dptr = d.rd_ptr; uent = d.ru_ent; dent = d.rd_ent;
@@ -713,6 +718,11 @@ __global__ __launch_bounds__(kRT) void k_reduce(DP d) {
       for (int j = guc_ptr[ru]; j < j1; ++j) acc = fma(-gu_val(j), Lx[(long long)guc_row[j] * W + c], acc);
       out[(long long)ru * nu + col] = acc;
     }
+}
+
+template <bool kLDS, int kVar>
+__global__ __launch_bounds__(kRT) void k_reduce(DP d) {
+  reduce_body<kLDS, kVar>(d, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x);
 }
 
 // ------------------------------------- local reduction with 64-column tiles
@@ -862,8 +872,8 @@ __device__ __forceinline__ void sweep64_any(const int* __restrict__ ptr, const i
 }
 
 template <bool kLDS, int kVar>
-__global__ __launch_bounds__(kRT) void k_reduce64(DP d) {
-  const int k = blockIdx.y, tile = blockIdx.x;
+__device__ __forceinline__ void reduce64_body(const DP& d, int bx_, int by_, int gx_) {
+  const int k = by_, tile = bx_;
   const int c0 = tile * kW64, nx = d.nx, nu = d.nu, nz = d.nz;
   const int tid = threadIdx.x, c = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -912,7 +922,7 @@ __global__ __launch_bounds__(kRT) void k_reduce64(DP d) {
       T = zk + c0;  // solved in place in the stacked panel
       ldT = d.nu_pad;
     } else {
-      T = d.panel + ((long long)k * gridDim.x + tile) * 2LL * nx * kW64;
+      T = d.panel + ((long long)k * gx_ + tile) * 2LL * nx * kW64;
       Lx = T + (long long)nx * kW64;
     }
   }
@@ -1115,6 +1125,11 @@ __global__ __launch_bounds__(kRT) void k_reduce64(DP d) {
     }
 }
 
+template <bool kLDS, int kVar>
+__global__ __launch_bounds__(kRT) void k_reduce64(DP d) {
+  reduce64_body<kLDS, kVar>(d, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x);
+}
+
 // ------------------------------------------------ single-column solves (step)
 // LDS mode: one workgroup of kGT threads per scenario stages everything the
 // scenario's step reads (factor and 1/u_ii, K, H and G_u values, the
@@ -1265,11 +1280,11 @@ __device__ __forceinline__ void in_sweep_group(F f) {
 //   a = G_x^-T (rhat1 - K_xx q),
 //   rpart = -H_u^T (Sigma_s r4 - r2) + G_u^T a + K_ux q
 template <bool kLDS, int kT>
-__global__ __launch_bounds__(kT) void k_step_rhs(DP d, const double* r1x, const double* r2,
+__device__ __forceinline__ void step_rhs_body(const DP& d, int bx_, int by_, int gx_, const double* r1x, const double* r2,
                                                  const double* r3, const double* r4,
                                                  const double* ss) {
   extern __shared__ double smem[];
-  const int k = blockIdx.x, tid = threadIdx.x;
+  const int k = bx_, tid = threadIdx.x;
   const StepView w = step_view<kLDS>(d, k, smem, r1x, r3, r2, r4, ss, nullptr);
   const int nx = d.nx, nu = d.nu;
   double* rh1 = w.v2;  // rhat1; the global copy is kept for the recovery
@@ -1307,16 +1322,23 @@ __global__ __launch_bounds__(kT) void k_step_rhs(DP d, const double* r1x, const 
   }
 }
 
+template <bool kLDS, int kT>
+__global__ __launch_bounds__(kT) void k_step_rhs(DP d, const double* r1x, const double* r2,
+                                                 const double* r3, const double* r4,
+                                                 const double* ss) {
+  step_rhs_body<kLDS, kT>(d, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, r1x, r2, r3, r4, ss);
+}
+
 // Recovery of one scenario (propositions "Reduction" and "Condensed KKT system"):
 //   p_x = -G_x^-1 (r3 + G_u p_u), p_y = -G_x^-T (rhat1 + K_xx p_x + K_xu p_u),
 //   p_s = -(r4 + H p_d), p_z = Sigma_s (H p_d + r4) - r2
 template <bool kLDS, int kT>
-__global__ __launch_bounds__(kT) void k_step_recover(DP d, const double* r2, const double* r3,
+__device__ __forceinline__ void step_recover_body(const DP& d, int bx_, int by_, int gx_, const double* r2, const double* r3,
                                                      const double* r4, const double* ss,
                                                      const double* pu, double* px, double* ps,
                                                      double* py, double* pz) {
   extern __shared__ double smem[];
-  const int k = blockIdx.x, tid = threadIdx.x;
+  const int k = bx_, tid = threadIdx.x;
   const StepView w = step_view<kLDS>(d, k, smem, d.rhat1, r3, r2, r4, ss, pu);
   const int nx = d.nx;
   double* xv = w.v0;
@@ -1352,6 +1374,14 @@ __global__ __launch_bounds__(kT) void k_step_recover(DP d, const double* r2, con
     ps[(long long)k * d.m + r] = -(w.r4[r] + hp);
     pz[(long long)k * d.m + r] = w.ss[r] * (hp + w.r4[r]) - w.r2[r];
   }
+}
+
+template <bool kLDS, int kT>
+__global__ __launch_bounds__(kT) void k_step_recover(DP d, const double* r2, const double* r3,
+                                                     const double* r4, const double* ss,
+                                                     const double* pu, double* px, double* ps,
+                                                     double* py, double* pz) {
+  step_recover_body<kLDS, kT>(d, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, r2, r3, r4, ss, pu, px, ps, py, pz);
 }
 
 // ------------------------------------- step of the stacked variant
@@ -1419,11 +1449,11 @@ __device__ __forceinline__ void dense_tt_times(const DP& d, const double* __rest
 }
 
 template <int kT>
-__global__ __launch_bounds__(kT) void k_step_rhs2(DP d, const double* r1x, const double* r2,
+__device__ __forceinline__ void step_rhs2_body(const DP& d, int bx_, int by_, int gx_, const double* r1x, const double* r2,
                                                   const double* r3, const double* r4,
                                                   const double* ss) {
   extern __shared__ double smem[];
-  const int k = blockIdx.x, tid = threadIdx.x;
+  const int k = bx_, tid = threadIdx.x;
   const int nx = d.nx, nu = d.nu, m = d.m, nf = d.nnz_f;
   double* lu = smem;
   double* q = lu + nf + nx;
@@ -1486,17 +1516,24 @@ __global__ __launch_bounds__(kT) void k_step_rhs2(DP d, const double* r1x, const
   }
 }
 
+template <int kT>
+__global__ __launch_bounds__(kT) void k_step_rhs2(DP d, const double* r1x, const double* r2,
+                                                  const double* r3, const double* r4,
+                                                  const double* ss) {
+  step_rhs2_body<kT>(d, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, r1x, r2, r3, r4, ss);
+}
+
 constexpr int kPxRows = 4;     // rows of T per 16-lane group in flight
 constexpr int kPxChunks = 8;   // 16-column chunks of a row per pass
 constexpr int kKxPre = 16;     // entries of a K_x row loaded ahead
 
 template <int kT>
-__global__ __launch_bounds__(kT) void k_step_recover2(DP d, const double* r2, const double* r3,
+__device__ __forceinline__ void step_recover2_body(const DP& d, int bx_, int by_, int gx_, const double* r2, const double* r3,
                                                       const double* r4, const double* ss,
                                                       const double* pu, double* px, double* ps,
                                                       double* py, double* pz) {
   extern __shared__ double smem[];
-  const int k = blockIdx.x, tid = threadIdx.x;
+  const int k = bx_, tid = threadIdx.x;
   const int nx = d.nx, nu = d.nu, m = d.m, nf = d.nnz_f;
   double* lu = smem;
   double* xv = lu + nf + nx;
@@ -1620,6 +1657,14 @@ __global__ __launch_bounds__(kT) void k_step_recover2(DP d, const double* r2, co
   for (int i = tid; i < nx; i += kT) py[(long long)k * nx + d.perm[i]] = yv[i];
 }
 
+template <int kT>
+__global__ __launch_bounds__(kT) void k_step_recover2(DP d, const double* r2, const double* r3,
+                                                      const double* r4, const double* ss,
+                                                      const double* pu, double* px, double* ps,
+                                                      double* py, double* pz) {
+  step_recover2_body<kT>(d, (int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, r2, r3, r4, ss, pu, px, ps, py, pz);
+}
+
 // rows nx .. nz of every scenario block of the stacked Z are the identity
 __global__ void k_identity_rows(DP d) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1636,6 +1681,54 @@ hipError_t allow_lds(const void* fn, int* cur, long long need) {
 }
 
 int ntiles(const DP& d) { return (d.nu + d.col_tile - 1) / d.col_tile; }
+
+// ---- entry points: several instances (block b is block (blk[b].bx,
+// blk[b].by) of instance blk[b].inst's own grid, blk[b].gx wide)
+#define RKKT_MULTI_ARGS \
+  const DP* __restrict__ dps, const rkkt_iteration* __restrict__ its, const MultiBlk* __restrict__ blk
+#define RKKT_MULTI_PROLOGUE                          \
+  const MultiBlk mb = blk[blockIdx.x];               \
+  const DP& d = dps[mb.inst];                        \
+  const rkkt_iteration& it = its[mb.inst];           \
+  (void)it;
+
+template <bool kLDS, int kT, bool kUpdLds>
+__global__ __launch_bounds__(kT) void k_refactor_m(RKKT_MULTI_ARGS) {
+  RKKT_MULTI_PROLOGUE
+  refactor_body<kLDS, kT, kUpdLds>(d, mb.bx, mb.by, mb.gx);
+}
+template <bool kLDS, int kVar>
+__global__ __launch_bounds__(kRT) void k_reduce_m(RKKT_MULTI_ARGS) {
+  RKKT_MULTI_PROLOGUE
+  reduce_body<kLDS, kVar>(d, mb.bx, mb.by, mb.gx);
+}
+template <bool kLDS, int kVar>
+__global__ __launch_bounds__(kRT) void k_reduce64_m(RKKT_MULTI_ARGS) {
+  RKKT_MULTI_PROLOGUE
+  reduce64_body<kLDS, kVar>(d, mb.bx, mb.by, mb.gx);
+}
+template <bool kLDS, int kT>
+__global__ __launch_bounds__(kT) void k_step_rhs_m(RKKT_MULTI_ARGS) {
+  RKKT_MULTI_PROLOGUE
+  step_rhs_body<kLDS, kT>(d, mb.bx, mb.by, mb.gx, it.r1x, it.r2, it.r3, it.r4, it.sigma_s);
+}
+template <int kT>
+__global__ __launch_bounds__(kT) void k_step_rhs2_m(RKKT_MULTI_ARGS) {
+  RKKT_MULTI_PROLOGUE
+  step_rhs2_body<kT>(d, mb.bx, mb.by, mb.gx, it.r1x, it.r2, it.r3, it.r4, it.sigma_s);
+}
+template <bool kLDS, int kT>
+__global__ __launch_bounds__(kT) void k_step_recover_m(RKKT_MULTI_ARGS) {
+  RKKT_MULTI_PROLOGUE
+  step_recover_body<kLDS, kT>(d, mb.bx, mb.by, mb.gx, it.r2, it.r3, it.r4, it.sigma_s, it.pu, it.px, it.ps,
+                              it.py, it.pz);
+}
+template <int kT>
+__global__ __launch_bounds__(kT) void k_step_recover2_m(RKKT_MULTI_ARGS) {
+  RKKT_MULTI_PROLOGUE
+  step_recover2_body<kT>(d, mb.bx, mb.by, mb.gx, it.r2, it.r3, it.r4, it.sigma_s, it.pu, it.px, it.ps, it.py,
+                         it.pz);
+}
 
 }  // namespace
 
@@ -1731,6 +1824,95 @@ void launch_step_recover(const DP& d, const double* r2, const double* r3, const 
                                                                            ps, py, pz);
   else
     k_step_recover<false, kRT><<<d.N, kRT, 0, s>>>(d, r2, r3, r4, ss, pu, px, ps, py, pz);
+}
+
+}  // namespace rkkt
+
+namespace rkkt {
+
+// the launches of launch_refactor, launch_reduce, launch_step_rhs and
+// launch_step_recover.  Variants: refactor 0 LDS with staged updates, 1 LDS,
+// 2 global; reduce (64-column or narrow tiles) 2 (lds ? 1 : 0) + (variant
+// == 2); steps 0 one-solve (stacked variant), 1 LDS, 2 global.
+void launches_lu(const DP& d, std::vector<Launch>& out) {
+  {
+    const LdsSizes z = sizes_of(d);
+    if (d.lds_grp)
+      out.push_back(Launch{kStRefactor * 4096, kKRefactor, d.upd_lds ? 0 : 1, (d.N + d.spw - 1) / d.spw, 1,
+                           kGroupLds * d.spw, 0, refactor_lds_bytes(z)});
+    else
+      out.push_back(Launch{kStRefactor * 4096, kKRefactor, 2, d.N, 1, kRT, 0, 0});
+    const long long lds = d.lds_red ? reduce_lds_bytes(z) : 8LL * d.chain_t * d.chain_t;
+    out.push_back(Launch{kStReduce * 4096, d.col_tile == kW64 ? kKReduce64 : kKReduce,
+                         2 * (d.lds_red ? 1 : 0) + (d.variant == 2 ? 1 : 0), ntiles(d), d.N, kRT, 0, lds});
+    if (step2(d)) {
+      out.push_back(Launch{kStStepRhs * 4096, kKStepRhs2, 0, d.N, 1, kGT, 0, step2_lds_bytes(z, kGT)});
+      out.push_back(Launch{kStRecover * 4096, kKStepRec2, 0, d.N, 1, kGT, 0, step2_lds_bytes(z, kGT)});
+    } else if (d.lds_stp) {
+      out.push_back(Launch{kStStepRhs * 4096, kKStepRhs, 1, d.N, 1, kGT, 0, step_lds_bytes(z)});
+      out.push_back(Launch{kStRecover * 4096, kKStepRec, 1, d.N, 1, kGT, 0, step_lds_bytes(z)});
+    } else {
+      out.push_back(Launch{kStStepRhs * 4096, kKStepRhs, 2, d.N, 1, kRT, 0, 0});
+      out.push_back(Launch{kStRecover * 4096, kKStepRec, 2, d.N, 1, kRT, 0, 0});
+    }
+  }
+}
+
+hipError_t multi_lu(const Launch& l, unsigned nblk, long long lds, const DP* dps, const rkkt_iteration* its,
+                    const MultiBlk* blk, hipStream_t s, bool prepare, bool* handled) {
+  *handled = true;
+  const size_t L = (size_t)lds;
+  const unsigned T = (unsigned)l.threads;
+  // one dynamic-LDS limit per multi-instance kernel, raised as needed
+  static int cur[32] = {};
+  auto go = [&](const void* fn, int slot, auto launch) -> hipError_t {
+    if (prepare) return allow_lds(fn, &cur[slot], lds);
+    launch();
+    return hipSuccess;
+  };
+  switch (l.kernel) {
+    case kKRefactor:
+      if (l.variant == 0)
+        return go((const void*)k_refactor_m<true, kGT, true>, 0,
+                  [&] { k_refactor_m<true, kGT, true><<<nblk, T, L, s>>>(dps, its, blk); });
+      if (l.variant == 1)
+        return go((const void*)k_refactor_m<true, kGT, false>, 1,
+                  [&] { k_refactor_m<true, kGT, false><<<nblk, T, L, s>>>(dps, its, blk); });
+      return go((const void*)k_refactor_m<false, kRT, false>, 2,
+                [&] { k_refactor_m<false, kRT, false><<<nblk, T, L, s>>>(dps, its, blk); });
+    case kKReduce64:
+      switch (l.variant) {
+        case 0: return go((const void*)k_reduce64_m<false, 1>, 3, [&] { k_reduce64_m<false, 1><<<nblk, T, L, s>>>(dps, its, blk); });
+        case 1: return go((const void*)k_reduce64_m<false, 2>, 4, [&] { k_reduce64_m<false, 2><<<nblk, T, L, s>>>(dps, its, blk); });
+        case 2: return go((const void*)k_reduce64_m<true, 1>, 5, [&] { k_reduce64_m<true, 1><<<nblk, T, L, s>>>(dps, its, blk); });
+        default: return go((const void*)k_reduce64_m<true, 2>, 6, [&] { k_reduce64_m<true, 2><<<nblk, T, L, s>>>(dps, its, blk); });
+      }
+    case kKReduce:
+      switch (l.variant) {
+        case 0: return go((const void*)k_reduce_m<false, 1>, 7, [&] { k_reduce_m<false, 1><<<nblk, T, L, s>>>(dps, its, blk); });
+        case 1: return go((const void*)k_reduce_m<false, 2>, 8, [&] { k_reduce_m<false, 2><<<nblk, T, L, s>>>(dps, its, blk); });
+        case 2: return go((const void*)k_reduce_m<true, 1>, 9, [&] { k_reduce_m<true, 1><<<nblk, T, L, s>>>(dps, its, blk); });
+        default: return go((const void*)k_reduce_m<true, 2>, 10, [&] { k_reduce_m<true, 2><<<nblk, T, L, s>>>(dps, its, blk); });
+      }
+    case kKStepRhs2:
+      return go((const void*)k_step_rhs2_m<kGT>, 11, [&] { k_step_rhs2_m<kGT><<<nblk, T, L, s>>>(dps, its, blk); });
+    case kKStepRec2:
+      return go((const void*)k_step_recover2_m<kGT>, 12,
+                [&] { k_step_recover2_m<kGT><<<nblk, T, L, s>>>(dps, its, blk); });
+    case kKStepRhs:
+      if (l.variant == 1)
+        return go((const void*)k_step_rhs_m<true, kGT>, 13, [&] { k_step_rhs_m<true, kGT><<<nblk, T, L, s>>>(dps, its, blk); });
+      return go((const void*)k_step_rhs_m<false, kRT>, 14, [&] { k_step_rhs_m<false, kRT><<<nblk, T, L, s>>>(dps, its, blk); });
+    case kKStepRec:
+      if (l.variant == 1)
+        return go((const void*)k_step_recover_m<true, kGT>, 15,
+                  [&] { k_step_recover_m<true, kGT><<<nblk, T, L, s>>>(dps, its, blk); });
+      return go((const void*)k_step_recover_m<false, kRT>, 16,
+                [&] { k_step_recover_m<false, kRT><<<nblk, T, L, s>>>(dps, its, blk); });
+    default:
+      *handled = false;
+      return hipSuccess;
+  }
 }
 
 }  // namespace rkkt

@@ -38,8 +38,8 @@ WORKLOADS = {
     "c4": "9241-bus / 16049-line / 1445-generator synthetic grid (the sizes of the paper's "
           "case9241pegase), N = 16 load scenarios (sigma 0.1), n_x = 17036, n_u = 2889; full hot path per step",
     "c2": "64 independent single-scenario grids, n_bus log-uniform in [300, 2000], 1.5 n_bus lines, "
-          "0.15 n_bus generators; autotuned column tiles; all 64 passes in one graph launch vs 64 "
-          "sequential plain launches",
+          "0.15 n_bus generators; launch shapes autotuned per instance; one multi-instance pass (one launch "
+          "per kernel configuration, captured as one graph) vs the 64 passes one after the other",
 }
 
 
@@ -99,10 +99,102 @@ def warm_main(args):
     print(json.dumps(out), flush=True)
 
 
-def batch_main(args):
-    print("bench.py --config c2: the graph batch of independent instances (rkkt_batch_create) is "
-          "switched off; its capture ended in a host fault whose cause is not shown", file=sys.stderr)
-    sys.exit(3)
+def multi_main(args):
+    """64 independent single-scenario grids of uneven size (n_bus log-uniform
+    in [300, 2000]) in one multi-instance handle: every kernel of the pass
+    launched once per configuration group for all instances (eager and as one
+    captured graph), against the 64 instances' own passes run one after the
+    other.  Launch shapes from the autotuner, per instance."""
+    import torch
+    import synthgrid as sg
+    from synthgrid.iterates import random_iterate
+    import paper_2301_04869_amd as R
+    insts = sg.batch_instances(64, seed=2000)
+    zf = lambda *sh: torch.zeros(*sh, dtype=torch.float64, device="cuda")  # noqa: E731
+    handles, arglist, shapes = [], [], []
+    t0 = time.time()
+    for j, inst in enumerate(insts):
+        pd, qd = inst.scen.pd.T, inst.scen.qd.T
+        best = R.rkkt_autotune(inst.net, pd, qd, reps=2)[0] if args.autotune else {}
+        p = R.rkkt_create(inst.net, pd, qd, **best)
+        d = p.dims
+        nx, nu, m = d["n_x"], d["n_u"], d["m"]
+        it = random_iterate(inst.net, 1, 3000 + j)
+        t = {k: torch.tensor(np.ascontiguousarray(v), dtype=torch.float64, device="cuda")
+             for k, v in it.items() if k != "obj_weight"}
+        a = dict(x=t["x"], u=t["u"], y=t["y"], z=t["z"], obj_weight=it["obj_weight"], f=zf(1), grad_x=zf(1, nx),
+                 grad_u=zf(1, nu), g=zf(1, nx), h=zf(1, m), sigma_x=t["sigma_x"], sigma_u=t["sigma_u"],
+                 sigma_s=t["sigma_s"], khat=zf(nu, nu), chol=zf(nu, nu),
+                 info=torch.zeros(1, dtype=torch.int32, device="cuda"), r1x=t["r1x"], r1u=t["r1u"],
+                 r2=t["r2"], r3=t["r3"], r4=t["r4"], px=zf(1, nx), pu=zf(nu), ps=zf(1, m), py=zf(1, nx),
+                 pz=zf(1, m))
+        R.rkkt_evaluate(p, a["x"], a["u"], a["y"], a["z"], a["obj_weight"], a["f"], a["grad_x"], a["grad_u"],
+                        a["g"], a["h"])
+        a["delta_w"] = find_delta_w(R, torch, p, t, a["khat"], a["chol"], a["info"])
+        handles.append(p)
+        arglist.append(a)
+        shapes.append({"n_bus": inst.net.n_bus, "n_x": nx, "n_u": nu, "variant": d["variant"],
+                       "col_tile": d["col_tile"], "lds_reduce": d["lds_reduce"], "sweep_form": d["sweep_form"],
+                       "scen_per_group": d["scen_per_group"], "chain_rows": d["chain_rows"]})
+        if (j + 1) % 8 == 0:
+            progress(f"{j + 1} of 64 instances set up ({time.time() - t0:.0f} s)")
+    setup_s = time.time() - t0
+    stream = torch.cuda.current_stream()
+    # reference: the instances' own passes, one after the other
+    for p, a in zip(handles, arglist):
+        R.rkkt_iterate(p, a, stream)
+    torch.cuda.synchronize()
+    ref = [(a["khat"].clone(), a["pu"].clone(), a["px"].clone()) for a in arglist]
+    mh = R.Multi(handles, arglist)
+    for a in arglist:
+        for k in ("khat", "pu", "px"):
+            a[k].fill_(float("nan"))
+    mh.iterate(stream)
+    torch.cuda.synchronize()
+    same = all(torch.equal(a["khat"], r[0]) and torch.equal(a["pu"], r[1]) and torch.equal(a["px"], r[2])
+               for a, r in zip(arglist, ref))
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, k):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(k):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    def sequential():
+        for p, a in zip(handles, arglist):
+            R.rkkt_iterate(p, a, stream)
+
+    seq_ms = timed(sequential, max(3, args.steps // 4))
+    progress(f"64 sequential passes: {seq_ms:.3f} ms")
+    eager_ms = timed(lambda: mh.iterate(stream), args.steps)
+    progress(f"multi-instance pass, eager: {eager_ms:.3f} ms")
+    mh.capture()
+    graph_ms = timed(lambda: mh.launch(stream), args.steps)
+    progress(f"multi-instance pass, graph: {graph_ms:.3f} ms")
+    torch.cuda.synchronize()
+    same = same and all(torch.equal(a["khat"], r[0]) and torch.equal(a["pu"], r[1]) for a, r in zip(arglist, ref))
+    ms = min(eager_ms, graph_ms)
+    out = {"metric": "instance-IPM-iterations/s, 64 independent instances of uneven size in one "
+                     "multi-instance pass vs the 64 passes one after the other",
+           "value": 64 / (ms * 1e-3), "unit": "instance-IPM-iterations/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": WORKLOADS["c2"], "instances": len(shapes), "autotuned": bool(args.autotune),
+                      "n_bus_min": min(x["n_bus"] for x in shapes), "n_bus_max": max(x["n_bus"] for x in shapes)},
+           "graph_ms_per_step": graph_ms, "eager_ms_per_step": eager_ms,
+           "launches_per_pass": mh.n_launches,
+           "sequential": {"ms_per_iteration": seq_ms, "value": 64 / (seq_ms * 1e-3),
+                          "what": "each instance's own rkkt_iterate pass, one after the other"},
+           "speedup_vs_sequential": seq_ms / ms, "outputs_equal_to_sequential": bool(same),
+           "setup_seconds": setup_s, "shapes": shapes}
+    print(json.dumps(out), flush=True)
 
 
 def progress(msg):
@@ -319,6 +411,8 @@ def main():
                     help="reduction: 1 adjoint solves, 2 stacked product, 0 automatic")
     ap.add_argument("--sweep-form", type=int, default=0, choices=(0, 1, 2),
                     help="reduction solve schedules: 1 push, 2 pull, 0 automatic")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="c2: automatic launch shapes instead of the autotuner's")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--seed", type=int, default=2024)
@@ -351,7 +445,7 @@ def main():
 
     R.lib()
     if args.config == "c2":
-        batch_main(args)
+        multi_main(args)
         return
     if args.config == "warm":
         warm_main(args)

@@ -436,12 +436,13 @@ typedef struct rkkt_batch rkkt_batch;
  * multipliers 0, all IPM diagonals and residuals 1, delta_w = 1) and times
  * `reps` calls with HIP events, in two stages: (1) every reduction variant
  * (1 and 2; 2 only while its stacked panels stay under 4 GiB) with the
- * automatic column tile and with 8, 16, 32, 64 up to n_u, each in the LDS or
- * global layout it implies, timed on condense; (2) the level-schedule
- * grouping for the winner of (1): scen_per_group 0, 1, 2, 4 x chain_rows 0,
- * -1, timed on whole rkkt_iterate passes.  Writes the fastest options (device
- * copied from opt; col_tile and variant as resolved, scen_per_group and
- * chain_rows as requested) into *best and its mean pass time in ms into
+ * automatic column tile and with 8, 16, 32, 64 up to n_u, each with the
+ * automatic, push and pull forms of the reduction's solve schedules (and the
+ * LDS or device-memory layout each implies), timed on condense; (2) the
+ * level-schedule grouping for the winner of (1): scen_per_group 0, 1, 2, 4 x
+ * chain_rows 0, -1, timed on whole rkkt_iterate passes.  Writes the fastest
+ * options (device copied from opt; col_tile, variant and sweep_form as
+ * resolved, scen_per_group and chain_rows as requested) into *best and its mean pass time in ms into
  * *best_ms; allocates and frees device memory and synchronises.
  */
 int rkkt_autotune(const rkkt_network* net, int n_scen, const double* pd, const double* qd,

@@ -325,7 +325,7 @@ def rkkt_autotune(net, pd, qd, reps=5, device=0):
                                qd.ctypes.data_as(c_dbl_p), ctypes.byref(Options(0, device, 0)),
                                int(reps), ctypes.byref(best), ctypes.byref(ms)))
     return ({"col_tile": best.col_tile, "variant": best.variant, "scen_per_group": best.scen_per_group,
-             "chain_rows": best.chain_rows}, ms.value)
+             "chain_rows": best.chain_rows, "sweep_form": best.sweep_form}, ms.value)
 
 
 def rkkt_dims_get(p):

@@ -824,7 +824,8 @@ int rkkt_multi_launch(rkkt_multi* m, hipStream_t stream) {
 int rkkt_multi_launches(const rkkt_multi* m) { return m ? (int)m->groups.size() : 0; }
 
 // Launch-shape autotuner.  Stage 1 times `reps` condense calls (the
-// reduction dominates them) for every reduction variant x column tile; stage
+// reduction dominates them) for every reduction variant x column tile x
+// schedule form of the reduction's solves (push / pull); stage
 // 2 keeps the winner's variant and tile and times `reps` whole passes
 // (rkkt_iterate) for every level-schedule grouping: scenarios per
 // refactorisation / step workgroup (automatic, 1, 2, 4) x chain of
@@ -845,12 +846,17 @@ int rkkt_autotune(const rkkt_network* net, int n_scen, const double* pd, const d
     if (v == 2 && stacked_bytes > 4.0 * (1ull << 30)) continue;
     for (int w : {0, 8, 16, 32, 64}) {
       if (w > nu) continue;
-      rkkt_options o = base;
-      o.variant = v;
-      o.col_tile = w;
-      o.scen_per_group = 0;
-      o.chain_rows = 0;
-      stage1.push_back(o);
+      // schedule form: automatic, then each explicit form (a shape the
+      // automatic choice already produced is skipped as seen)
+      for (int form : {0, 1, 2}) {
+        rkkt_options o = base;
+        o.variant = v;
+        o.col_tile = w;
+        o.scen_per_group = 0;
+        o.chain_rows = 0;
+        o.sweep_form = form;
+        stage1.push_back(o);
+      }
     }
   }
   // fixed interior point (host), copied once; residuals all ones
@@ -860,12 +866,29 @@ int rkkt_autotune(const rkkt_network* net, int n_scen, const double* pd, const d
     for (int i = 0; i < nx; ++i) hx[(size_t)k * nx + i] = i < s0.nb - 1 ? 0.0 : 1.0;
   for (int c = 0; c < nu; ++c) hu[c] = c < s0.ng ? 1.0 : 0.5 * (s0.ul[c] + s0.uu[c]);
   std::vector<double> ones(std::max({NX, NM, (size_t)nu}), 1.0);
+  // every device array of the timed passes, carved from one allocation: the
+  // sizes below, in the order they are taken, then the info word
+  const size_t NN = (size_t)nu * nu;
+  const size_t sizes[] = {NX, NX, NX, NX, NX, NM, NM, NM, NM, (size_t)nu, (size_t)nu, (size_t)nu,
+                          (size_t)N, NX, NU, NX, NM, NN, NN, NX, (size_t)nu, NM, NX, NM};
+  size_t nbuf = 0;
+  for (size_t n : sizes) nbuf += n;
   double* buf = nullptr;
-  const size_t nbuf = 6 * NX + 6 * NM + 5 * (size_t)nu + N + NU + 2 * (size_t)nu * nu;
   hipError_t e = hipMalloc((void**)&buf, nbuf * sizeof(double) + sizeof(int));
   if (e != hipSuccess) return hip_fail(nullptr, e, "rkkt_autotune: buffers");
   double* q = buf;
-  auto take = [&](size_t n) { double* r = q; q += n; return r; };
+  constexpr size_t kTakes = sizeof(sizes) / sizeof(sizes[0]);
+  size_t taken = 0, ti = 0;
+  bool layout_ok = true;
+  auto take = [&](size_t n) {
+    // the takes must follow `sizes` exactly (checked before any launch)
+    layout_ok = layout_ok && ti < kTakes && sizes[ti] == n;
+    ++ti;
+    double* r = q;
+    q += n;
+    taken += n;
+    return r;
+  };
   rkkt_iteration it{};
   double *dx = take(NX), *dy = take(NX), *dsx = take(NX), *r1x = take(NX), *r3 = take(NX);
   double *dz = take(NM), *dss = take(NM), *r2 = take(NM), *r4 = take(NM);
@@ -877,6 +900,10 @@ int rkkt_autotune(const rkkt_network* net, int n_scen, const double* pd, const d
   it.r1x = r1x; it.r1u = r1u; it.r2 = r2; it.r3 = r3; it.r4 = r4;
   it.px = take(NX); it.pu = take(nu); it.ps = take(NM); it.py = take(NX); it.pz = take(NM);
   it.info = reinterpret_cast<int*>(q);
+  if (!layout_ok || taken != nbuf || ti != kTakes) {
+    (void)hipFree(buf);
+    return fail(nullptr, RKKT_ERR_ARG, "rkkt_autotune: internal: buffer layout mismatch");
+  }
   auto up = [&](double* d, const double* v, size_t n) {
     return hipMemcpy(d, v, n * sizeof(double), hipMemcpyHostToDevice);
   };
@@ -902,7 +929,8 @@ int rkkt_autotune(const rkkt_network* net, int n_scen, const double* pd, const d
     rc = rkkt_create(net, n_scen, pd, qd, &o, &h);
     if (rc != RKKT_OK) return 1e300;
     const rkkt::Sym& sy = h->sym;
-    const std::vector<int> key{whole ? 1 : 0, sy.variant, sy.col_tile, sy.spw, sy.chain_t};
+    const std::vector<int> key{whole ? 1 : 0, sy.variant, sy.col_tile, sy.spw, sy.chain_t, sy.sweep_form,
+                               sy.lds_reduce ? 1 : 0};
     if (std::find(seen.begin(), seen.end(), key) != seen.end()) {
       rkkt_destroy(h);
       return 1e300;
@@ -911,6 +939,7 @@ int rkkt_autotune(const rkkt_network* net, int n_scen, const double* pd, const d
     *got = o;
     got->variant = sy.variant;
     got->col_tile = sy.col_tile;
+    got->sweep_form = sy.sweep_form;
     float ms = 0.f;
     rc = rkkt_evaluate(h, dx, du, dy, dz, it.obj_weight, it.f, it.grad_x, it.grad_u, it.g, it.h, nullptr);
     auto one = [&]() {

@@ -42,12 +42,12 @@ def oracle_state(inst, it, delta_w=None, reduced=True):
 class GpuRun:
     """Runs evaluate / condense / factor / step through the C ABI."""
 
-    def __init__(self, inst, it, delta_w, torch, col_tile=0, variant=0):
+    def __init__(self, inst, it, delta_w, torch, col_tile=0, variant=0, **opts):
         import paper_2301_04869_amd as R
         self.R = R
         net = inst.net
         self.p = R.rkkt_create(net, inst.scen.pd.T, inst.scen.qd.T, col_tile=col_tile,
-                               variant=variant)
+                               variant=variant, **opts)
         d = self.p.dims
         N, nx, nu, m = d["n_scen"], d["n_x"], d["n_u"], d["m"]
         t = lambda a: dev(a, torch)  # noqa: E731

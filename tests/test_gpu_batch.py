@@ -83,3 +83,28 @@ def test_autotune_returns_a_working_shape():
     assert ms > 0
     p = R.rkkt_create(inst.net, inst.scen.pd.T, inst.scen.qd.T, **best)
     assert p.dims["col_tile"] == best["col_tile"] and p.dims["variant"] == best["variant"]
+
+
+def test_autotune_on_the_largest_uneven_instance():
+    """The autotuner on the largest of the 64 uneven instances (1859 buses):
+    its whole-pass timings write every step output, which must fit the
+    tuner's own buffers; the chosen shape then runs a pass that matches the
+    oracle."""
+    import paper_2301_04869_amd as R
+    insts = sg.batch_instances(64, seed=2000)
+    inst = max(insts, key=lambda i: i.net.n_bus)
+    best, ms = R.rkkt_autotune(inst.net, inst.scen.pd.T, inst.scen.qd.T, reps=2)
+    print(f"\nautotune, {inst.net.n_bus} buses: {best}, {ms:.3f} ms per pass", flush=True)
+    it = random_iterate(inst.net, 1, 4321)
+    prob, ev, dg, red, dw = gc.oracle_state(inst, it)
+    st = gc.oracle_step(prob, ev, dg, red, dw, it)
+    run = gc.GpuRun(inst, it, dw, torch, **best)
+    run.evaluate()
+    run.condense()
+    run.factor()
+    run.step()
+    code, scen = R.rkkt_status(run.p)
+    assert code == 0, (code, scen)
+    torch.cuda.synchronize()
+    assert gc.rel_fro(run.khat.cpu().numpy(), red.khat) <= 1e-10
+    gc.check_step({k: v.cpu().numpy() for k, v in run.out.items()}, st, gc.cond2(red.khat))

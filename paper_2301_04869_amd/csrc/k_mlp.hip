@@ -19,13 +19,12 @@
 // bias gradient, the column sums of dZ_l, in the row that follows W_l in the
 // parameter layout.
 //
-// One wavefront per 32 x 32 output tile, as 2 x 2 blocks of
-// v_mfma_f32_16x16x32_bf16 (A operand: lane holds row lane % 16, k group
-// lane / 16 of 8 consecutive k; B operand: column lane % 16, the same k
-// group; result register r of a lane: row 4 (lane / 16) + r, column
-// lane % 16).  Operands come straight from global memory (each 16-byte
-// fragment is used by two products), the next k step's fragments loaded
-// while the current step's products run.
+// Each 32 x 32 output tile is 2 x 2 blocks of v_mfma_f32_16x16x32_bf16 (A
+// operand: lane holds row lane % 16, k group lane / 16 of 8 consecutive k;
+// B operand: column lane % 16, the same k group; result register r of a
+// lane: row 4 (lane / 16) + r, column lane % 16).  Operands come straight
+// from global memory (each 16-byte fragment is used by two products), the
+// next k step's fragments loaded while the current step's products run.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -80,9 +79,17 @@ __device__ __forceinline__ f32x4 mfma(uint4 a, uint4 b, f32x4 c) {
                                                  c, 0, 0, 0);
 }
 
+// One workgroup of four wavefronts per 32 x 32 output tile: wavefront w
+// takes the k steps w, w + 4, ... (so each wavefront's chain of dependent
+// loads is a quarter of K long), the four partial tiles are added in LDS in
+// wavefront order, and wavefront w then applies the epilogue to block
+// (w / 2, w % 2) of the tile.
+constexpr int kGemmWaves = 4;
+
 template <int EPI>
-__global__ __launch_bounds__(64) void k_gemm(MlpGemm g) {
-  const int lane = threadIdx.x;
+__global__ __launch_bounds__(64 * kGemmWaves) void k_gemm(MlpGemm g) {
+  __shared__ f32x4 part[kGemmWaves][4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int m0 = blockIdx.y * 32, n0 = blockIdx.x * 32;
   const int r16 = lane & 15, kq = (lane >> 4) * 8;
   const uint16_t* pa[2];
@@ -97,15 +104,16 @@ __global__ __launch_bounds__(64) void k_gemm(MlpGemm g) {
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  constexpr int kStride = 32 * kGemmWaves;
   uint4 a[2], b[2];
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
-    a[i] = frag8(pa[i], kq, g.K);
-    b[i] = frag8(pb[i], kq, g.K);
+    a[i] = frag8(pa[i], 32 * w + kq, g.K);
+    b[i] = frag8(pb[i], 32 * w + kq, g.K);
   }
-  for (int k0 = 0; k0 < g.K; k0 += 32) {
+  for (int k0 = 32 * w; k0 < g.K; k0 += kStride) {
     uint4 an[2], bn[2];
-    const int kn = k0 + 32 + kq;
+    const int kn = k0 + kStride + kq;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       an[i] = frag8(pa[i], kn, g.K);
@@ -121,48 +129,51 @@ __global__ __launch_bounds__(64) void k_gemm(MlpGemm g) {
       b[i] = bn[i];
     }
   }
-  // epilogue: lane holds rows mr .. mr + 3 of column nc in each block
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const int mr = m0 + 16 * i + 4 * (lane >> 4);
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int nc = n0 + 16 * j + r16;
-      if (nc >= g.N) continue;
-      float v[4];
+    for (int j = 0; j < 2; ++j) part[w][2 * i + j][lane] = acc[i][j];
+  __syncthreads();
+  // epilogue of block (i, j) = (w / 2, w % 2): lane holds rows mr .. mr + 3 of column nc
+  const int i = w >> 1, j = w & 1;
+  f32x4 t = part[0][w][lane];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) v[r] = acc[i][j][r];
-      uint16_t h[4];
+  for (int q = 1; q < kGemmWaves; ++q) t += part[q][w][lane];
+  const int mr = m0 + 16 * i + 4 * (lane >> 4);
+  const int nc = n0 + 16 * j + r16;
+  if (nc >= g.N) return;
+  float v[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int m = mr + r;
-        if (m >= g.M) break;
-        const long long o = (long long)m * g.ldz + nc;
-        if (EPI == kMlpStore) {
-          g.zout[o] = v[r];
-        } else if (EPI == kMlpBiasGelu || EPI == kMlpBiasOut) {
-          const float z = v[r] + g.bias[nc];
-          if (g.zout) g.zout[o] = z;
-          if (EPI == kMlpBiasOut) {
-            if (g.y) g.y[(long long)m * g.N + nc] = z;
-          } else {
-            h[r] = to_bf16(gelu(z));
-            g.hout[(long long)m * g.ldh + nc] = h[r];
-          }
-        } else {  // kMlpGeluBack: dZ_{l-1} = dA g'(Z_{l-1})
-          h[r] = to_bf16(v[r] * gelu_grad(g.zin[o]));
-          g.hout[(long long)m * g.ldh + nc] = h[r];
-        }
+  for (int r = 0; r < 4; ++r) v[r] = t[r];
+  uint16_t h[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int m = mr + r;
+    if (m >= g.M) break;
+    const long long o = (long long)m * g.ldz + nc;
+    if (EPI == kMlpStore) {
+      g.zout[o] = v[r];
+    } else if (EPI == kMlpBiasGelu || EPI == kMlpBiasOut) {
+      const float z = v[r] + g.bias[nc];
+      if (g.zout) g.zout[o] = z;
+      if (EPI == kMlpBiasOut) {
+        if (g.y) g.y[(long long)m * g.N + nc] = z;
+      } else {
+        h[r] = to_bf16(gelu(z));
+        g.hout[(long long)m * g.ldh + nc] = h[r];
       }
-      if ((EPI == kMlpBiasGelu || EPI == kMlpGeluBack) && g.tout) {
-        uint16_t* t = g.tout + (long long)nc * g.ldt + mr;
-        if (mr + 3 < g.M) {
-          *reinterpret_cast<uint2*>(t) = make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16),
-                                                    (uint32_t)h[2] | ((uint32_t)h[3] << 16));
-        } else {
-          for (int r = 0; r < 4 && mr + r < g.M; ++r) t[r] = h[r];
-        }
-      }
+    } else {  // kMlpGeluBack: dZ_{l-1} = dA g'(Z_{l-1})
+      h[r] = to_bf16(v[r] * gelu_grad(g.zin[o]));
+      g.hout[(long long)m * g.ldh + nc] = h[r];
+    }
+  }
+  if ((EPI == kMlpBiasGelu || EPI == kMlpGeluBack) && g.tout) {
+    uint16_t* tp = g.tout + (long long)nc * g.ldt + mr;
+    if (mr + 3 < g.M) {
+      *reinterpret_cast<uint2*>(tp) = make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16),
+                                                 (uint32_t)h[2] | ((uint32_t)h[3] << 16));
+    } else {
+      for (int r = 0; r < 4 && mr + r < g.M; ++r) tp[r] = h[r];
     }
   }
 }
@@ -178,28 +189,56 @@ __global__ void k_input_bf16(const float* __restrict__ x, int rows, int cols, ui
   if (t) t[(long long)c * ldt + r] = v;
 }
 
-// one workgroup: dZ = (Y - T) / B in BF16 (row-major and transposed) and the
-// loss 1/(2B) sum (Y - T)^2, summed in a fixed order
-constexpr int kLossT = 1024;
-__global__ __launch_bounds__(kLossT) void k_out_grad(const float* __restrict__ Y, const float* __restrict__ T,
-                                                     int rows, int cols, float inv_b, uint16_t* __restrict__ h,
-                                                     int ldh, uint16_t* __restrict__ t, int ldt,
-                                                     float* __restrict__ loss) {
-  __shared__ float red[kLossT];
-  const long long n = (long long)rows * cols;
+// dZ = (Y - T) / B in BF16, row-major and transposed, and the per-tile
+// partial sums of (Y - T)^2: one workgroup per 32 x 32 tile, the transposed
+// copy written through LDS so both stores are coalesced
+constexpr int kOG = 32, kOGT = 256;
+__global__ __launch_bounds__(kOGT) void k_out_grad(const float* __restrict__ Y, const float* __restrict__ T,
+                                                   int rows, int cols, float inv_b, uint16_t* __restrict__ h,
+                                                   int ldh, uint16_t* __restrict__ t, int ldt,
+                                                   float* __restrict__ part) {
+  __shared__ uint16_t tile[kOG][kOG + 2];
+  __shared__ float red[kOGT];
+  const int c0 = blockIdx.x * kOG, r0 = blockIdx.y * kOG;
+  const int tx = threadIdx.x % kOG, ty = threadIdx.x / kOG;
   float sq = 0.0f;
-  for (long long i = threadIdx.x; i < n; i += kLossT) {
-    const int r = (int)(i / cols), c = (int)(i % cols);
-    const float d = Y[i] - T[i];
-    sq = fmaf(d, d, sq);
-    const uint16_t v = to_bf16(d * inv_b);
-    h[(long long)r * ldh + c] = v;
-    t[(long long)c * ldt + r] = v;
+  for (int rr = ty; rr < kOG; rr += kOGT / kOG) {
+    const int r = r0 + rr, c = c0 + tx;
+    uint16_t v = 0;
+    if (r < rows && c < cols) {
+      const long long i = (long long)r * cols + c;
+      const float d = Y[i] - T[i];
+      sq = fmaf(d, d, sq);
+      v = to_bf16(d * inv_b);
+      h[(long long)r * ldh + c] = v;
+    }
+    tile[rr][tx] = v;
+  }
+  __syncthreads();
+  for (int cc = ty; cc < kOG; cc += kOGT / kOG) {
+    const int c = c0 + cc, r = r0 + tx;
+    if (c < cols && r < rows) t[(long long)c * ldt + r] = tile[tx][cc];
   }
   red[threadIdx.x] = sq;
   __syncthreads();
-  for (int s = kLossT / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+  for (int w = kOGT / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+}
+
+// loss = 0.5 inv_b sum of the partials, in a fixed order
+constexpr int kLossT = 256;
+__global__ __launch_bounds__(kLossT) void k_loss_final(const float* __restrict__ part, int np, float inv_b,
+                                                       float* __restrict__ loss) {
+  __shared__ float red[kLossT];
+  float sum = 0.0f;
+  for (int i = threadIdx.x; i < np; i += kLossT) sum += part[i];
+  red[threadIdx.x] = sum;
+  __syncthreads();
+  for (int w = kLossT / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x == 0) *loss = 0.5f * inv_b * red[0];
@@ -254,10 +293,10 @@ __global__ void k_fill_bf16(uint16_t* __restrict__ d, long long n, uint16_t v) {
 void mlp_gemm(int epi, const MlpGemm& g, hipStream_t st) {
   const dim3 grid((unsigned)((g.N + 31) / 32), (unsigned)((g.M + 31) / 32));
   switch (epi) {
-    case kMlpStore: k_gemm<kMlpStore><<<grid, 64, 0, st>>>(g); break;
-    case kMlpBiasGelu: k_gemm<kMlpBiasGelu><<<grid, 64, 0, st>>>(g); break;
-    case kMlpBiasOut: k_gemm<kMlpBiasOut><<<grid, 64, 0, st>>>(g); break;
-    default: k_gemm<kMlpGeluBack><<<grid, 64, 0, st>>>(g); break;
+    case kMlpStore: k_gemm<kMlpStore><<<grid, 64 * kGemmWaves, 0, st>>>(g); break;
+    case kMlpBiasGelu: k_gemm<kMlpBiasGelu><<<grid, 64 * kGemmWaves, 0, st>>>(g); break;
+    case kMlpBiasOut: k_gemm<kMlpBiasOut><<<grid, 64 * kGemmWaves, 0, st>>>(g); break;
+    default: k_gemm<kMlpGeluBack><<<grid, 64 * kGemmWaves, 0, st>>>(g); break;
   }
 }
 
@@ -266,9 +305,14 @@ void mlp_input_bf16(const float* x, int rows, int cols, uint16_t* h, int ldh, ui
   k_input_bf16<<<blocks((long long)rows * cols), kT, 0, st>>>(x, rows, cols, h, ldh, t, ldt);
 }
 
+int mlp_out_grad_tiles(int rows, int cols) { return ((rows + kOG - 1) / kOG) * ((cols + kOG - 1) / kOG); }
+
 void mlp_out_grad(const float* Y, const float* T, int rows, int cols, uint16_t* h, int ldh, uint16_t* t,
-                  int ldt, float* loss, hipStream_t st) {
-  k_out_grad<<<1, kLossT, 0, st>>>(Y, T, rows, cols, 1.0f / (float)rows, h, ldh, t, ldt, loss);
+                  int ldt, float* part, float* loss, hipStream_t st) {
+  const dim3 grid((unsigned)((cols + kOG - 1) / kOG), (unsigned)((rows + kOG - 1) / kOG));
+  const float inv_b = 1.0f / (float)rows;
+  k_out_grad<<<grid, kOGT, 0, st>>>(Y, T, rows, cols, inv_b, h, ldh, t, ldt, part);
+  k_loss_final<<<1, kLossT, 0, st>>>(part, mlp_out_grad_tiles(rows, cols), inv_b, loss);
 }
 
 void mlp_param_copies(const float* p, long long n, const MlpLayers& L, uint16_t* wb, uint16_t* wt,

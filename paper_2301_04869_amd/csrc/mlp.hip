@@ -23,6 +23,7 @@ struct rkkt_mlp {
   std::vector<uint16_t*> AT;          // A_l^T [sz[l] + 1][bpit], BF16, last row ones
   std::vector<float*> Z;              // Z_l [bmax][sz[l + 1]], FP32 pre-activations
   uint16_t *dZb[2] = {nullptr, nullptr}, *dZT[2] = {nullptr, nullptr};  // output gradients, both orientations
+  float* lpart = nullptr;             // loss partial sums, one per output-gradient tile
   int t = 0;
   std::vector<void*> allocs;
   std::string err;
@@ -93,7 +94,8 @@ int gradients_impl(rkkt_mlp* m, const float* x, const float* t, int B, float* lo
   if (int rc = forward_impl(m, x, B, nullptr, true, st)) return rc;
   const int L = m->L;
   int c = 0;
-  rkkt::mlp_out_grad(m->Z[L - 1], t, B, m->sz[L], m->dZb[c], mlp_pad8(m->sz[L]), m->dZT[c], m->bpit, loss, st);
+  rkkt::mlp_out_grad(m->Z[L - 1], t, B, m->sz[L], m->dZb[c], mlp_pad8(m->sz[L]), m->dZT[c], m->bpit, m->lpart,
+                     loss, st);
   for (int l = L - 1; l >= 0; --l) {
     const int fi = m->sz[l], fo = m->sz[l + 1];
     // [dW_l; db_l] = [A_l^T; 1^T] dZ_l: fi + 1 rows, the last one lands on b_l
@@ -235,6 +237,7 @@ int rkkt_mlp_create(const int* sizes, int n_layers, int batch_max, rkkt_mlp** ou
     e = dalloc(m, &m->dZb[c], (long long)batch_max * mlp_pad8(wmax));
     if (e == hipSuccess) e = dalloc(m, &m->dZT[c], (long long)wmax * m->bpit);
   }
+  if (e == hipSuccess) e = dalloc(m, &m->lpart, rkkt::mlp_out_grad_tiles(batch_max, m->sz[n_layers]));
   if (e == hipSuccess) {
     for (int l = 0; l < n_layers; ++l)
       rkkt::mlp_fill_bf16(m->AT[l] + (long long)m->sz[l] * m->bpit, m->bpit, 1.0f, nullptr);

@@ -50,8 +50,10 @@ inline int mlp_pad8(int n) { return (n + 7) / 8 * 8; }
 void mlp_gemm(int epi, const MlpGemm& g, hipStream_t st);
 void mlp_input_bf16(const float* x, int rows, int cols, uint16_t* h, int ldh, uint16_t* t, int ldt,
                     hipStream_t st);
+// partial sums per 32 x 32 tile of the output gradient (the part buffer's length)
+int mlp_out_grad_tiles(int rows, int cols);
 void mlp_out_grad(const float* Y, const float* T, int rows, int cols, uint16_t* h, int ldh, uint16_t* t,
-                  int ldt, float* loss, hipStream_t st);
+                  int ldt, float* part, float* loss, hipStream_t st);
 void mlp_param_copies(const float* p, long long n, const MlpLayers& L, uint16_t* wb, uint16_t* wt,
                       hipStream_t st);
 void mlp_adam(float* p, const float* g, float* m, float* v, long long n, float lr, int t, const MlpLayers& L,

@@ -331,6 +331,24 @@ def pass_roofline(d, ms_per_step, cf_ms):
                                 "measured_us": cf_ms * 1e3, "frac": t_cf / (cf_ms * 1e-3)}}
 
 
+def attach_probe_peaks(out, probe):
+    """The rates the copy and FP64 probes reach on this device, and the
+    roofline fractions against them beside those against the datasheet peaks
+    (HBM 8 TB/s; FP64 vector and matrix core 78.6 TFLOP/s)."""
+    out["probe_peaks"] = {"hbm_gbs": probe["hbm_gbs"], "fp64_vec_tfs": probe["fp64_vec_tfs"],
+                          "fp64_mfma_tfs": probe["fp64_mfma_tfs"],
+                          "what": "1 GiB device copy; 8 independent FP64 FMA chains per thread; "
+                                  "4 independent v_mfma_f64_16x16x4f64 accumulations per wavefront"}
+    roof = out["roofline"]
+    meas = probe["hbm_gbs"] if roof["bound"] == "hbm" else probe["fp64_vec_tfs"]
+    roof["measured_peak"] = meas
+    roof["frac_of_measured"] = roof["achieved"] / meas
+    for part in out["roofline_pass"].values():
+        t = max(part["bytes"] / (probe["hbm_gbs"] * 1e9), part["flops"] / (probe["fp64_vec_tfs"] * 1e12))
+        part["roof_us_measured_peaks"] = t * 1e6
+        part["frac_of_measured"] = t / (part["measured_us"] * 1e-6)
+
+
 def find_delta_w(R, torch, p, t, khat, chol, info):
     """Inertia correction of the interior-point rules: delta_w = 0, then 1e-4,
     x100 until the reduced matrix factorises."""
@@ -415,6 +433,8 @@ def main():
                     help="c2: automatic launch shapes instead of the autotuner's")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-probe", action="store_true",
+                    help="skip the copy / FP64 probes of the machine balance")
     ap.add_argument("--seed", type=int, default=2024)
     ap.add_argument("--n-train", type=int, default=20000, help="warm: training draws")
     ap.add_argument("--n-val", type=int, default=200, help="warm: validation draws (choice of mu0)")
@@ -507,12 +527,15 @@ def main():
     for _ in range(args.warmup):
         R.rkkt_graph_launch(p, stream)
     torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(args.steps):
+    # an event between every two replays (recording one adds no dependency)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    evs[0].record(stream)
+    for i in range(args.steps):
         R.rkkt_graph_launch(p, stream)
-    e1.record(stream)
+        evs[i + 1].record(stream)
     torch.cuda.synchronize()
-    graph_ms = e0.elapsed_time(e1) / args.steps
+    graph_ms = evs[0].elapsed_time(evs[-1]) / args.steps
+    per_replay = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
     progress(f"graph replays timed: {graph_ms:.3f} ms per pass")
     ms = min(graph_ms, eager_ms)
     value = N / (ms * 1e-3)
@@ -532,11 +555,18 @@ def main():
                    "sweep_form": d["sweep_form"], "delta_w": dw,
                    "seed": args.seed},
         "graph_ms_per_step": graph_ms, "eager_ms_per_step": eager_ms,
+        "graph_replay_ms": {"median": float(np.median(per_replay)),
+                            "p90": float(np.percentile(per_replay, 90)),
+                            "min": float(per_replay.min()), "max": float(per_replay.max()),
+                            "n": int(per_replay.size)},
         "condense_factor_value": N / (cf_ms * 1e-3),
         "stage_ms": {s: stages[s][0] / max(stages[s][1], 1) for s in stages},
         "roofline": roof,
         "roofline_pass": pass_roofline(d, ms, cf_ms),
     }
+
+    if not args.no_probe:
+        attach_probe_peaks(out, R.rkkt_probe_peaks())
 
     if not args.no_plain:
         # the same kernels, one scenario per handle and per launch, no batching

@@ -354,6 +354,22 @@ int rkkt_profile_begin(rkkt_problem* p, int max_records);
 int rkkt_profile_end(rkkt_problem* p, hipStream_t stream, double* ms, int* count);
 
 /*
+ * Machine-balance probes for roofline reports (measurement only; no stage of
+ * the hot path uses them).  On `device` it times, best of five launches after
+ * one untimed launch each, on a stream of its own:
+ *   hbm_gbs       a device-to-device copy of 1 GiB in 16-byte units
+ *                 (GB/s = 2 GiB moved / time);
+ *   fp64_vec_tfs  eight independent FP64 multiply-add chains per thread over
+ *                 8 workgroups of 256 threads per compute unit (TFLOP/s);
+ *   fp64_mfma_tfs four independent v_mfma_f64_16x16x4f64 accumulations per
+ *                 wavefront over the same grid (TFLOP/s, 2048 flops each).
+ * Allocates and frees 2 GiB plus a small output buffer and synchronises the
+ * device.  RKKT_ERR_ARG for a null output, RKKT_ERR_NOMEM when the buffers do
+ * not fit, RKKT_ERR_HIP for any other failed HIP call (outputs then unset).
+ */
+int rkkt_probe_peaks(int device, double* hbm_gbs, double* fp64_vec_tfs, double* fp64_mfma_tfs);
+
+/*
  * One hot-path pass with fixed buffers: evaluate, condense, factor, step (the
  * calls above, each argument as documented there), with the same results as
  * those calls in that order, except that the factor of khat is written to

@@ -6,7 +6,7 @@ from ._lib import (RkktError, lib, rkkt_analyze, rkkt_create, rkkt_set_loads, rk
                    rkkt_destroy, rkkt_last_error, rkkt_profile_begin, rkkt_profile_end,
                    rkkt_solve, rkkt_solve_warm, rkkt_iterate, rkkt_graph_capture, rkkt_graph_launch,
                    rkkt_batch_create, rkkt_batch_launch, rkkt_batch_destroy, rkkt_autotune,
-                   rkkt_analyze_lu, rkkt_analyze_schedule, SCHEDULES, EXPORTS, STAGES, LIB_PATH,
+                   rkkt_analyze_lu, rkkt_analyze_schedule, rkkt_probe_peaks, SCHEDULES, EXPORTS, STAGES, LIB_PATH,
                    Mlp, Multi, mlp_layout, MLP_EXPORTS)
 
 __all__ = ["RkktError", "lib", "rkkt_analyze", "rkkt_create", "rkkt_set_loads", "rkkt_set_line_status", "rkkt_dims_get",
@@ -14,5 +14,5 @@ __all__ = ["RkktError", "lib", "rkkt_analyze", "rkkt_create", "rkkt_set_loads", 
            "rkkt_destroy", "rkkt_last_error", "rkkt_profile_begin", "rkkt_profile_end",
            "rkkt_solve", "rkkt_solve_warm", "rkkt_iterate", "rkkt_graph_capture",
            "rkkt_graph_launch", "rkkt_batch_create", "rkkt_batch_launch", "rkkt_batch_destroy",
-           "rkkt_autotune", "rkkt_analyze_lu", "rkkt_analyze_schedule", "SCHEDULES", "EXPORTS",
+           "rkkt_autotune", "rkkt_analyze_lu", "rkkt_analyze_schedule", "rkkt_probe_peaks", "SCHEDULES", "EXPORTS",
            "STAGES", "LIB_PATH", "Mlp", "Multi", "mlp_layout", "MLP_EXPORTS"]

@@ -28,7 +28,7 @@ EXPORTS = ("rkkt_create", "rkkt_analyze", "rkkt_set_loads", "rkkt_dims_get", "rk
            "rkkt_batch_launch", "rkkt_batch_destroy", "rkkt_autotune", "rkkt_analyze_lu",
            "rkkt_analyze_schedule", "rkkt_set_line_status", "rkkt_solve_warm", "rkkt_multi_create",
            "rkkt_multi_iterate", "rkkt_multi_capture", "rkkt_multi_launch", "rkkt_multi_launches",
-           "rkkt_multi_destroy", "rkkt_multi_last_error")
+           "rkkt_multi_destroy", "rkkt_multi_last_error", "rkkt_probe_peaks")
 MLP_EXPORTS = ("rkkt_mlp_create", "rkkt_mlp_destroy", "rkkt_mlp_last_error", "rkkt_mlp_n_params",
                "rkkt_mlp_set_params", "rkkt_mlp_get_params", "rkkt_mlp_forward", "rkkt_mlp_gradients",
                "rkkt_mlp_train_step", "rkkt_mlp_forward_static")
@@ -131,6 +131,7 @@ def lib():
     L.rkkt_status.argtypes = [vp, vp, c_int_p, c_int_p]
     L.rkkt_destroy.argtypes = [vp]
     L.rkkt_profile_begin.argtypes = [vp, ctypes.c_int]
+    L.rkkt_probe_peaks.argtypes = [ctypes.c_int] + [ctypes.POINTER(ctypes.c_double)] * 3
     L.rkkt_profile_end.argtypes = [vp, vp, c_dbl_p, c_int_p]
     L.rkkt_solve.argtypes = [vp, ctypes.POINTER(IpmOptions), vp, vp, vp, vp, vp,
                              ctypes.POINTER(IpmResult), vp]
@@ -399,6 +400,14 @@ def rkkt_profile_end(p, stream=None):
     cnt = (ctypes.c_int * len(STAGES))()
     _check(lib().rkkt_profile_end(p.ptr, _stream(stream), ms, cnt), p.ptr)
     return {s: (ms[i], cnt[i]) for i, s in enumerate(STAGES)}
+
+
+def rkkt_probe_peaks(device=0):
+    """Measured machine balance: {"hbm_gbs", "fp64_vec_tfs", "fp64_mfma_tfs"}
+    (copy, FP64 multiply-add and FP64 matrix-core probes)."""
+    out = [ctypes.c_double() for _ in range(3)]
+    _check(lib().rkkt_probe_peaks(int(device), *[ctypes.byref(v) for v in out]))
+    return {"hbm_gbs": out[0].value, "fp64_vec_tfs": out[1].value, "fp64_mfma_tfs": out[2].value}
 
 
 def rkkt_solve(p, x=None, u=None, y=None, z=None, s=None, tol=0.0, max_iter=-1, mu0=0.0,

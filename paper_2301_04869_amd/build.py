@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SOURCES = ["symbolic.cpp", "api.cpp", "ipm.cpp", "k_eval.hip", "k_lu.hip", "k_dense.hip", "k_ipm.hip",
-           "k_mlp.hip", "mlp.hip"]
+           "k_mlp.hip", "mlp.hip", "k_probe.hip"]
 LIB = os.path.join(HERE, "librkkt.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -215,6 +215,8 @@ int rkkt_create(const rkkt_network* net, int n_scen, const double* pd, const dou
   d.nlev_dn = (int)s.lvd_ptr.size() - 1;
   d.nph_u = s.stp_up.nphase;
   d.nph_d = s.stp_dn.nphase;
+  d.n_kz = (int)(s.kz_items.size() / 4);
+  d.kz_rounds = s.kz_rounds;
   d.nph_ru = s.red_up.nphase;
   d.nph_rd = s.red_dn.nphase;
   d.n_upd = (int)s.upd_dst.size();
@@ -272,6 +274,7 @@ int rkkt_create(const rkkt_network* net, int n_scen, const double* pd, const dou
   UP(h_ptr, s.h_ptr) UP(h_col, s.h_col) UP(ht_ptr, s.ht_ptr) UP(ht_row, s.ht_row)
   UP(ht_pos, s.ht_pos) UP(h0pos, s.h0pos)
   UP(k_ptr, s.k_ptr) UP(k_col, s.k_col) UP(k_diag, s.k_diag) UP(k_usplit, s.k_usplit)
+  UP(kz_items, s.kz_items)
   UP(k_row, k_row)
   UP(w_ptr, s.w_ptr) UP(w_src, s.w_src) UP(wp_ptr, s.wp_ptr) UP(wp_a, s.wp_a) UP(wp_b, s.wp_b)
   UP(wp_coef, s.wp_coef) UP(w_const, s.w_const)

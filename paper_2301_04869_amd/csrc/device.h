@@ -41,6 +41,8 @@ struct DP {
   const int *gu_ptr, *gu_col, *guc_ptr, *guc_row, *guc_pos;
   const int *h_ptr, *h_col, *ht_ptr, *ht_row, *ht_pos, *h0pos;
   const int *k_ptr, *k_col, *k_diag, *k_usplit, *k_row;
+  const int* kz_items;  // K-row pieces, four ints each (see Sym::kz_items)
+  int n_kz, kz_rounds;
   const int *w_ptr, *w_src, *wp_ptr, *wp_a, *wp_b;
   const double *wp_coef, *w_const;
   const int *t_ptr, *t_row, *t_a, *t_b;

@@ -903,17 +903,53 @@ __device__ __forceinline__ void reduce64_body(const DP& d, int bx_, int by_, int
     int* skp = ip; ip += nz + 1;
     int* sku = ip; ip += nz;
     int* skc = ip;
-    stage_copy(slu, lu_of(d, k), d.nnz_f + nx, tid, kRT);
-    stage_copy(skv, d.K + (long long)k * d.nnz_k, d.nnz_k, tid, kRT);
-    stage_copy(skp, d.k_ptr, nz + 1, tid, kRT);
-    stage_copy(sku, d.k_usplit, nz, tid, kRT);
-    stage_copy(skc, d.k_col, d.nnz_k, tid, kRT);
+    // Staging: the loads of every array (factor values and 1/u_ii, K values
+    // and pattern, the scenario's G_u values) are in flight together before
+    // the first LDS store, about two round trips to L2 or HBM in all (the
+    // G_u values wait for their positions) instead of one or more per array.
+    {
+      constexpr int kB = 4;  // elements per thread and array in flight
+      const int nlu = d.nnz_f + nx, nk = d.nnz_k, ngu = d.nnz_gu;
+      const double* glu = lu_of(d, k);
+      const double* gk = d.K + (long long)k * nk;
+      const int nmax = max(max(nlu, nk), max(nz + 1, ngu));
+      for (int i0 = tid; i0 < nmax; i0 += kB * kRT) {
+        double va[kB], vb[kB], vg[kB];
+        int ia[kB], ib[kB], ic[kB], ig[kB];
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+          const int i = i0 + u * kRT;
+          if (i < nlu) va[u] = glu[i];
+          if (i < nk) {
+            vb[u] = gk[i];
+            ic[u] = d.k_col[i];
+          }
+          if (i <= nz) ia[u] = d.k_ptr[i];
+          if (i < nz) ib[u] = d.k_usplit[i];
+          if (i < ngu) ig[u] = d.guc_pos[i];
+        }
+#pragma unroll
+        for (int u = 0; u < kB; ++u)
+          if (i0 + u * kRT < ngu) vg[u] = ev[d.off_gu + ig[u]];
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+          const int i = i0 + u * kRT;
+          if (i < nlu) slu[i] = va[u];
+          if (i < nk) {
+            skv[i] = vb[u];
+            skc[i] = ic[u];
+          }
+          if (i <= nz) skp[i] = ia[u];
+          if (i < nz) sku[i] = ib[u];
+          if (i < ngu) sgu[i] = vg[u];
+        }
+      }
+    }
     k_ptr = skp;
     k_usplit = sku;
     k_col = skc;
     kv = skv;
     cv = smem + (reduce_lds_bytes(sizes_of(d)) / 8 - (long long)d.chain_t * d.chain_t);
-    for (int j = tid; j < d.nnz_gu; j += kRT) sgu[j] = ev[d.off_gu + d.guc_pos[j]];
     lu = slu; invd = slu + d.nnz_f; guv = sgu;
   } else {
     lu = lu_of(d, k);
@@ -1048,25 +1084,73 @@ __device__ __forceinline__ void reduce64_body(const DP& d, int bx_, int by_, int
       // of one instruction spread over the LDS banks.  Each value is
       // K[r][n_x + col] plus the x entries' terms in pattern order.
       const int ln = (tid >> 2) & 15;
-      for (int it = tid; it < nz * 4; it += kRT) {
-        const int r = it >> 2, lo = 16 * (it & 3);
-        const int e0 = k_ptr[r], eu = k_usplit[r], e1 = k_ptr[r + 1];
-        double acc[16];
+      // the terms of row r from entries [e0, e1) into acc (the quarter at
+      // column lo), the u-part value K[r][n_x + col] first when `head`
+      auto item = [&](int r, int e0, int e1, bool head, int lo, double (&acc)[16]) {
 #pragma unroll
         for (int j = 0; j < 16; ++j) acc[j] = 0.0;
-        for (int e = eu; e < e1; ++e) {
-          const int cu = k_col[e] - nx - c0 - lo;
-          const double v = kv[e];
+        if (head)
+          for (int e = k_usplit[r]; e < k_ptr[r + 1]; ++e) {
+            const int cu = k_col[e] - nx - c0 - lo;
+            const double v = kv[e];
 #pragma unroll
-          for (int j = 0; j < 16; ++j)
-            if (((j + ln) & 15) == cu) acc[j] = v;
-        }
-        for (int e = e0; e < eu; ++e) {
+            for (int j = 0; j < 16; ++j)
+              if (((j + ln) & 15) == cu) acc[j] = v;
+          }
+        for (int e = e0; e < e1; ++e) {
           const double v = kv[e];
           const double* tr = T + (long long)k_col[e] * kW64 + lo;
 #pragma unroll
           for (int j = 0; j < 16; ++j) acc[j] = fma(v, tr[(j + ln) & 15], acc[j]);
         }
+      };
+      if (d.n_kz > 0) {
+        // Items (piece of a K row, 16-column quarter), the longest pieces
+        // first, at most kKzItems per thread.  A thread's items stay in
+        // registers until every panel read is done; the rows then pass
+        // through LDS (the whole workgroup's LDS is dead by then), the pieces
+        // of a row added in piece order one round each, and leave as whole
+        // 512-byte rows instead of one 8-byte store per value (the 8-byte
+        // stores, spread over the row items, measured 3 us slower per launch
+        // on the 118-bus grid).
+        const int4* items = reinterpret_cast<const int4*>(d.kz_items);
+        double res[kKzItems][16];
+        int4 pc[kKzItems];
+#pragma unroll
+        for (int u = 0; u < kKzItems; ++u) {
+          const int it = tid + u * kRT;
+          pc[u] = it < 4 * d.n_kz ? items[it >> 2] : make_int4(-1, 0, 0, -1);
+          if (pc[u].x >= 0) item(pc[u].x, pc[u].y, pc[u].z, pc[u].w == 0, 16 * (tid & 3), res[u]);
+        }
+        __syncthreads();
+        const int rows = (int)(reduce_lds_bytes(sizes_of(d)) / (8 * kW64));
+        for (int rb = 0; rb < nz; rb += rows) {
+          for (int q = 0; q < d.kz_rounds; ++q) {
+#pragma unroll
+            for (int u = 0; u < kKzItems; ++u) {
+              const int r = pc[u].x - rb, lo = 16 * (tid & 3);
+              if (pc[u].w == q && r >= 0 && r < rows) {
+                double* srow = smem + (long long)r * kW64 + lo;
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                  const int cj = (j + ln) & 15;
+                  srow[cj] = q == 0 ? res[u][j] : srow[cj] + res[u][j];
+                }
+              }
+            }
+            __syncthreads();
+          }
+          const int rn = min(rows, nz - rb);
+          if (colok)
+            for (int r = wv; r < rn; r += kS64) kzk[(long long)(rb + r) * d.nu_pad + col] = smem[r * kW64 + c];
+          if (rb + rows < nz) __syncthreads();
+        }
+        return;
+      }
+      for (int it = tid; it < nz * 4; it += kRT) {
+        const int r = it >> 2, lo = 16 * (it & 3);
+        double acc[16];
+        item(r, k_ptr[r], k_usplit[r], true, lo, acc);
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
           const int cc = c0 + lo + ((j + ln) & 15);

@@ -738,6 +738,21 @@ std::string build_symbolic(const rkkt_network& net, int N, const rkkt_options* o
     auto b = s.k_col.begin() + s.k_ptr[r], e = s.k_col.begin() + s.k_ptr[r + 1];
     s.k_usplit[r] = (int)(std::lower_bound(b, e, nx) - s.k_col.begin());
   }
+  // K-row items of the product K Z in the LDS-mode reduction: one per row
+  // (its x-part entries as one run), longest first, so that the threads
+  // holding the longest rows start them first and the shortest rows are the
+  // second items; none when they need more than kKzItems items of four per
+  // thread.  (Cutting the long rows into shorter runs, summed in order one
+  // round each, measured no faster on the 118-bus grid.)
+  if (4LL * s.nz <= (long long)kKzItems * kRedThreads) {
+    std::vector<std::array<int, 4>> pc;
+    for (int r = 0; r < s.nz; ++r) pc.push_back({r, s.k_ptr[r], s.k_usplit[r], 0});
+    std::stable_sort(pc.begin(), pc.end(), [](const std::array<int, 4>& a, const std::array<int, 4>& b) {
+      return a[2] - a[1] > b[2] - b[1];
+    });
+    for (auto& t : pc) s.kz_items.insert(s.kz_items.end(), t.begin(), t.end());
+    s.kz_rounds = 1;
+  }
 
   // G_x entries inside the filled pattern
   s.gx2f.resize(s.gx_col.size());

@@ -78,6 +78,12 @@ struct Sym {
 
   // K over internal z = (xhat, u): CSR, full symmetric storage, sorted columns
   std::vector<int> k_ptr, k_col, k_diag, k_usplit;  // k_usplit[r]: first entry with col >= nx
+  // pieces of the K rows for the product K Z in the LDS-mode reduction, as
+  // (row, first entry, end entry of its x part, index of the piece within
+  // its row), longest first; kz_rounds = most pieces of one row (empty when
+  // they need more than kKzItems items of four per thread)
+  std::vector<int> kz_items;
+  int kz_rounds = 0;
   // W gather: LH sources, product terms (coef * Hval[a] * Hval[b]), constant (times obj weight)
   std::vector<int> w_ptr, w_src;
   std::vector<int> wp_ptr, wp_a, wp_b;

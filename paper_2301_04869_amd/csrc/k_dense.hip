@@ -85,20 +85,45 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // so that sum_c gpart_c = sum_k Z_k^T K_k Z_k.  The output's lower triangle
 // is cut into 16 x 16 blocks, grouped into super-tiles of kSB x kSB blocks
 // (triangular on the diagonal).  One workgroup per (super-tile, chunk): it
-// streams the chunk's rows in slabs of 32 through LDS (the super-tile's 16 kSB
-// columns of Z and of K Z, double-buffered, each value read from HBM once per
-// super-tile) and its 4 wavefronts take the super-tile's blocks round robin,
-// each block one v_mfma_f64_16x16x4f64 accumulator (A operand: lane holds
-// Z[rho + lane/16][i + lane%16]; B operand: (K Z)[rho + lane/16][j + lane%16];
-// result register r of a lane: row lane/16 + 4 r, column lane%16).
+// streams the chunk's rows in slabs of kSpSlab rows (the super-tile's 16 kSB
+// columns of Z and of K Z) straight from global memory into LDS
+// (global_load_lds_dwordx4, no registers held), four slab buffers deep with
+// three slabs in flight, and its 4 wavefronts take the super-tile's blocks
+// round robin, each block one v_mfma_f64_16x16x4f64 accumulator (A operand:
+// lane holds Z[rho + lane/16][i + lane%16]; B operand: (K Z)[rho +
+// lane/16][j + lane%16]; result register r of a lane: row lane/16 + 4 r,
+// column lane%16).  Chunks are whole slabs except the last, whose rows past
+// the last stacked row are zero rows of the panels (four slabs of them, as
+// the pipeline loads up to three slabs past a chunk's last one; those slabs
+// are not multiplied), so they add nothing.
 constexpr int kSB = 7;                        // blocks per super-tile side
 constexpr int kSBMax = (kSB * kSB + 3) / 4;   // blocks per wavefront, at most
-constexpr int kSlab = 32, kSW = 16 * kSB + 1; // slab rows, LDS row pitch
+constexpr int kSpCols = 16 * kSB;             // columns of a slab part (Z or K Z), LDS row pitch
+constexpr int kSpPart = kSpSlab * kSpCols;    // doubles of one part of a slab
+constexpr int kSpLoads = 2 * kSpPart / 128;   // 1 KiB wavefront loads per slab (64 lanes x 16 bytes)
+constexpr int kSpPerWave = kSpLoads / 4;
+static_assert(kSpPart % 128 == 0 && kSpLoads % 4 == 0, "slab loads: whole 1 KiB units, four wavefronts");
+static_assert(kSpCols % 2 == 0, "a lane's two doubles stay in one row");
 
 __host__ __device__ inline int sp_nblk(int nu) { return (nu + 15) / 16; }
 __host__ __device__ inline int sp_nsuper(int nu) { return (sp_nblk(nu) + kSB - 1) / kSB; }
 __host__ __device__ inline long long sp_rows_per_chunk(long long rows, int nchunk) {
-  return ((rows + nchunk - 1) / nchunk + kSlab - 1) / kSlab * kSlab;
+  return ((rows + nchunk - 1) / nchunk + kSpSlab - 1) / kSpSlab * kSpSlab;
+}
+
+__shared__ double sp_buf0[2 * kSpPart], sp_buf1[2 * kSpPart], sp_buf2[2 * kSpPart], sp_buf3[2 * kSpPart];
+
+// s_waitcnt immediates (vmcnt in bits 3:0, expcnt and lgkmcnt at their maxima)
+constexpr int kWaitVm2Slabs = 0x0F70 | (2 * kSpPerWave);
+constexpr int kWaitVm0 = 0x0F70;
+static_assert(2 * kSpPerWave < 16, "vmcnt wait fits the low field");
+
+// workgroup barrier that the compiler may not move memory accesses across;
+// the hardware waits are explicit (the slab loads in flight must stay so)
+__device__ __forceinline__ void sp_barrier() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
 // kSlots: blocks per wavefront for this shape; every slot's product runs
@@ -106,22 +131,19 @@ __host__ __device__ inline long long sp_rows_per_chunk(long long rows, int nchun
 // so the accumulators stay in fixed registers with no branches around them
 template <int kSlots>
 __device__ __forceinline__ void stacked_product_body(int bx_, int by_, int gx_, const DP& d, long long per) {
-  __shared__ double zs[2][kSlab * kSW], ks[2][kSlab * kSW];
   int t = bx_, SI = 0;
   while (t > SI) { t -= SI + 1; ++SI; }
   const int SJ = t, chunk = by_;
   const int nblk = sp_nblk(d.nu);
   const int bi0 = SI * kSB, bj0 = SJ * kSB;
   const int ni = min(kSB, nblk - bi0), nj = min(kSB, nblk - bj0);
-  const int ci = 16 * ni, cj = 16 * nj;        // columns staged of Z, of K Z
   const long long rows = (long long)d.N * d.nz;
   const long long r0 = (long long)chunk * per, r1 = min(rows, r0 + per);
+  const int nsl = r1 > r0 ? (int)((r1 - r0 + kSpSlab - 1) / kSpSlab) : 0;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lm = lane & 15, lk = lane >> 4;
   const long long ld = d.nu_pad;
-  const double* Z = d.Zst + 16LL * bi0;
-  const double* KZ = d.KZst + 16LL * bj0;
   // this wavefront's blocks: numbers wv, wv + 4, ... of the super-tile's
   // blocks (a, b) in row order (lower triangle on the diagonal), a over Z,
   // b over K Z
@@ -145,75 +167,89 @@ __device__ __forceinline__ void stacked_product_body(int bx_, int by_, int gx_, 
   v4d acc[kSlots];
 #pragma unroll
   for (int q = 0; q < kSlots; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
-  // slab staging: each thread moves kPer values; element u of a thread has
-  // a fixed row, source (Z or K Z, at a fixed offset from the slab's first
-  // row) and LDS place, so only the row bound changes from slab to slab.
-  // Branch-free: an element outside the chunk or the super-tile is loaded
-  // from row 0 of the super-tile's columns of Z (a chunk may start past the
-  // last row) and stored as 0, and the zero is applied when the value goes
-  // to LDS, after the products, so that no wait on the loads precedes them.
-  constexpr int kPer = (kSlab * 2 * 16 * kSB + 255) / 256;
-  int goff[kPer], soff[kPer];
-  unsigned colok = 0, isk = 0;
+  // slab loads: load u of this wavefront moves 128 doubles of one part (Z
+  // for the first kSpLoads / 2 loads of the slab, K Z after) to LDS offset
+  // 128 g of that part, g its number within the part; lane l brings the
+  // two doubles at (row, col) = divmod(128 g + 2 l, kSpCols).  Columns past
+  // the super-tile's blocks repeat its last two columns (in bounds; no
+  // stored block reads them).
+  // Slab loads go through buffer resources whose base is the chunk's first
+  // row (of the super-tile's columns): the lane offsets (bytes from a slab's
+  // first row) stay fixed in their registers and the slab's offset is a
+  // scalar operand, so no register read by a load in flight is rewritten.
+  // Load u of this wavefront moves 128 doubles of one part (Z for the first
+  // kSpLoads / 2 loads of the slab, K Z after) to LDS offset 128 g of that
+  // part, g its number within the part; lane l brings the two doubles at
+  // (row, col) = divmod(128 g + 2 l, kSpCols).  Columns past the
+  // super-tile's blocks repeat its last two columns (no stored block reads
+  // them).
+  const long long pbytes = ((long long)rows + 4 * kSpSlab) * ld * 8;  // panel allocation
+  auto rsrc = [&](const double* panel, int colblk) {
+    const long long off = (r0 * ld + 16LL * colblk) * 8;
+    const long long left = pbytes - off;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(reinterpret_cast<const char*>(panel) + off),
+                                             (short)0, (int)min(left, 0x7fffffffLL), 0x00020000);
+  };
+  const __amdgpu_buffer_rsrc_t rz = rsrc(d.Zst, bi0), rk = rsrc(d.KZst, bj0);
+  int voff[kSpPerWave], loff[kSpPerWave];
+  bool pk[kSpPerWave];
 #pragma unroll
-  for (int u = 0; u < kPer; ++u) {
-    const int e = tid + 256 * u;
-    const int row = e / (2 * 16 * kSB), col = e % (2 * 16 * kSB);
-    const bool isz = col < 16 * kSB;
-    const int cc = isz ? col : col - 16 * kSB;
-    goff[u] = row * (int)ld + cc;
-    soff[u] = row * kSW + cc;
-    colok |= (cc < (isz ? ci : cj) ? 1u : 0u) << u;
-    isk |= (isz ? 0u : 1u) << u;
+  for (int u = 0; u < kSpPerWave; ++u) {
+    const int ti = wv * kSpPerWave + u, part = ti >= kSpLoads / 2, g = part ? ti - kSpLoads / 2 : ti;
+    const int e = 128 * g + 2 * lane, row = e / kSpCols, col = e % kSpCols;
+    const int lim = 16 * (part ? nj : ni);
+    pk[u] = part;
+    voff[u] = 8 * (row * (int)ld + min(col, lim - 2));
+    loff[u] = part * kSpPart + 128 * g;
   }
-  auto load = [&](long long rs, double* v) -> unsigned {
-    unsigned ok = 0;
-    const double* zb = Z + rs * ld;
-    const double* kzb = KZ + rs * ld;
-    const long long left = r1 - rs;  // rows of this slab inside the chunk
+  auto issue = [&](double* buf, int s) {
+    const int soff = s * kSpSlab * (int)ld * 8;
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-      const int row = (tid + 256 * u) / (2 * 16 * kSB);
-      const bool in = ((colok >> u) & 1u) && row < left;
-      ok |= (in ? 1u : 0u) << u;
-      v[u] = *(in ? ((isk >> u) & 1u ? kzb : zb) + goff[u] : Z);
-    }
-    return ok;
+    for (int u = 0; u < kSpPerWave; ++u)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(pk[u] ? rk : rz,
+                                               (__attribute__((address_space(3))) void*)(buf + loff[u]), 16,
+                                               voff[u], soff, 0, 0);
   };
-  auto store = [&](int buf, const double* v, unsigned ok) {
+  auto compute = [&](const double* buf) {
+    const double* za = buf;
+    const double* kb = buf + kSpPart;
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-      const double x = (ok >> u) & 1u ? v[u] : 0.0;
-      if ((isk >> u) & 1u) ks[buf][soff[u]] = x;
-      else zs[buf][soff[u]] = x;
-    }
-  };
-  static_assert(kPer * 256 == kSlab * 2 * 16 * kSB, "slab staging covers the slab exactly");
-  double v[kPer];
-  unsigned ok = load(r0, v);
-  store(0, v, ok);
-  __syncthreads();
-  int buf = 0;
-  for (long long rs = r0; rs < r1; rs += kSlab) {
-    const bool more = rs + kSlab < r1;
-    if (more) ok = load(rs + kSlab, v);
-    const double* za = zs[buf];
-    const double* kb = ks[buf];
-#pragma unroll
-    for (int k0 = 0; k0 < kSlab; k0 += 4) {
+    for (int k0 = 0; k0 < kSpSlab; k0 += 4) {
       double av[kSlots], bv[kSlots];
 #pragma unroll
       for (int q = 0; q < kSlots; ++q) {
-        av[q] = za[(k0 + lk) * kSW + 16 * ba[q] + lm];
-        bv[q] = kb[(k0 + lk) * kSW + 16 * bb[q] + lm];
+        av[q] = za[(k0 + lk) * kSpCols + 16 * ba[q] + lm];
+        bv[q] = kb[(k0 + lk) * kSpCols + 16 * bb[q] + lm];
       }
 #pragma unroll
       for (int q = 0; q < kSlots; ++q)
         acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[q], acc[q], 0, 0, 0);
     }
-    if (more) store(buf ^ 1, v, ok);
-    __syncthreads();
-    buf ^= 1;
+  };
+  // slab s sits in buffer s % 4; each step waits for its own loads of slab
+  // s (two later slabs' loads stay in flight), meets the others at the
+  // barrier (after which slab s - 1's buffer is free: every wavefront has
+  // consumed it), loads slab s + 3 into that buffer and multiplies slab s
+  auto step = [&](int s, double* cur, double* nxt) {
+    if (s < nsl) {
+      __builtin_amdgcn_s_waitcnt(kWaitVm2Slabs);
+      sp_barrier();
+      issue(nxt, s + 3);
+      compute(cur);
+    }
+  };
+  if (nsl > 0) {
+    issue(sp_buf0, 0);
+    issue(sp_buf1, 1);
+    issue(sp_buf2, 2);
+    for (int s0 = 0; s0 < nsl; s0 += 4) {
+      step(s0, sp_buf0, sp_buf3);
+      step(s0 + 1, sp_buf1, sp_buf0);
+      step(s0 + 2, sp_buf2, sp_buf1);
+      step(s0 + 3, sp_buf3, sp_buf2);
+    }
+    // the loads of the slabs past the last one land before the workgroup ends
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
   }
 #pragma unroll
   for (int q = 0; q < kSlots; ++q) {

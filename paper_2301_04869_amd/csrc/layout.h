@@ -36,6 +36,7 @@ constexpr int kRedThreads = 1024;  // reduction workgroup
 constexpr int kChainMax = 32;      // longest chain of single-row levels solved in registers
 constexpr int kGroupLds = 64;      // threads per scenario in the LDS-mode refactor / step
 constexpr int kKzItems = 2;        // K-row items per thread held in registers by the LDS-mode reduction
+constexpr int kSpSlab = 16;        // stacked rows per slab of the stacked product (chunks are whole slabs)
 
 __host__ __device__ inline int red_slots(const LdsSizes& z) { return kRedThreads / z.w; }
 

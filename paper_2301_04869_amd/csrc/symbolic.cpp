@@ -847,8 +847,8 @@ std::string build_symbolic(const rkkt_network& net, int N, const rkkt_options* o
     const long long tiles = T * (T + 1) / 2;
     long long nc = std::max(1LL, 256 / tiles);
     nc = std::min(nc, std::max(1LL, rows / 64));
-    // chunks of whole 32-row slabs; no chunk starts past the last row
-    const long long per = ((rows + nc - 1) / nc + 31) / 32 * 32;
+    // chunks of whole slabs; no chunk starts past the last row
+    const long long per = ((rows + nc - 1) / nc + kSpSlab - 1) / kSpSlab * kSpSlab;
     nc = (rows + per - 1) / per;
     s.nchunk = (int)nc;
   }

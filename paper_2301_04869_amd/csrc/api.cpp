@@ -216,6 +216,22 @@ int rkkt_create(const rkkt_network* net, int n_scen, const double* pd, const dou
   d.nph_u = s.stp_up.nphase;
   d.nph_d = s.stp_dn.nphase;
   d.n_kz = (int)(s.kz_items.size() / 4);
+  {
+    // condensed values: enough workgroups per scenario for about 512 in all
+    // (at most 16), each staging the scenario's sigma_s and H values and its
+    // share of the triplets; none when that exceeds 64 KiB of LDS
+    const int E = (int)s.k_col.size();
+    const int G = std::min(16, std::max(1, (512 + s.N - 1) / s.N));
+    const int per = (E + G - 1) / G;
+    int nt = 0;
+    for (int g = 0; g < G; ++g) {
+      const int e0 = std::min(E, g * per), e1 = std::min(E, e0 + per);
+      nt = std::max(nt, s.t_ptr[e1] - s.t_ptr[e0]);
+    }
+    const long long lds = 8LL * (s.m + (long long)s.h_col.size()) + 4LL * (per + 1 + 3LL * nt);
+    d.cv_split = lds <= 64 * 1024 ? G : 0;
+    d.cv_nt = nt;
+  }
   d.kz_rounds = s.kz_rounds;
   d.nph_ru = s.red_up.nphase;
   d.nph_rd = s.red_dn.nphase;

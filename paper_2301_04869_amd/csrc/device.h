@@ -43,6 +43,10 @@ struct DP {
   const int *k_ptr, *k_col, *k_diag, *k_usplit, *k_row;
   const int* kz_items;  // K-row pieces, four ints each (see Sym::kz_items)
   int n_kz, kz_rounds;
+  // condensed values with a scenario's sigma_s, H values and triplets in LDS:
+  // cv_split workgroups per scenario (0: one thread per value, no LDS), at
+  // most cv_nt triplets per workgroup
+  int cv_split, cv_nt;
   const int *w_ptr, *w_src, *wp_ptr, *wp_a, *wp_b;
   const double *wp_coef, *w_const;
   const int *t_ptr, *t_row, *t_a, *t_b;
@@ -218,7 +222,7 @@ enum : int {
   kKLineEvalGather = 1, kKLineEval, kKGatherEv, kKAssemble, kKLineHess, kKWGather, kKCondense,
   kKRefactor, kKReduce64, kKReduce, kKStepRhs2, kKStepRhs, kKStepRec2, kKStepRec,
   kKStacked, kKSymSum, kKCholSmall, kKCopyChol, kKSetInfo, kKCholDiag, kKCholTrsm, kKCholUpdate,
-  kKRSolveBlk, kKRSolve
+  kKRSolveBlk, kKRSolve, kKCondenseLds
 };
 enum : int {
   kStEvalValues = 0, kStEvalRest, kStCondense, kStRefactor, kStReduce, kStStepRhs, kStStacked,

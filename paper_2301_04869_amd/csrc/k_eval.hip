@@ -312,7 +312,83 @@ __device__ __forceinline__ void condense_values_body(const DP& d, int bx, const 
   d.K[t] = condense_value(d, k, e, d.W[t], d.EV + (long long)k * d.n_ev + d.off_h, sx, ss, dw);
 }
 
+// The same values with the work of a scenario in d.cv_split workgroups of
+// kCvT threads, each taking a contiguous range of the K entries: the
+// scenario's sigma_s and H values and the range's triplet lists are staged
+// in LDS first (all of their loads in flight together), so a value's terms
+// cost LDS reads instead of dependent global gathers.  The terms are added
+// in the same order as in condense_value.
+constexpr int kCvT = 256;
+
+__host__ __device__ inline long long cv_lds_bytes(const DP& d) {
+  const int per = (d.nnz_k + d.cv_split - 1) / d.cv_split;
+  return (8LL * (d.m + d.nnz_h) + 4LL * (per + 1 + 3LL * d.cv_nt) + 7) / 8 * 8;
+}
+
+__device__ __forceinline__ void condense_lds_body(const DP& d, int bx, const double* sx, const double* ss,
+                                                  double dw) {
+  const int G = d.cv_split, k = bx / G, g = bx % G, E = d.nnz_k;
+  const int per = (E + G - 1) / G, e0 = min(E, g * per), e1 = min(E, e0 + per), ne = e1 - e0;
+  const int tid = threadIdx.x;
+  extern __shared__ double smem[];
+  double* ssl = smem;
+  double* hvl = ssl + d.m;
+  int* tp = reinterpret_cast<int*>(hvl + d.nnz_h);
+  int* tr = tp + per + 1;
+  int* ta = tr + d.cv_nt;
+  int* tb = ta + d.cv_nt;
+  const int j0 = d.t_ptr[e0], nt = d.t_ptr[e1] - j0;
+  const double* hv = d.EV + (long long)k * d.n_ev + d.off_h;
+  const double* sk = ss + (long long)k * d.m;
+  {
+    constexpr int kB = 4;  // elements per thread and array in flight
+    const int nmax = max(max(d.m, d.nnz_h), max(ne + 1, nt));
+    for (int i0 = tid; i0 < nmax; i0 += kB * kCvT) {
+      double vs[kB], vh[kB];
+      int ip[kB], ir[kB], ia[kB], ib[kB];
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        const int i = i0 + u * kCvT;
+        if (i < d.m) vs[u] = sk[i];
+        if (i < d.nnz_h) vh[u] = hv[i];
+        if (i <= ne) ip[u] = d.t_ptr[e0 + i];
+        if (i < nt) {
+          ir[u] = d.t_row[j0 + i];
+          ia[u] = d.t_a[j0 + i];
+          ib[u] = d.t_b[j0 + i];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        const int i = i0 + u * kCvT;
+        if (i < d.m) ssl[i] = vs[u];
+        if (i < d.nnz_h) hvl[i] = vh[u];
+        if (i <= ne) tp[i] = ip[u] - j0;
+        if (i < nt) {
+          tr[i] = ir[u];
+          ta[i] = ia[u];
+          tb[i] = ib[u];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int e = e0 + tid; e < e1; e += kCvT) {
+    const long long o = (long long)k * E + e;
+    double acc = d.W[o];
+    const int r = d.k_row[e], cdiag = d.k_col[e];
+    const int ja = tp[e - e0], jb = tp[e - e0 + 1];
+    for (int j = ja; j < jb; ++j) acc += ssl[tr[j]] * hvl[ta[j]] * hvl[tb[j]];
+    if (r < d.nx && cdiag == r) acc += sx[(long long)k * d.nx + d.perm[r]] + dw;
+    if (!isfinite(acc)) atomicCAS(d.status, 0, RKKT_ERR_NONFINITE);
+    d.K[o] = acc;
+  }
+}
+
 // ---- entry points: one instance
+__global__ __launch_bounds__(kCvT) void k_condense_lds(DP d, const double* sx, const double* ss, double dw) {
+  condense_lds_body(d, blockIdx.x, sx, ss, dw);
+}
 __global__ __launch_bounds__(kLvT) void k_line_eval_gather(DP d, const double* x, const double* u) {
   line_eval_gather_body(d, blockIdx.x, x, u);
 }
@@ -367,6 +443,12 @@ __global__ void k_w_gather_m(const DP* __restrict__ dps, const rkkt_iteration* _
                              const MultiBlk* __restrict__ blk) {
   RKKT_MULTI_PROLOGUE
   w_gather_body(d, mb.bx, it.obj_weight);
+}
+__global__ __launch_bounds__(kCvT) void k_condense_lds_m(const DP* __restrict__ dps,
+                                                          const rkkt_iteration* __restrict__ its,
+                                                          const MultiBlk* __restrict__ blk) {
+  RKKT_MULTI_PROLOGUE
+  condense_lds_body(d, mb.bx, it.sigma_x, it.sigma_s, it.delta_w);
 }
 __global__ void k_condense_values_m(const DP* __restrict__ dps, const rkkt_iteration* __restrict__ its,
                                     const MultiBlk* __restrict__ blk) {
@@ -436,6 +518,10 @@ void launch_evaluate(const DP& d, const double* x, const double* u, const double
 
 void launch_condense_values(const DP& d, const double* sx, const double* ss, double dw,
                             hipStream_t s) {
+  if (d.cv_split > 0) {
+    k_condense_lds<<<d.N * d.cv_split, kCvT, (size_t)cv_lds_bytes(d), s>>>(d, sx, ss, dw);
+    return;
+  }
   long long nk = (long long)d.N * d.nnz_k;
   k_condense_values<<<grid_for(nk), kBlock, 0, s>>>(d, sx, ss, dw);
 }
@@ -455,7 +541,10 @@ void launches_eval(const DP& d, std::vector<Launch>& out) {
   add(kStEvalRest * 4096, kKAssemble, grid_for((long long)d.N * (2 * d.nx + d.m + d.nu + 1)), kBlock, 0);
   add(kStEvalRest * 4096 + 1, kKLineHess, grid_for((long long)d.N * d.nl), kBlock, 0);
   add(kStEvalRest * 4096 + 2, kKWGather, grid_for((long long)d.N * d.nnz_k), kBlock, 0);
-  add(kStCondense * 4096, kKCondense, grid_for((long long)d.N * d.nnz_k), kBlock, 0);
+  if (d.cv_split > 0)
+    add(kStCondense * 4096, kKCondenseLds, (long long)d.N * d.cv_split, kCvT, cv_lds_bytes(d));
+  else
+    add(kStCondense * 4096, kKCondense, grid_for((long long)d.N * d.nnz_k), kBlock, 0);
 }
 
 hipError_t multi_eval(const Launch& l, unsigned nblk, long long lds, const DP* dps, const rkkt_iteration* its,
@@ -477,6 +566,7 @@ hipError_t multi_eval(const Launch& l, unsigned nblk, long long lds, const DP* d
     case kKLineHess: k_line_hess_m<<<nblk, kBlock, 0, s>>>(dps, its, blk); break;
     case kKWGather: k_w_gather_m<<<nblk, kBlock, 0, s>>>(dps, its, blk); break;
     case kKCondense: k_condense_values_m<<<nblk, kBlock, 0, s>>>(dps, its, blk); break;
+    case kKCondenseLds: k_condense_lds_m<<<nblk, kCvT, (size_t)lds, s>>>(dps, its, blk); break;
     default: *handled = false;
   }
   return hipSuccess;

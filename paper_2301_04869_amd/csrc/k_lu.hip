@@ -431,38 +431,62 @@ __device__ __forceinline__ void chain_factor(const DP& d, double* lu, double* in
   const int t = d.chain_t, c0 = d.chain_c0;
   const int* __restrict__ P = d.chain_pos;
   const bool own = lane < t;
+  // every position load in flight before the first factor value is read
+  int pos[kChainMax];
+#pragma unroll
+  for (int b = 0; b < kChainMax; ++b) pos[b] = own && b < t ? P[lane * t + b] : -1;
   double row[kChainMax];
 #pragma unroll
-  for (int b = 0; b < kChainMax; ++b) {
-    const int pp = own && b < t ? P[lane * t + b] : -1;
-    row[b] = pp >= 0 ? lu[pp] : 0.0;
-  }
-#pragma unroll
-  for (int j = 0; j < kChainMax; ++j) {
-    if (j < t) {
-      const double ujj = readlane_d(row[j], j);
-      const double inv = 1.0 / ujj;
-      if (lane == j) {
-        if (!(fabs(ujj) > 0.0 && fabs(ujj) >= 1e-10 * rmax[c0 + j]) || !isfinite(ujj))
-          raise_status(d, RKKT_ERR_SINGULAR_GX, k);
-        invd[c0 + j] = inv;
-      }
-      double ub[kChainMax];
-#pragma unroll
-      for (int b = j + 1; b < kChainMax; ++b) ub[b] = readlane_d(row[b], j);
-      if (own && lane > j) {
+  for (int b = 0; b < kChainMax; ++b) row[b] = pos[b] >= 0 ? lu[pos[b]] : 0.0;
+  auto pivot = [&](int j, double ujj) {
+    const double inv = 1.0 / ujj;
+    if (lane == j) {
+      if (!(fabs(ujj) > 0.0 && fabs(ujj) >= 1e-10 * rmax[c0 + j]) || !isfinite(ujj))
+        raise_status(d, RKKT_ERR_SINGULAR_GX, k);
+      invd[c0 + j] = inv;
+    }
+    return inv;
+  };
+  if (t <= 16) {
+    // rows in lanes 0..15: row j's entries reach the other rows as DPP
+    // broadcasts of lane j within the row of 16 lanes, and only the columns
+    // of the chain are touched
+    auto elim = [&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      if (j < t) {
+        const double inv = pivot(j, row_bcast<j>(row[j]));
         const double l = row[j] * inv;
-        row[j] = l;
+        const bool upd = own && lane > j;
+        if (upd) row[j] = l;
 #pragma unroll
-        for (int b = j + 1; b < kChainMax; ++b) row[b] = fma(-l, ub[b], row[b]);
+        for (int b = j + 1; b < 16; ++b)
+          if (b < t) {
+            const double ub = row_bcast<j>(row[b]);
+            if (upd) row[b] = fma(-l, ub, row[b]);
+          }
+      }
+    };
+    for_each_const(elim, std::make_integer_sequence<int, 16>{});
+  } else {
+#pragma unroll
+    for (int j = 0; j < kChainMax; ++j) {
+      if (j < t) {
+        const double inv = pivot(j, readlane_d(row[j], j));
+        const double l = row[j] * inv;
+        const bool upd = own && lane > j;
+        if (upd) row[j] = l;
+#pragma unroll
+        for (int b = j + 1; b < kChainMax; ++b)
+          if (b < t) {
+            const double ub = readlane_d(row[b], j);
+            if (upd) row[b] = fma(-l, ub, row[b]);
+          }
       }
     }
   }
 #pragma unroll
-  for (int b = 0; b < kChainMax; ++b) {
-    const int pp = own && b < t ? P[lane * t + b] : -1;
-    if (pp >= 0) lu[pp] = row[b];
-  }
+  for (int b = 0; b < kChainMax; ++b)
+    if (pos[b] >= 0) lu[pos[b]] = row[b];
 }
 
 // ------------------------------------------------------------ refactorisation

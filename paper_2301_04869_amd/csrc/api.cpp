@@ -265,7 +265,10 @@ int rkkt_create(const rkkt_network* net, int n_scen, const double* pd, const dou
   }
   d.aref = ca[s.gref];
   d.bref = cb[s.gref];
-  std::vector<int> load_of_bus(s.nb, -1), grow_bus(s.nx), gen_u(s.ng, -1), k_row(s.k_col.size());
+  std::vector<int> load_of_bus(s.nb, -1), grow_bus(s.nx), gen_u(s.ng, -1), k_row(s.k_col.size()),
+      gx_row(s.gx_col.size());
+  for (int i = 0; i < s.nx; ++i)
+    for (int q = s.gx_ptr[i]; q < s.gx_ptr[i + 1]; ++q) gx_row[q] = i;
   for (int j = 0; j < s.nload; ++j) load_of_bus[net->load_bus[j]] = j;
   for (int b = 0; b < s.nb; ++b) {
     if (s.prow[b] >= 0) grow_bus[s.prow[b]] = b;
@@ -291,7 +294,7 @@ int rkkt_create(const rkkt_network* net, int n_scen, const double* pd, const dou
   UP(ht_pos, s.ht_pos) UP(h0pos, s.h0pos)
   UP(k_ptr, s.k_ptr) UP(k_col, s.k_col) UP(k_diag, s.k_diag) UP(k_usplit, s.k_usplit)
   UP(kz_items, s.kz_items)
-  UP(k_row, k_row)
+  UP(k_row, k_row) UP(gx_row, gx_row)
   UP(w_ptr, s.w_ptr) UP(w_src, s.w_src) UP(wp_ptr, s.wp_ptr) UP(wp_a, s.wp_a) UP(wp_b, s.wp_b)
   UP(wp_coef, s.wp_coef) UP(w_const, s.w_const)
   UP(t_ptr, s.t_ptr) UP(t_row, s.t_row) UP(t_a, s.t_a) UP(t_b, s.t_b)

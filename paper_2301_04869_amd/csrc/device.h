@@ -37,7 +37,7 @@ struct DP {
   // gathers
   const int *ev_ptr, *ev_src;
   const double *ev_const;
-  const int *gx_ptr, *gx_col, *gxc_ptr, *gxc_row, *gxc_pos;
+  const int *gx_ptr, *gx_col, *gx_row, *gxc_ptr, *gxc_row, *gxc_pos;
   const int *gu_ptr, *gu_col, *guc_ptr, *guc_row, *guc_pos;
   const int *h_ptr, *h_col, *ht_ptr, *ht_row, *ht_pos, *h0pos;
   const int *k_ptr, *k_col, *k_diag, *k_usplit, *k_row;

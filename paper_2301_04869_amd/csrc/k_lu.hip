@@ -537,19 +537,47 @@ __device__ __forceinline__ void refactor_body(const DP& d, int bx_, int by_, int
   if (live) {
     const double* gv = d.EV + (long long)k * d.n_ev + d.off_gx;
     for (int e = gl; e < nf; e += G) lu[e] = 0.0;
+    if (kLDS)
+      for (int i = gl; i < nx; i += G) rmax[i] = 0.0;
     gsync();
-    scatter_overlapped(lu, d.gx2f, gv, d.nnz_gx, gl, G);
+    if (kLDS) {
+      // the values land in the filled pattern, and the largest |entry| of
+      // every row of G_x builds up by LDS atomic maxima on the bits of
+      // |value| (non-negative doubles order as their bit patterns)
+      for (int e0 = gl; e0 < d.nnz_gx; e0 += kStageBatch * G) {
+        int id[kStageBatch], row[kStageBatch];
+        double v[kStageBatch];
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+          const int e = e0 + u * G;
+          id[u] = e < d.nnz_gx ? d.gx2f[e] : -1;
+          row[u] = e < d.nnz_gx ? d.gx_row[e] : 0;
+          v[u] = e < d.nnz_gx ? gv[e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u)
+          if (id[u] >= 0) {
+            lu[id[u]] = v[u];
+            atomicMax(reinterpret_cast<unsigned long long*>(rmax + row[u]),
+                      (unsigned long long)__double_as_longlong(fabs(v[u])));
+          }
+      }
+    } else {
+      scatter_overlapped(lu, d.gx2f, gv, d.nnz_gx, gl, G);
+    }
   }
   __syncthreads();
   if (!live) return;
-  // largest |entry| of every row of G_x (fill positions hold zeros)
-  for (int i = gl; i < nx; i += G) {
-    double mx = 0.0;
-    const int e1 = f_ptr[i + 1];
-    for (int e = f_ptr[i]; e < e1; ++e) mx = fmax(mx, fabs(lu[e]));
-    rmax[i] = mx;
+  if (!kLDS) {
+    // largest |entry| of every row of G_x (fill positions hold zeros)
+    for (int i = gl; i < nx; i += G) {
+      double mx = 0.0;
+      const int e1 = f_ptr[i + 1];
+      for (int e = f_ptr[i]; e < e1; ++e) mx = fmax(mx, fabs(lu[e]));
+      rmax[i] = mx;
+    }
+    gsync();
   }
-  gsync();
   for (int q = 0; q < d.nph_u; ++q) {
     {
       const int e1 = ptr[q * G + gl + 1];

@@ -527,16 +527,23 @@ def main():
     for _ in range(args.warmup):
         R.rkkt_graph_launch(p, stream)
     torch.cuda.synchronize()
-    # an event between every two replays (recording one adds no dependency)
+    e0.record(stream)
+    for _ in range(args.steps):
+        R.rkkt_graph_launch(p, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    graph_ms = e0.elapsed_time(e1) / args.steps
+    progress(f"graph replays timed: {graph_ms:.3f} ms per pass")
+    # the spread of single replays: the same number again with an event
+    # between every two (the markers add a little to each, so these are not
+    # the timed value)
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     evs[0].record(stream)
     for i in range(args.steps):
         R.rkkt_graph_launch(p, stream)
         evs[i + 1].record(stream)
     torch.cuda.synchronize()
-    graph_ms = evs[0].elapsed_time(evs[-1]) / args.steps
     per_replay = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
-    progress(f"graph replays timed: {graph_ms:.3f} ms per pass")
     ms = min(graph_ms, eager_ms)
     value = N / (ms * 1e-3)
     cf_ms = sum(stages[s][0] for s in ("condense_values", "refactor", "reduce", "stacked_product",

@@ -357,10 +357,9 @@ int rkkt_create(const rkkt_network* net, int n_scen, const double* pd, const dou
     const int ntile = (s.nu + s.col_tile - 1) / s.col_tile;
     size_t panel = d.lds_stp ? 1 : 2 * N * (size_t)s.nx;
     if (!d.lds_red && d.variant == 1) panel = std::max(panel, N * ntile * 2 * (size_t)s.nx * s.col_tile);
-    // stacked panels: N n_z rows, then four slabs of zero rows that the
-    // stacked product's last chunk reads past the last row (its pipeline
-    // loads up to three slabs beyond its last one)
-    const size_t stacked = d.variant == 2 ? (N * (size_t)s.nz + 4 * rkkt::kSpSlab) * s.nu_pad : 1;
+    // stacked panels: N n_z rows, then a slab of zero rows that the stacked
+    // product's last chunk reads past the last row
+    const size_t stacked = d.variant == 2 ? (N * (size_t)s.nz + rkkt::kSpSlab) * s.nu_pad : 1;
     if ((e = dalloc(p, &d.pdb, N * s.nb)) != hipSuccess) goto hip_error;
     if ((e = dalloc(p, &d.lstat, N * s.nl)) != hipSuccess) goto hip_error;
     if ((e = dalloc(p, &d.qdb, N * s.nb)) != hipSuccess) goto hip_error;

@@ -93,9 +93,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // lane holds Z[rho + lane/16][i + lane%16]; B operand: (K Z)[rho +
 // lane/16][j + lane%16]; result register r of a lane: row lane/16 + 4 r,
 // column lane%16).  Chunks are whole slabs except the last, whose rows past
-// the last stacked row are zero rows of the panels (four slabs of them, as
-// the pipeline loads up to three slabs past a chunk's last one; those slabs
-// are not multiplied), so they add nothing.
+// the last stacked row are zero rows of the panels, so they add nothing.
 constexpr int kSB = 7;                        // blocks per super-tile side
 constexpr int kSBMax = (kSB * kSB + 3) / 4;   // blocks per wavefront, at most
 constexpr int kSpCols = 16 * kSB;             // columns of a slab part (Z or K Z), LDS row pitch
@@ -113,7 +111,8 @@ __host__ __device__ inline long long sp_rows_per_chunk(long long rows, int nchun
 
 __shared__ double sp_buf0[2 * kSpPart], sp_buf1[2 * kSpPart], sp_buf2[2 * kSpPart], sp_buf3[2 * kSpPart];
 
-// s_waitcnt immediates (vmcnt in bits 3:0, expcnt and lgkmcnt at their maxima)
+// s_waitcnt immediates (vmcnt in bits 3:0, expcnt and lgkmcnt at their
+// maxima): all but the loads of the last two slabs, or all
 constexpr int kWaitVm2Slabs = 0x0F70 | (2 * kSpPerWave);
 constexpr int kWaitVm0 = 0x0F70;
 static_assert(2 * kSpPerWave < 16, "vmcnt wait fits the low field");
@@ -183,7 +182,7 @@ __device__ __forceinline__ void stacked_product_body(int bx_, int by_, int gx_, 
   // (row, col) = divmod(128 g + 2 l, kSpCols).  Columns past the
   // super-tile's blocks repeat its last two columns (no stored block reads
   // them).
-  const long long pbytes = ((long long)rows + 4 * kSpSlab) * ld * 8;  // panel allocation
+  const long long pbytes = ((long long)rows + kSpSlab) * ld * 8;  // panel allocation
   auto rsrc = [&](const double* panel, int colblk) {
     const long long off = (r0 * ld + 16LL * colblk) * 8;
     const long long left = pbytes - off;
@@ -191,6 +190,11 @@ __device__ __forceinline__ void stacked_product_body(int bx_, int by_, int gx_, 
                                              (short)0, (int)min(left, 0x7fffffffLL), 0x00020000);
   };
   const __amdgpu_buffer_rsrc_t rz = rsrc(d.Zst, bi0), rk = rsrc(d.KZst, bj0);
+  // a resource with no records: loads through it return zeros without
+  // touching memory (the slabs past the chunk's last one, which keep the
+  // pipeline's wait counts uniform and are never multiplied)
+  const __amdgpu_buffer_rsrc_t rnone = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<double*>(d.Zst), (short)0, 0, 0x00020000);
   int voff[kSpPerWave], loff[kSpPerWave];
   bool pk[kSpPerWave];
 #pragma unroll
@@ -204,9 +208,10 @@ __device__ __forceinline__ void stacked_product_body(int bx_, int by_, int gx_, 
   }
   auto issue = [&](double* buf, int s) {
     const int soff = s * kSpSlab * (int)ld * 8;
+    const bool real = s < nsl;
 #pragma unroll
     for (int u = 0; u < kSpPerWave; ++u)
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(pk[u] ? rk : rz,
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(real ? (pk[u] ? rk : rz) : rnone,
                                                (__attribute__((address_space(3))) void*)(buf + loff[u]), 16,
                                                voff[u], soff, 0, 0);
   };

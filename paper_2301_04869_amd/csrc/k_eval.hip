@@ -86,8 +86,19 @@ __device__ inline void line_eval_one(const DP& d, int k, int l, const double* x,
 // one bus injection or Jacobian value on the fixed patterns; lv = the
 // scenario's line values
 __device__ inline double gather_ev_one(const DP& d, int e, const double* lv) {
+  // terms added in list order, the source indices of kEb terms loaded
+  // together before their values are read
+  constexpr int kEb = 4;
+  const int j0 = d.ev_ptr[e], j1 = d.ev_ptr[e + 1];
   double acc = d.ev_const[e];
-  for (int j = d.ev_ptr[e]; j < d.ev_ptr[e + 1]; ++j) acc += lv[d.ev_src[j]];
+  for (int j = j0; j < j1; j += kEb) {
+    int src[kEb];
+#pragma unroll
+    for (int q = 0; q < kEb; ++q) src[q] = d.ev_src[min(j + q, j1 - 1)];
+#pragma unroll
+    for (int q = 0; q < kEb; ++q)
+      if (j + q < j1) acc += lv[src[q]];
+  }
   return acc;
 }
 
@@ -149,11 +160,24 @@ __device__ inline void assemble_one(const DP& d, int k, int i, const double* u, 
     gu[(long long)k * d.nu + i] = v;
     return;
   }
+  // one thread per scenario sums the generator costs in generator order;
+  // the loads of kFb generators are issued before their terms are added
+  constexpr int kFb = 8;
   double acc = 0.0;
-  for (int gg = 0; gg < d.ng; ++gg) {
-    int ui = d.gen_u[gg];
-    double pg = ui >= 0 ? u[ui] : pref;
-    acc += d.ca[gg] * pg * pg + d.cb[gg] * pg + d.cc[gg];
+  for (int g0 = 0; g0 < d.ng; g0 += kFb) {
+    double pg[kFb], a[kFb], b[kFb], c[kFb];
+#pragma unroll
+    for (int q = 0; q < kFb; ++q) {
+      const int gg = min(g0 + q, d.ng - 1);
+      const int ui = d.gen_u[gg];
+      pg[q] = ui >= 0 ? u[ui] : pref;
+      a[q] = d.ca[gg];
+      b[q] = d.cb[gg];
+      c[q] = d.cc[gg];
+    }
+#pragma unroll
+    for (int q = 0; q < kFb; ++q)
+      if (g0 + q < d.ng) acc += a[q] * pg[q] * pg[q] + b[q] * pg[q] + c[q];
   }
   f[k] = w * acc;
 }
@@ -215,10 +239,34 @@ __device__ inline void line_hess_one(const DP& d, int k, int l, const double* x,
 // scenario's line Hessians, hv = its Jacobian values of h
 __device__ inline double w_gather_one(const DP& d, int e, double w, const double* lh,
                                       const double* hv) {
+  // terms added in list order; the loads of kWb terms are issued before
+  // they are added, so a long list costs one round of dependent loads per
+  // kWb terms instead of one per term
+  constexpr int kWb = 4;
+  const int w0 = d.w_ptr[e], w1 = d.w_ptr[e + 1], p0 = d.wp_ptr[e], p1 = d.wp_ptr[e + 1];
   double acc = 0.0;
-  for (int j = d.w_ptr[e]; j < d.w_ptr[e + 1]; ++j) acc += lh[d.w_src[j]];
+  for (int j = w0; j < w1; j += kWb) {
+    double v[kWb];
+#pragma unroll
+    for (int q = 0; q < kWb; ++q) v[q] = lh[d.w_src[min(j + q, w1 - 1)]];
+#pragma unroll
+    for (int q = 0; q < kWb; ++q)
+      if (j + q < w1) acc += v[q];
+  }
   double prod = d.w_const[e];
-  for (int j = d.wp_ptr[e]; j < d.wp_ptr[e + 1]; ++j) prod += d.wp_coef[j] * hv[d.wp_a[j]] * hv[d.wp_b[j]];
+  for (int j = p0; j < p1; j += kWb) {
+    double cf[kWb], va[kWb], vb[kWb];
+#pragma unroll
+    for (int q = 0; q < kWb; ++q) {
+      const int jj = min(j + q, p1 - 1);
+      cf[q] = d.wp_coef[jj];
+      va[q] = hv[d.wp_a[jj]];
+      vb[q] = hv[d.wp_b[jj]];
+    }
+#pragma unroll
+    for (int q = 0; q < kWb; ++q)
+      if (j + q < p1) prod += cf[q] * va[q] * vb[q];
+  }
   return acc + w * prod;
 }
 

@@ -174,36 +174,48 @@ __device__ __forceinline__ void sweep(const int* __restrict__ ptr, const void* e
 // One sweep for a single right-hand side by one wavefront in LDS (lane =
 // slot of kGroupLds), fewest instructions per phase: a phase whose slots hold
 // at most one entry each (most phases of these schedules) is one guarded
-// multiply-add per lane; longer slots run their entries in order.  The bound
-// and first entry of the next phase are loaded while the current one runs.
+// multiply-add per lane; longer slots run their entries in order.  Each phase
+// first issues its own operand reads (from the entry already in registers),
+// then the reads of the next phase's first entry and slot maximum and of the
+// slot extent two phases ahead, so one LDS round trip per phase is exposed;
+// a lane without an entry reads through the schedule's first entry and
+// stores nothing.  The wavefront's LDS operations complete in issue order,
+// so a phase's reads see the previous phase's stores.
 template <bool kTrans, typename Sync>
 __device__ __forceinline__ void sweep_w(const int* ptr, const uint2* ent, const int* phmax, int nphase,
                                         int slot, const double* lu, double* X, Sync sync) {
   auto pos = [](uint2 v) { return (int)(kTrans ? v.y >> 16 : v.y & 0xffffu); };
   auto dst = [](uint2 v) { return (int)(v.x & 0xffffu); };
   auto src = [](uint2 v) { return (int)(v.x >> 16); };
-  int e0 = 0, n = 0;
+  // phase q: extent (e0, n), first entry t, slot maximum m; phase q + 1: the
+  // extent's ends (e1, b1) as read
+  int e0 = 0, n = 0, m = 0, e1 = 0, b1 = 0;
   uint2 t = make_uint2(0u, 0u);
   if (nphase > 0) {
     e0 = ptr[slot];
     n = ptr[slot + 1] - e0;
     t = ent[n > 0 ? e0 : 0];
+    m = phmax[0];
+  }
+  // reads past the last phase take the last phase's (valid) data, unused
+  if (nphase > 0) {
+    const int q1 = min(1, nphase - 1);
+    e1 = ptr[q1 * kGroupLds + slot];
+    b1 = ptr[q1 * kGroupLds + slot + 1];
   }
   for (int q = 0; q < nphase; ++q) {
-    const int m = __builtin_amdgcn_readfirstlane(phmax[q]);
-    int e0n = 0, nn = 0;
-    uint2 tn = make_uint2(0u, 0u);
-    if (q + 1 < nphase) {
-      e0n = ptr[(q + 1) * kGroupLds + slot];
-      nn = ptr[(q + 1) * kGroupLds + slot + 1] - e0n;
-      tn = ent[nn > 0 ? e0n : 0];
-    }
+    const int mq = __builtin_amdgcn_readfirstlane(m);
+    const double a = lu[pos(t)], xs = X[src(t)], xd = X[dst(t)];
+    const int n1 = b1 - e1, q1 = min(q + 1, nphase - 1), q2 = min(q + 2, nphase - 1);
+    const uint2 t1 = ent[n1 > 0 ? e1 : 0];
+    const int m1 = phmax[q1];
+    const int e2 = ptr[q2 * kGroupLds + slot], b2 = ptr[q2 * kGroupLds + slot + 1];
     if (n > 0) {
-      if (m <= 1) {
-        X[dst(t)] = fma(-lu[pos(t)], X[src(t)], X[dst(t)]);
+      if (mq <= 1) {
+        X[dst(t)] = fma(-a, xs, xd);
       } else {
         int cur = dst(t);
-        double acc = fma(-lu[pos(t)], X[src(t)], X[cur]);
+        double acc = fma(-a, xs, xd);
         for (int u = 1; u < n; ++u) {
           const uint2 v = ent[e0 + u];
           if (dst(v) != cur) {
@@ -217,9 +229,12 @@ __device__ __forceinline__ void sweep_w(const int* ptr, const uint2* ent, const 
       }
     }
     sync();
-    e0 = e0n;
-    n = nn;
-    t = tn;
+    e0 = e1;
+    n = n1;
+    t = t1;
+    m = m1;
+    e1 = e2;
+    b1 = b2;
   }
 }
 
@@ -1550,6 +1565,10 @@ __device__ __forceinline__ StepView sweep_view(const DP& d, double* lu, unsigned
 // keeps kTtRows loads of its column in flight.
 constexpr int kTtRows = 8;
 
+// entries of a sparse row (K, or H^T) whose loads the step kernels issue
+// together before adding their terms in row order
+constexpr int kRowBatch = 8;
+
 template <int kT>
 __device__ __forceinline__ void dense_tt_times(const DP& d, const double* __restrict__ Zk,
                                                const double* b, double* red) {
@@ -1615,9 +1634,17 @@ __device__ __forceinline__ void step_rhs2_body(const DP& d, int bx_, int by_, in
     for (int v = tid - 64; v < nx + nu; v += kT - 64) {
       double acc = v < nx ? r1k[d.perm[v]] : 0.0;
       const int j1 = d.ht_ptr[v + 1];
-      for (int j = d.ht_ptr[v]; j < j1; ++j) {
-        const int r = d.ht_row[j];
-        acc = fma(hv[d.ht_pos[j]], ssk[r] * r4k[r] - r2k[r], acc);
+      for (int j = d.ht_ptr[v]; j < j1; j += kRowBatch) {
+        double hj[kRowBatch], wj[kRowBatch];
+#pragma unroll
+        for (int u = 0; u < kRowBatch; ++u) {
+          const int jj = min(j + u, j1 - 1), r = d.ht_row[jj];
+          hj[u] = hv[d.ht_pos[jj]];
+          wj[u] = ssk[r] * r4k[r] - r2k[r];
+        }
+#pragma unroll
+        for (int u = 0; u < kRowBatch; ++u)
+          if (j + u < j1) acc = fma(hj[u], wj[u], acc);
       }
       if (v < nx) b[v] = acc;
       else part[v - nx] = -acc;
@@ -1634,7 +1661,19 @@ __device__ __forceinline__ void step_rhs2_body(const DP& d, int bx_, int by_, in
     gq[i] = q[i];
     double acc = rh;
     const int e1 = d.k_usplit[i];
-    for (int e = d.k_ptr[i]; e < e1; ++e) acc = fma(-Kk[e], q[d.k_col[e]], acc);
+    for (int e = d.k_ptr[i]; e < e1; e += kRowBatch) {
+      double kv[kRowBatch];
+      int kc[kRowBatch];
+#pragma unroll
+      for (int u = 0; u < kRowBatch; ++u) {
+        const int ee = min(e + u, e1 - 1);
+        kv[u] = Kk[ee];
+        kc[u] = d.k_col[ee];
+      }
+#pragma unroll
+      for (int u = 0; u < kRowBatch; ++u)
+        if (e + u < e1) acc = fma(-kv[u], q[kc[u]], acc);
+    }
     b[i] = acc;
   }
   __syncthreads();
@@ -1645,7 +1684,19 @@ __device__ __forceinline__ void step_rhs2_body(const DP& d, int bx_, int by_, in
     const int v = nx + c;
     double acc = part[c];
     const int e1 = d.k_usplit[v];
-    for (int e = d.k_ptr[v]; e < e1; ++e) acc = fma(Kk[e], q[d.k_col[e]], acc);
+    for (int e = d.k_ptr[v]; e < e1; e += kRowBatch) {
+      double kv[kRowBatch];
+      int kc[kRowBatch];
+#pragma unroll
+      for (int u = 0; u < kRowBatch; ++u) {
+        const int ee = min(e + u, e1 - 1);
+        kv[u] = Kk[ee];
+        kc[u] = d.k_col[ee];
+      }
+#pragma unroll
+      for (int u = 0; u < kRowBatch; ++u)
+        if (e + u < e1) acc = fma(kv[u], q[kc[u]], acc);
+    }
     double tb = 0.0;
     for (int s = 0; s < ns; ++s) tb += red[s * nu + c];
     d.rpart[(long long)k * nu + c] = acc - tb;
@@ -1763,9 +1814,18 @@ __device__ __forceinline__ void step_recover2_body(const DP& d, int bx_, int by_
       e = d.k_ptr[i];
       e1 = d.k_ptr[i + 1];
     }
-    for (; e < e1; ++e) {
-      const int cc = d.k_col[e];
-      acc = fma(Kk[e], cc < nx ? xv[cc] : spu[cc - nx], acc);
+    for (; e < e1; e += kRowBatch) {
+      double kv2[kRowBatch];
+      int kc2[kRowBatch];
+#pragma unroll
+      for (int u = 0; u < kRowBatch; ++u) {
+        const int ee = min(e + u, e1 - 1);
+        kv2[u] = Kk[ee];
+        kc2[u] = d.k_col[ee];
+      }
+#pragma unroll
+      for (int u = 0; u < kRowBatch; ++u)
+        if (e + u < e1) acc = fma(kv2[u], kc2[u] < nx ? xv[kc2[u]] : spu[kc2[u] - nx], acc);
     }
     yv[i] = -acc * invd[i];
   }

@@ -102,10 +102,10 @@ __device__ inline double gather_ev_one(const DP& d, int e, const double* lv) {
   return acc;
 }
 
-// one entry of g, h, the gradient of f, or f itself (item i of
-// 2 nx + m + nu + 1); ev, lv = the scenario's values
+// one entry of g, h or the gradient of f (item i of 2 nx + m + nu); ev,
+// lv = the scenario's values
 __device__ inline void assemble_one(const DP& d, int k, int i, const double* u, double w,
-                                    double* f, double* gx, double* gu, double* g, double* h,
+                                    double* gx, double* gu, double* g, double* h,
                                     const double* ev, const double* lv) {
   const double* pdb = d.pdb + (long long)k * d.nb;
   const double* qdb = d.qdb + (long long)k * d.nb;
@@ -158,29 +158,32 @@ __device__ inline void assemble_one(const DP& d, int k, int i, const double* u, 
       v = w * (2.0 * d.ca[gg] * u[i] + d.cb[gg]);
     }
     gu[(long long)k * d.nu + i] = v;
-    return;
   }
-  // one thread per scenario sums the generator costs in generator order;
-  // the loads of kFb generators are issued before their terms are added
-  constexpr int kFb = 8;
-  double acc = 0.0;
-  for (int g0 = 0; g0 < d.ng; g0 += kFb) {
-    double pg[kFb], a[kFb], b[kFb], c[kFb];
-#pragma unroll
-    for (int q = 0; q < kFb; ++q) {
-      const int gg = min(g0 + q, d.ng - 1);
-      const int ui = d.gen_u[gg];
-      pg[q] = ui >= 0 ? u[ui] : pref;
-      a[q] = d.ca[gg];
-      b[q] = d.cb[gg];
-      c[q] = d.cc[gg];
-    }
-#pragma unroll
-    for (int q = 0; q < kFb; ++q)
-      if (g0 + q < d.ng) acc += a[q] * pg[q] * pg[q] + b[q] * pg[q] + c[q];
-  }
-  f[k] = w * acc;
 }
+
+// the objective f of scenario k by one wavefront: lane j adds the costs of
+// generators j, j + 64, ... in order, then the 64 partial sums meet in a
+// fixed butterfly, so the result does not depend on the run
+__device__ inline void objective_wave(const DP& d, int k, int lane, const double* u, double w, double* f) {
+  const double pref = d.EV[(long long)k * d.n_ev + d.off_P + d.ref] + d.pdb[(long long)k * d.nb + d.ref];
+  double acc = 0.0;
+  for (int gg = lane; gg < d.ng; gg += 64) {
+    const int ui = d.gen_u[gg];
+    const double pg = ui >= 0 ? u[ui] : pref;
+    acc += d.ca[gg] * pg * pg + d.cb[gg] * pg + d.cc[gg];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (lane == 0) f[k] = w * acc;
+}
+
+// threads of k_assemble: one per entry of g, h and the gradients (2 nx + m +
+// nu per scenario), then, from the next wavefront boundary, one wavefront per
+// scenario for f
+__host__ __device__ inline long long assemble_f_base(const DP& d) {
+  return ((long long)d.N * (2 * d.nx + d.m + d.nu) + 63) / 64 * 64;
+}
+__host__ __device__ inline long long assemble_threads(const DP& d) { return assemble_f_base(d) + 64LL * d.N; }
 
 // a3: local 4x4 Hessian of line l's share of f + y^T g + z^T h; le = the
 // line's 28 values, o = its 10 Hessian values
@@ -314,11 +317,17 @@ __device__ __forceinline__ void gather_ev_body(const DP& d, int bx) {
 
 __device__ __forceinline__ void assemble_body(const DP& d, int bx, const double* u, double w, double* f,
                                               double* gx, double* gu, double* g, double* h) {
-  const int per = 2 * d.nx + d.m + d.nu + 1;
+  const int per = 2 * d.nx + d.m + d.nu;
   long long t = (long long)bx * blockDim.x + threadIdx.x;
+  const long long fb = assemble_f_base(d);
+  if (t >= fb) {  // whole wavefronts (fb and the block size are multiples of 64)
+    const long long r = t - fb;
+    if (r < 64LL * d.N) objective_wave(d, (int)(r >> 6), (int)(r & 63), u, w, f);
+    return;
+  }
   if (t >= (long long)d.N * per) return;
   int k = (int)(t / per), i = (int)(t % per);
-  assemble_one(d, k, i, u, w, f, gx, gu, g, h, d.EV + (long long)k * d.n_ev,
+  assemble_one(d, k, i, u, w, gx, gu, g, h, d.EV + (long long)k * d.n_ev,
                d.LV + (long long)k * d.nl * kLVsize);
 }
 
@@ -549,8 +558,7 @@ void launch_evaluate_values(const DP& d, const double* x, const double* u, hipSt
 void launch_evaluate_rest(const DP& d, const double* x, const double* u, const double* y,
                           const double* z, double w, double* f, double* gx, double* gu, double* g,
                           double* h, hipStream_t s) {
-  long long na = (long long)d.N * (2 * d.nx + d.m + d.nu + 1);
-  k_assemble<<<grid_for(na), kBlock, 0, s>>>(d, u, w, f, gx, gu, g, h);
+  k_assemble<<<grid_for(assemble_threads(d)), kBlock, 0, s>>>(d, u, w, f, gx, gu, g, h);
   long long nl = (long long)d.N * d.nl;
   k_line_hess<<<grid_for(nl), kBlock, 0, s>>>(d, x, u, y, z, w);
   long long nk = (long long)d.N * d.nnz_k;
@@ -586,7 +594,7 @@ void launches_eval(const DP& d, std::vector<Launch>& out) {
     add(kStEvalValues * 4096, kKLineEval, grid_for((long long)d.N * d.nl), kBlock, 0);
     add(kStEvalValues * 4096 + 1, kKGatherEv, grid_for((long long)d.N * d.n_ev), kBlock, 0);
   }
-  add(kStEvalRest * 4096, kKAssemble, grid_for((long long)d.N * (2 * d.nx + d.m + d.nu + 1)), kBlock, 0);
+  add(kStEvalRest * 4096, kKAssemble, grid_for(assemble_threads(d)), kBlock, 0);
   add(kStEvalRest * 4096 + 1, kKLineHess, grid_for((long long)d.N * d.nl), kBlock, 0);
   add(kStEvalRest * 4096 + 2, kKWGather, grid_for((long long)d.N * d.nnz_k), kBlock, 0);
   if (d.cv_split > 0)

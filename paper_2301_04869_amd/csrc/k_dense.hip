@@ -20,20 +20,28 @@ __global__ void k_set_int(int* p, int v) { *p = v; }
 // K_hat = sum_c src_c + diag(sigma_u) + delta_w I over `cnt` n_u x n_u
 // matrices (the scenario contributions, or the chunk partials of the stacked
 // product), lower triangle, mirrored into the upper one so K_hat is exactly
-// symmetric.  A workgroup owns 64 entries of the lower triangle (row-major
-// order); its 8 wavefronts each sum a contiguous eighth of the matrices in
-// index order and the eight partial sums are added in wavefront order, so the
-// result does not depend on scheduling.
+// symmetric.  A workgroup of kE * kW threads owns kE entries of the lower
+// triangle (row-major order); its kW groups of kE threads each sum a
+// contiguous share of the matrices in index order, and the kW partial sums
+// are added in a fixed order (in groups of eight first when kW > 16), so the
+// result does not depend on scheduling.  Few matrices (the scenario
+// contributions): 64 entries x 16 groups; many (the 256 chunk partials): 16
+// entries x 64 groups, so that four times as many workgroups share the reads.
 constexpr int kSumEntries = 64, kSumWaves = 16;
+constexpr int kSumEntriesMany = 16, kSumWavesMany = 64;
+constexpr int kSumManyFrom = 128;  // matrices from which the second shape is used
 
-__device__ __forceinline__ void sym_sum_body(int bx_, int by_, int gx_, const DP& d, const double* src, int cnt,
-                                                                      const double* su, double dw,
-                                                                      double* khat) {
-  __shared__ double part[kSumWaves][kSumEntries];
+template <int kE, int kW>
+__device__ __forceinline__ void sym_sum_body(int bx_, const DP& d, const double* src, int cnt, const double* su,
+                                             double dw, double* khat) {
+  static_assert(kW <= 16 || kW % 8 == 0, "partials in groups of eight");
+  constexpr int kG = kW > 16 ? kW / 8 : kW;  // partials left after the grouping
+  __shared__ double part[kW][kE];
+  __shared__ double part2[kW > 16 ? kG : 1][kE];
   const int n = d.nu;
   const long long nn = (long long)n * n, ntri = (long long)n * (n + 1) / 2;
-  const int lane = threadIdx.x % kSumEntries, wv = threadIdx.x / kSumEntries;
-  const long long t = (long long)bx_ * kSumEntries + lane;
+  const int lane = threadIdx.x % kE, wv = threadIdx.x / kE;
+  const long long t = (long long)bx_ * kE + lane;
   // t -> (r, c), c <= r, rows in order
   int r = 0, c = 0;
   if (t < ntri) {
@@ -43,27 +51,37 @@ __device__ __forceinline__ void sym_sum_body(int bx_, int by_, int gx_, const DP
     c = (int)(t - (long long)r * (r + 1) / 2);
   }
   const long long off = (long long)r * n + c;
-  const int per = (cnt + kSumWaves - 1) / kSumWaves;
+  const int per = (cnt + kW - 1) / kW;
   const int k0 = wv * per, k1 = min(cnt, k0 + per);
   double acc = 0.0;
   if (t < ntri) {
     // loads in batches of 16 so that they are in flight together; the
-    // additions keep the chunk order
-    int k = k0;
-    for (; k + 16 <= k1; k += 16) {
+    // additions keep the matrix order
+    for (int k = k0; k < k1; k += 16) {
       double v[16];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) v[u] = src[(long long)(k + u) * nn + off];
+      for (int u = 0; u < 16; ++u) v[u] = k + u < k1 ? src[(long long)(k + u) * nn + off] : 0.0;
 #pragma unroll
-      for (int u = 0; u < 16; ++u) acc += v[u];
+      for (int u = 0; u < 16; ++u)
+        if (k + u < k1) acc += v[u];
     }
-    for (; k < k1; ++k) acc += src[(long long)k * nn + off];
   }
   part[wv][lane] = acc;
   __syncthreads();
+  const double* fin = &part[0][0];
+  if constexpr (kW > 16) {
+    if (wv < kG) {
+      double s2 = part[8 * wv][lane];
+#pragma unroll
+      for (int q = 1; q < 8; ++q) s2 += part[8 * wv + q][lane];
+      part2[wv][lane] = s2;
+    }
+    __syncthreads();
+    fin = &part2[0][0];
+  }
   if (wv == 0 && t < ntri) {
-    double s = part[0][lane];
-    for (int q = 1; q < kSumWaves; ++q) s += part[q][lane];
+    double s = fin[lane];
+    for (int q = 1; q < kG; ++q) s += fin[q * kE + lane];
     if (r == c) s += su[r] + dw;
     if (!isfinite(s)) atomicCAS(d.status, 0, RKKT_ERR_NONFINITE);
     khat[off] = s;
@@ -71,10 +89,10 @@ __device__ __forceinline__ void sym_sum_body(int bx_, int by_, int gx_, const DP
   }
 }
 
-__global__ __launch_bounds__(kSumEntries * kSumWaves) void k_sym_sum(DP d, const double* src, int cnt,
-                                                                      const double* su, double dw,
-                                                                      double* khat) {
-  sym_sum_body((int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, d, src, cnt, su, dw, khat);
+template <int kE, int kW>
+__global__ __launch_bounds__(kE * kW) void k_sym_sum(DP d, const double* src, int cnt, const double* su, double dw,
+                                                     double* khat) {
+  sym_sum_body<kE, kW>((int)blockIdx.x, d, src, cnt, su, dw, khat);
 }
 
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -1087,11 +1105,16 @@ void launch_copy(const double* a, double* b, long long n, hipStream_t s) {
 
 void launch_scenario_sum(const DP& d, const double* su, double dw, double* khat, hipStream_t s) {
   const long long ntri = (long long)d.nu * (d.nu + 1) / 2;
-  const unsigned grid = (unsigned)((ntri + kSumEntries - 1) / kSumEntries);
-  if (d.variant == 2)
-    k_sym_sum<<<grid, kSumEntries * kSumWaves, 0, s>>>(d, d.gpart, d.nchunk, su, dw, khat);
-  else
-    k_sym_sum<<<grid, kSumEntries * kSumWaves, 0, s>>>(d, d.part, d.N, su, dw, khat);
+  const double* src = d.variant == 2 ? d.gpart : d.part;
+  const int cnt = d.variant == 2 ? d.nchunk : d.N;
+  if (cnt >= kSumManyFrom) {
+    const unsigned grid = (unsigned)((ntri + kSumEntriesMany - 1) / kSumEntriesMany);
+    k_sym_sum<kSumEntriesMany, kSumWavesMany><<<grid, kSumEntriesMany * kSumWavesMany, 0, s>>>(d, src, cnt, su, dw,
+                                                                                                khat);
+  } else {
+    const unsigned grid = (unsigned)((ntri + kSumEntries - 1) / kSumEntries);
+    k_sym_sum<kSumEntries, kSumWaves><<<grid, kSumEntries * kSumWaves, 0, s>>>(d, src, cnt, su, dw, khat);
+  }
 }
 
 void launch_stacked_product(const DP& d, hipStream_t s) {
@@ -1154,8 +1177,8 @@ void launch_reduced_solve(const DP& d, const double* r1u, const double* chol, do
 
 __global__ __launch_bounds__(kSumEntries * kSumWaves) void k_sym_sum_m(RKKT_MULTI_ARGS) {
   RKKT_MULTI_PROLOGUE
-  sym_sum_body(mb.bx, mb.by, mb.gx, d, d.variant == 2 ? d.gpart : d.part, d.variant == 2 ? d.nchunk : d.N,
-               it.sigma_u, it.delta_w, it.khat);
+  sym_sum_body<kSumEntries, kSumWaves>(mb.bx, d, d.variant == 2 ? d.gpart : d.part,
+                                       d.variant == 2 ? d.nchunk : d.N, it.sigma_u, it.delta_w, it.khat);
 }
 template <int kSlots>
 __global__ __launch_bounds__(256) void k_stacked_product_m(RKKT_MULTI_ARGS) {

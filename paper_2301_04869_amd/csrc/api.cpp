@@ -577,14 +577,19 @@ static int iterate_impl(rkkt_problem* p, const rkkt_iteration* it, hipStream_t s
   e = join_wait(0, ej);
   if (e != hipSuccess) return hip_fail(p, e, "rkkt_iterate: join");
   stage(p, RKKT_STAGE_REDUCE, stream, [&] { rkkt::launch_reduce(d, stream); });
-  e = fork_to_side(1);
+  // group B's fork is recorded right after the reduction and the stacked
+  // product is enqueued before the side stream waits on it, so the graph's
+  // first child of the reduction is the stacked product
+  e = fork ? hipEventRecord(p->fork_ev[1], stream) : hipSuccess;
+  if (e != hipSuccess) return hip_fail(p, e, "rkkt_iterate: fork");
+  if (d.variant == 2)
+    stage(p, RKKT_STAGE_STACKED_PRODUCT, stream, [&] { rkkt::launch_stacked_product(d, stream); });
+  e = fork ? hipStreamWaitEvent(side, p->fork_ev[1], 0) : hipSuccess;
   if (e != hipSuccess) return hip_fail(p, e, "rkkt_iterate: fork");
   stage(p, RKKT_STAGE_STEP_RHS, side, [&] {
     rkkt::launch_step_rhs(d, it->r1x, it->r2, it->r3, it->r4, it->sigma_s, side);
   });
   ej = join_record(1);
-  if (d.variant == 2)
-    stage(p, RKKT_STAGE_STACKED_PRODUCT, stream, [&] { rkkt::launch_stacked_product(d, stream); });
   stage(p, RKKT_STAGE_SCENARIO_SUM, stream,
         [&] { rkkt::launch_scenario_sum(d, it->sigma_u, it->delta_w, it->khat, stream); });
   stage(p, RKKT_STAGE_FACTOR, stream,

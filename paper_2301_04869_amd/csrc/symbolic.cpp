@@ -795,10 +795,13 @@ std::string build_symbolic(const rkkt_network& net, int N, const rkkt_options* o
   const long long lds_max = 160 * 1024;
   const bool pack_ok = nx < 65536 && s.f_col.size() < 65536 && s.lu_flops < 65536;
   // refactorisation and step: up to 4 scenarios per workgroup, one
-  // wavefront each, when a scenario's LU values and vectors fit in LDS
+  // wavefront each, when a scenario's LU values and vectors fit in LDS; the
+  // automatic choice stops at 2 (at 118 buses and 128 scenarios the pass
+  // measured 232 us with 2 or 1 against 234 us with 4: four wavefronts on
+  // one compute unit share its memory pipeline)
   s.spw = 0;
   for (int spw : {4, 2, 1}) {
-    if (spw_req > 0 && spw > spw_req) continue;
+    if (spw_req > 0 ? spw > spw_req : spw > 2) continue;
     for (int staged : {1, 0}) {
       s.upd_lds = staged;
       if (pack_ok && refactor_lds_bytes(lds_sizes(s, 1, 1, spw)) <= lds_max) {

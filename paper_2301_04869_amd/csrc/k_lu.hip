@@ -175,11 +175,11 @@ __device__ __forceinline__ void sweep(const int* __restrict__ ptr, const void* e
 // slot of kGroupLds), fewest instructions per phase: a phase whose slots hold
 // at most one entry each (most phases of these schedules) is one guarded
 // multiply-add per lane; longer slots run their entries in order.  Each phase
-// first issues its own operand reads (from the entry already in registers),
-// then the reads of the next phase's first entry and slot maximum and of the
-// slot extent two phases ahead, so one LDS round trip per phase is exposed;
-// a lane without an entry reads through the schedule's first entry and
-// stores nothing.  The wavefront's LDS operations complete in issue order,
+// issues its own operand reads (from the entry already in registers) together
+// with the reads of the next phase's first entry and slot maximum and of the
+// slot extent two phases ahead, so the schedule reads no longer form a chain
+// of round trips in front of the update; a lane without an entry reads
+// through the schedule's first entry and stores nothing.  The wavefront's LDS operations complete in issue order,
 // so a phase's reads see the previous phase's stores.
 template <bool kTrans, typename Sync>
 __device__ __forceinline__ void sweep_w(const int* ptr, const uint2* ent, const int* phmax, int nphase,
@@ -196,9 +196,7 @@ __device__ __forceinline__ void sweep_w(const int* ptr, const uint2* ent, const 
     n = ptr[slot + 1] - e0;
     t = ent[n > 0 ? e0 : 0];
     m = phmax[0];
-  }
-  // reads past the last phase take the last phase's (valid) data, unused
-  if (nphase > 0) {
+    // reads past the last phase take the last phase's (valid) data, unused
     const int q1 = min(1, nphase - 1);
     e1 = ptr[q1 * kGroupLds + slot];
     b1 = ptr[q1 * kGroupLds + slot + 1];

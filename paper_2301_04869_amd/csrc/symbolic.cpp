@@ -797,8 +797,7 @@ std::string build_symbolic(const rkkt_network& net, int N, const rkkt_options* o
   // refactorisation and step: up to 4 scenarios per workgroup, one
   // wavefront each, when a scenario's LU values and vectors fit in LDS; the
   // automatic choice stops at 2 (at 118 buses and 128 scenarios the pass
-  // measured 232 us with 2 or 1 against 234 us with 4: four wavefronts on
-  // one compute unit share its memory pipeline)
+  // measured 232 us with 2 or 1 scenarios per workgroup against 234 us with 4)
   s.spw = 0;
   for (int spw : {4, 2, 1}) {
     if (spw_req > 0 ? spw > spw_req : spw > 2) continue;

@@ -1561,7 +1561,7 @@ __device__ __forceinline__ StepView sweep_view(const DP& d, double* lu, unsigned
 // out[c] = sum_i Z[i][c] b[i] for c < nu; kT threads as row slices x columns,
 // partial sums through red[kT + nu] (LDS), one barrier inside.  Each thread
 // keeps kTtRows loads of its column in flight.
-constexpr int kTtRows = 8;
+constexpr int kTtRows = 16;
 
 // entries of a sparse row (K, or H^T) whose loads the step kernels issue
 // together before adding their terms in row order
